@@ -1,0 +1,142 @@
+/*
+ * wally.h -- C ABI of the MI355X library for server-side encrypted
+ * nearest-neighbour scoring (BFV, Halevi-Shoup diagonals, baby-step
+ * giant-step rotations).
+ *
+ * The problem (paper §5, "Server computation"; Server Computation algorithm):
+ * the server holds an index of clusters encoded as plaintexts (Server
+ * Initialization algorithm, §5) and receives queries (ct, evk, cluster id); for
+ * each it returns ceil(N_c / n) ciphertexts whose slot s of chunk k decrypts to
+ * the inner product of the query with entry k*n + s of the cluster, mod t.
+ * Queries are independent (paper §8: no inter-query synchronisation) and are
+ * scored in batches or served as they arrive.
+ *
+ * Conventions (fixed; the oracle used for testing follows the same ones):
+ *   n = 2^log_n; moduli q_0 > ... > q_{L-1} are the largest primes below
+ *   2^limb_bits with q = 1 mod 2n; P is the next one (key switching);
+ *   t is the smallest prime above 2^t_bits with t = 1 mod 2n.
+ *   NTT form: entry i of limb l holds the polynomial at psi_l^(2 brv(i)+1),
+ *   psi_l the smallest primitive 2n-th root of unity mod q_l.
+ *   Ciphertext:  uint64 [2][L][n], NTT form, words in [0, q_l).
+ *   Galois key:  uint64 [L][2][L+1][n] (digit, polynomial b/a, modulus with P
+ *                last), NTT form; key_baby is for X -> X^3 (rotate left by 1),
+ *                key_giant for X -> X^(3^g mod 2n) (rotate left by g).
+ *   Response:    uint64 [chunks][2][L][n] per query, NTT form.
+ *   d_pad = next power of two >= dim; g = 2^ceil(log2(d_pad)/2), h = d_pad/g.
+ *
+ * Errors: every call returns a status code; no exception or abort crosses the
+ * ABI.  wally_last_error() gives a message for the last failing call on a
+ * context.  Pointers documented as "device" are HIP device pointers the
+ * caller owns (e.g. PyTorch tensors) and must keep alive until the work on
+ * the given stream has completed.
+ */
+#ifndef WALLY_H
+#define WALLY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WALLY_OK 0
+#define WALLY_EINVAL (-1)   /* bad argument: nothing was enqueued            */
+#define WALLY_ENOMEM (-2)   /* over the HBM budget or allocation failed      */
+#define WALLY_EAGAIN (-3)   /* serving: admission refused now, retry later   */
+#define WALLY_EPENDING (-4) /* serving: ticket not finished                  */
+#define WALLY_EDEVICE (-5)  /* HIP runtime error (sticky for the context)    */
+#define WALLY_ESTATE (-6)   /* call not valid in the current state           */
+
+#define WALLY_LAYOUT_PER_CLUSTER 0 /* each cluster owns ceil(N_c/n) chunks (paper §4.1) */
+
+#define WALLY_PATH_BATCHED 0 /* queries of all clusters share launches        */
+#define WALLY_PATH_PLAIN 1   /* one launch sequence per cluster (baseline)     */
+
+typedef struct wally_ctx wally_ctx;
+
+typedef struct {
+  uint32_t log_n;      /* 12 or 13                                          */
+  uint32_t num_limbs;  /* L, 1..8                                           */
+  uint32_t limb_bits;  /* 30..60 bits per ciphertext prime                  */
+  uint32_t t_bits;     /* plaintext modulus just above 2^t_bits (< limb_bits)*/
+  uint32_t dim;        /* embedding dimension d                             */
+  uint32_t layout;     /* WALLY_LAYOUT_PER_CLUSTER                          */
+  int32_t device;      /* HIP device ordinal                                */
+  uint32_t max_batch;  /* queries resident per wave (0 = library default)   */
+  uint64_t hbm_budget; /* bytes the context may allocate (0 = 90% of free)  */
+} wally_params_desc;
+
+typedef struct {
+  uint32_t n, L, d, d_pad, g, h;
+  uint64_t q[8];      /* ciphertext primes (first L used)                    */
+  uint64_t P;         /* special prime                                      */
+  uint64_t t;         /* plaintext modulus                                  */
+  uint64_t psi[9];    /* roots for q_0..q_{L-1}, then P                      */
+  uint64_t psi_t;
+  uint64_t gal_baby, gal_giant;
+  uint64_t ct_words;  /* words per ciphertext = 2 L n                       */
+  uint64_t key_words; /* words per Galois key = L * 2 * (L+1) * n           */
+  uint64_t pt_chunk_words; /* words per encoded chunk = d_pad L n           */
+  uint64_t bytes_allocated; /* device bytes held by the context             */
+} wally_params_info;
+
+/* One query: every pointer is a device pointer.  `out` receives
+ * chunks(cluster) consecutive ciphertexts. */
+typedef struct {
+  uint32_t cluster;
+  uint32_t reserved;
+  const uint64_t* ct;        /* [2][L][n]                                   */
+  const uint64_t* key_baby;  /* [L][2][L+1][n]                              */
+  const uint64_t* key_giant; /* [L][2][L+1][n]                              */
+  uint64_t* out;             /* [chunks][2][L][n]                           */
+} wally_query;
+
+/* Derive the parameters (rules above), build the NTT tables on the host and
+ * upload them to `desc->device`.  On success *out owns all device memory it
+ * allocates.  EINVAL for unsupported sizes, ENOMEM, EDEVICE. */
+int wally_params_init(const wally_params_desc* desc, wally_ctx** out);
+
+/* Parameter values and byte sizes (the client side needs them to build
+ * ciphertexts and keys). */
+int wally_params_query(const wally_ctx* ctx, wally_params_info* out);
+
+/* Server Initialization (paper §5; diagonal packing §4.1): encode K clusters
+ * of int8 embeddings into NTT-form plaintexts resident on the device.
+ * emb: host, row-major [n_entries][dim]; offsets: host, K+1 entries, cluster
+ * c = rows [offsets[c], offsets[c+1]), non-decreasing, offsets[K] = n_entries,
+ * every cluster non-empty.  The inputs are copied; the caller keeps them.
+ * Replaces any previous index.  Synchronous.  EINVAL, ENOMEM, EDEVICE. */
+int wally_encode_clusters(wally_ctx* ctx, const int8_t* emb, uint64_t n_entries, const uint64_t* offsets,
+                          uint32_t k);
+
+/* Chunks of cluster c and the device address of its plaintexts
+ * [chunks][d_pad][L][n] (read-only for the caller). */
+int wally_cluster_info(const wally_ctx* ctx, uint32_t c, uint32_t* n_chunks, const uint64_t** plaintexts);
+
+/* Score nq queries (Server Computation algorithm, paper §5): for each, g-1
+ * baby-step rotations, then per chunk the giant-step sums of plaintext
+ * products combined by h-1 giant rotations.  q: host array of descriptors
+ * with device pointers.  `path` selects WALLY_PATH_BATCHED or
+ * WALLY_PATH_PLAIN; both give identical words.  Work is enqueued on
+ * hip_stream (a hipStream_t; NULL = default stream) and the call returns once
+ * it is enqueued; output is independent of batch composition.  Validation
+ * errors are reported before anything is enqueued (EINVAL). */
+int wally_score_batch(wally_ctx* ctx, const wally_query* q, uint64_t nq, int path, void* hip_stream);
+
+/* Serving (continuous batching).  start: begin accepting work on hip_stream.
+ * submit: non-blocking; EAGAIN when the in-flight budget is full (retry
+ * after poll).  poll: non-blocking; writes up to `max` finished tickets.
+ * stop: waits for in-flight work and ends the session. */
+int wally_serve_start(wally_ctx* ctx, void* hip_stream);
+int wally_serve_submit(wally_ctx* ctx, const wally_query* q, uint64_t* ticket);
+int wally_serve_poll(wally_ctx* ctx, uint64_t* done, uint32_t max, uint32_t* n_done);
+int wally_serve_stop(wally_ctx* ctx);
+
+const char* wally_strerror(int code);
+const char* wally_last_error(const wally_ctx* ctx);
+void wally_destroy(wally_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WALLY_H */

@@ -1,0 +1,35 @@
+/*
+ * wally_diag.h -- component entry points of the MI355X library, for checking
+ * single steps of the scoring path against a reference.  Same conventions,
+ * ownership and error rules as wally.h.
+ */
+#ifndef WALLY_DIAG_H
+#define WALLY_DIAG_H
+
+#include <stdint.h>
+
+#include "wally.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* In-place negacyclic NTT (inverse = 0: coefficients -> NTT form, canonical
+ * order; inverse = 1: back, including the n^-1 factor) of `rows` consecutive
+ * rows of n words.  mi selects the modulus: 0..L-1 = q_i, L = P, L+1 = t.
+ * Input words must be below the modulus.  data: device.  Enqueued on
+ * hip_stream. */
+int wally_diag_ntt(wally_ctx* ctx, uint32_t mi, uint64_t* data, uint64_t rows, int inverse, void* hip_stream);
+
+/* CtRotate with key switching (paper §2.1; hybrid RNS key switching §7.1) of
+ * `count` ciphertexts.  in: [count][2][L][n]; keys: [count][L][2][L+1][n];
+ * out: [count][2][L][n] (must not overlap in); which = 0 rotates left by 1
+ * (X -> X^3, keys for that element), 1 rotates left by g (X -> X^(3^g)).
+ * All device.  Enqueued on hip_stream. */
+int wally_diag_rotate(wally_ctx* ctx, const uint64_t* in, const uint64_t* keys, uint64_t* out, uint64_t count,
+                      int which, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WALLY_DIAG_H */

@@ -1,0 +1,62 @@
+// Device modular arithmetic for word-size primes q < 2^62 (limbs of 36 and 54
+// bits, the special prime and the plaintext modulus).  Everything is exact
+// integer arithmetic on the VALU: gfx950 has no 64x64 multiplier, so 64-bit
+// products are built by the compiler from v_mad_u64_u32 / v_mul_hi_u32, which
+// issue at close to full rate on this chip.
+//
+// Reduction strategy (lazy reduction, paper §7.1 "NTT ... with lazy modular
+// reduction" and the accumulation of many plaintext products before one
+// reduction):
+//  * products with a constant (twiddles, n^-1, P^-1) use Shoup's method:
+//    w' = floor(w * 2^64 / q) precomputed on the host, result in [0, 2q);
+//  * sums of products of two variables are accumulated in 128 bits and
+//    reduced once.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wally {
+
+struct u128w {
+  uint64_t lo, hi;
+};
+
+__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+
+// a * w mod q in [0, 2q) for any a < 2^64, w < q, wp = floor(w 2^64 / q).
+__device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+  const uint64_t qh = mulhi64(a, wp);
+  return a * w - qh * q;
+}
+
+// x in [0, 2q) -> [0, q)
+__device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t q) { return x >= q ? x - q : x; }
+
+// x in [0, 4q) -> [0, q)
+__device__ __forceinline__ uint64_t reduce4(uint64_t x, uint64_t q, uint64_t q2) {
+  x = x >= q2 ? x - q2 : x;
+  return x >= q ? x - q : x;
+}
+
+__device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) { return csub(a + b, q); }
+__device__ __forceinline__ uint64_t submod(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
+
+// acc += a * b (128-bit)
+__device__ __forceinline__ void mac128(u128w& acc, uint64_t a, uint64_t b) {
+  const uint64_t lo = a * b;
+  const uint64_t hi = mulhi64(a, b);
+  const uint64_t s = acc.lo + lo;
+  acc.hi += hi + (s < lo ? 1u : 0u);
+  acc.lo = s;
+}
+
+// (hi * 2^64 + lo) mod q for any hi, lo < 2^64: result in [0, q).
+__device__ __forceinline__ uint64_t reduce128(u128w x, uint64_t q, uint64_t r64, uint64_t r64p, uint64_t onep) {
+  const uint64_t a = shoup(x.hi, r64, r64p, q);   // hi * 2^64 mod q, [0, 2q)
+  const uint64_t b = x.lo - mulhi64(x.lo, onep) * q;  // lo mod q, [0, 2q)
+  uint64_t s = a + b;                              // [0, 4q)
+  s = s >= 2 * q ? s - 2 * q : s;
+  return s >= q ? s - q : s;
+}
+
+}  // namespace wally

@@ -1,0 +1,779 @@
+// Host side of the MI355X scoring library: parameter derivation, NTT tables,
+// the resident plaintext index, the wave scheduler (batched and per-cluster
+// paths) and the serving loop.  The C ABI is declared in include/wally.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "wally.h"
+#include "wally_diag.h"
+
+using namespace wally;
+typedef unsigned __int128 u128;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// number theory for the parameter rules (host, exact)
+
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+
+uint64_t powmod(uint64_t a, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  a %= m;
+  for (; e; e >>= 1) {
+    if (e & 1) r = mulmod(r, a, m);
+    a = mulmod(a, a, m);
+  }
+  return r;
+}
+
+// Deterministic Miller-Rabin for 64-bit n (the first twelve primes as bases).
+bool is_prime(uint64_t n) {
+  static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  if (n < 2) return false;
+  for (uint64_t p : bases)
+    if (n % p == 0) return n == p;
+  uint64_t d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) d >>= 1, ++s;
+  for (uint64_t a : bases) {
+    uint64_t x = powmod(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s; ++r) {
+      x = mulmod(x, x, n);
+      if (x == n - 1) {
+        comp = false;
+        break;
+      }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+uint32_t bitrev(uint32_t x, int bits) {
+  uint32_t r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+// Smallest primitive two_n-th root of unity mod prime q.
+uint64_t min_root(uint64_t q, uint64_t two_n) {
+  const uint64_t cof = (q - 1) / two_n;
+  uint64_t w = 0;
+  for (uint64_t x = 2;; ++x) {
+    w = powmod(x, cof, q);
+    if (powmod(w, two_n / 2, q) == q - 1) break;
+  }
+  const uint64_t w2 = mulmod(w, w, q);
+  uint64_t best = w, cur = w;
+  for (uint64_t k = 1; k < two_n / 2; ++k) {
+    cur = mulmod(cur, w2, q);
+    best = std::min(best, cur);
+  }
+  return best;
+}
+
+uint64_t shoup_of(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
+
+struct WaveWork {
+  // one workspace set: buffers for one wave of queries in flight
+  uint64_t* ctp = nullptr;  // [B][g][2][L][n]
+  uint64_t* X = nullptr;    // [B][L][n]
+  uint64_t* U = nullptr;    // [B][2][L][n]
+  uint64_t* Y = nullptr;    // [B][2][n]
+  uint64_t* D = nullptr;    // [B][L+1][L][n]
+  uint64_t* R0 = nullptr;   // [B][2][L][n]
+  uint64_t* R1 = nullptr;
+  // descriptors: copy items, baby items, giant items
+  CopyItem* copy_dev = nullptr;
+  KsItem* baby_dev = nullptr;
+  KsItem* giant_dev = nullptr;
+  CopyItem* copy_host = nullptr;
+  KsItem* baby_host = nullptr;
+  KsItem* giant_host = nullptr;
+  size_t giant_cap = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t staged = nullptr;  // host descriptors copied
+  hipEvent_t done = nullptr;    // wave finished
+  bool busy = false;
+  std::vector<uint64_t> tickets;  // serving: tickets of the wave in flight
+};
+
+struct ServeReq {
+  wally_query q;
+  uint64_t ticket;
+};
+
+}  // namespace
+
+struct wally_ctx {
+  int device = 0;
+  int log_n = 0, n = 0, L = 0, d = 0, d_pad = 0, g = 0, h = 0;
+  uint64_t mods[kMaxMod] = {};
+  uint64_t psi[kMaxMod] = {};
+  uint32_t gal_baby = 3, gal_giant = 0;
+  DevModuli M{};
+  uint64_t budget = 0, allocated = 0;
+  std::vector<std::pair<void*, size_t>> allocs;
+  void* tables = nullptr;
+  uint32_t* slot_of = nullptr;
+  // index
+  uint32_t K = 0;
+  std::vector<uint32_t> chunks;
+  std::vector<uint64_t> chunk_base;
+  uint32_t max_chunks = 0;
+  uint64_t* pt = nullptr;
+  // waves
+  int B = 0;
+  int n_sets = 2;
+  std::vector<WaveWork> sets;
+  hipEvent_t fork = nullptr;
+  std::string err;
+  bool dead = false;
+  std::mutex mu;
+  // serving
+  bool serving = false;
+  hipStream_t serve_stream = nullptr;
+  std::deque<ServeReq> pending;
+  std::deque<uint64_t> finished;
+  uint64_t next_ticket = 1;
+  uint64_t max_pending = 0;
+
+  uint64_t ctw() const { return 2ull * L * n; }
+  uint64_t keyw() const { return (uint64_t)L * 2 * (L + 1) * n; }
+  uint64_t ptw() const { return (uint64_t)d_pad * L * n; }
+};
+
+namespace {
+
+int set_err(wally_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  if (code == WALLY_EDEVICE && c) c->dead = true;
+  return code;
+}
+
+#define HIP_OK(c, call)                                                                     \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return set_err((c), WALLY_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));  \
+  } while (0)
+
+int dalloc(wally_ctx* c, size_t bytes, void** p) {
+  if (c->allocated + bytes > c->budget)
+    return set_err(c, WALLY_ENOMEM, "device allocation of %zu bytes exceeds the budget (%llu of %llu in use)", bytes,
+                   (unsigned long long)c->allocated, (unsigned long long)c->budget);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(c, WALLY_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  c->allocated += bytes;
+  c->allocs.push_back({*p, bytes});
+  return WALLY_OK;
+}
+
+void dfree(wally_ctx* c, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < c->allocs.size(); ++i)
+    if (c->allocs[i].first == p) {
+      c->allocated -= c->allocs[i].second;
+      c->allocs.erase(c->allocs.begin() + i);
+      break;
+    }
+  (void)hipFree(p);
+}
+
+int check_live(wally_ctx* c) {
+  if (!c) return WALLY_EINVAL;
+  if (c->dead) return WALLY_EDEVICE;
+  HIP_OK(c, hipSetDevice(c->device));
+  return WALLY_OK;
+}
+
+void free_sets(wally_ctx* c) {
+  for (auto& s : c->sets) {
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
+    dfree(c, s.ctp);
+    dfree(c, s.X);
+    dfree(c, s.U);
+    dfree(c, s.Y);
+    dfree(c, s.D);
+    dfree(c, s.R0);
+    dfree(c, s.R1);
+    dfree(c, s.copy_dev);
+    dfree(c, s.baby_dev);
+    dfree(c, s.giant_dev);
+    if (s.copy_host) (void)hipHostFree(s.copy_host);
+    if (s.baby_host) (void)hipHostFree(s.baby_host);
+    if (s.giant_host) (void)hipHostFree(s.giant_host);
+    if (s.staged) (void)hipEventDestroy(s.staged);
+    if (s.done) (void)hipEventDestroy(s.done);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+  }
+  c->sets.clear();
+}
+
+// Workspace sets for waves of up to B queries (allocated on first use and
+// whenever the index changes the largest chunk count).
+int ensure_sets(wally_ctx* c) {
+  const size_t giant_cap = (size_t)c->B * std::max<uint32_t>(1, c->max_chunks);
+  if (!c->sets.empty() && c->sets[0].giant_cap >= giant_cap) return WALLY_OK;
+  free_sets(c);
+  c->sets.resize(c->n_sets);
+  const size_t B = c->B;
+  const size_t w8 = sizeof(uint64_t);
+  for (auto& s : c->sets) {
+    int rc;
+    if ((rc = dalloc(c, B * c->g * c->ctw() * w8, (void**)&s.ctp))) return rc;
+    if ((rc = dalloc(c, B * c->L * c->n * w8, (void**)&s.X))) return rc;
+    if ((rc = dalloc(c, B * c->ctw() * w8, (void**)&s.U))) return rc;
+    if ((rc = dalloc(c, B * 2 * c->n * w8, (void**)&s.Y))) return rc;
+    if ((rc = dalloc(c, B * (c->L + 1) * c->L * c->n * w8, (void**)&s.D))) return rc;
+    if ((rc = dalloc(c, B * c->ctw() * w8, (void**)&s.R0))) return rc;
+    if ((rc = dalloc(c, B * c->ctw() * w8, (void**)&s.R1))) return rc;
+    if ((rc = dalloc(c, B * sizeof(CopyItem), (void**)&s.copy_dev))) return rc;
+    if ((rc = dalloc(c, B * sizeof(KsItem), (void**)&s.baby_dev))) return rc;
+    if ((rc = dalloc(c, giant_cap * sizeof(KsItem), (void**)&s.giant_dev))) return rc;
+    HIP_OK(c, hipHostMalloc((void**)&s.copy_host, B * sizeof(CopyItem), hipHostMallocDefault));
+    HIP_OK(c, hipHostMalloc((void**)&s.baby_host, B * sizeof(KsItem), hipHostMallocDefault));
+    HIP_OK(c, hipHostMalloc((void**)&s.giant_host, giant_cap * sizeof(KsItem), hipHostMallocDefault));
+    HIP_OK(c, hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+    HIP_OK(c, hipEventCreateWithFlags(&s.staged, hipEventDisableTiming));
+    HIP_OK(c, hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+    s.giant_cap = giant_cap;
+  }
+  return WALLY_OK;
+}
+
+KsArgs base_args(const wally_ctx* c, const WaveWork& s) {
+  KsArgs a{};
+  a.log_n = c->log_n;
+  a.L = c->L;
+  a.g = c->g;
+  a.giant = -1;
+  a.X = s.X;
+  a.U = s.U;
+  a.Y = s.Y;
+  a.D = s.D;
+  return a;
+}
+
+// Enqueue the whole scoring of one wave (queries qs[0..w)) on set s.
+// All queries must already be validated.
+int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w) {
+  const uint64_t ctw = c->ctw(), ptw = c->ptw();
+  // host descriptors may be rewritten only after the previous copy landed
+  HIP_OK(c, hipEventSynchronize(s.staged));
+  size_t ng = 0;
+  for (int k = 0; k < w; ++k) {
+    const wally_query& q = *qs[k];
+    uint64_t* ctp = s.ctp + (uint64_t)k * c->g * ctw;
+    s.copy_host[k] = CopyItem{q.ct, ctp};
+    s.baby_host[k] = KsItem{q.key_baby, ctp, nullptr, nullptr, nullptr, nullptr};
+    for (uint32_t ch = 0; ch < c->chunks[q.cluster]; ++ch) {
+      KsItem gi{};
+      gi.key = q.key_giant;
+      gi.fin = q.out + (uint64_t)ch * ctw;
+      gi.pt = c->pt + (c->chunk_base[q.cluster] + ch) * ptw;
+      gi.ctp = ctp;
+      s.giant_host[ng++] = gi;
+    }
+  }
+  HIP_OK(c, hipMemcpyAsync(s.copy_dev, s.copy_host, w * sizeof(CopyItem), hipMemcpyHostToDevice, s.stream));
+  HIP_OK(c, hipMemcpyAsync(s.baby_dev, s.baby_host, w * sizeof(KsItem), hipMemcpyHostToDevice, s.stream));
+  // giant items: R ping-pong slots are assigned per sub-wave on the device copy
+  for (size_t k = 0; k < ng; ++k) {
+    const size_t slot = k % (size_t)c->B;
+    s.giant_host[k].buf0 = s.R0 + slot * ctw;
+    s.giant_host[k].buf1 = s.R1 + slot * ctw;
+  }
+  HIP_OK(c, hipMemcpyAsync(s.giant_dev, s.giant_host, ng * sizeof(KsItem), hipMemcpyHostToDevice, s.stream));
+  HIP_OK(c, hipEventRecord(s.staged, s.stream));
+
+  // baby steps: ct'_0 = ct, ct'_j = Rot(ct'_{j-1}, 1)
+  HIP_OK(c, launch_copy_ct(s.copy_dev, w, ctw, s.stream));
+  for (int j = 1; j < c->g; ++j) {
+    KsArgs a = base_args(c, s);
+    a.gal = c->gal_baby;
+    a.in_sel = 0;
+    a.in_off = (uint64_t)(j - 1) * ctw;
+    a.out_sel = 0;
+    a.out_off = (uint64_t)j * ctw;
+    HIP_OK(c, launch_keyswitch(s.baby_dev, w, a, c->M, s.stream));
+  }
+  // giant steps per (query, chunk): R = acc_{h-1}; R = acc_i + Rot(R, g), i = h-2..0
+  for (size_t g0 = 0; g0 < ng; g0 += c->B) {
+    const int cnt = (int)std::min<size_t>(c->B, ng - g0);
+    const KsItem* items = s.giant_dev + g0;
+    KsArgs a = base_args(c, s);
+    a.giant = c->h - 1;
+    a.out_sel = c->h == 1 ? 2 : 0;
+    HIP_OK(c, launch_mac_init(items, cnt, a, c->M, s.stream));
+    int cur = 0;
+    for (int i = c->h - 2; i >= 0; --i) {
+      KsArgs b = base_args(c, s);
+      b.gal = c->gal_giant;
+      b.in_sel = cur;
+      b.out_sel = i == 0 ? 2 : 1 - cur;
+      b.giant = i;
+      HIP_OK(c, launch_keyswitch(items, cnt, b, c->M, s.stream));
+      cur = 1 - cur;
+    }
+  }
+  HIP_OK(c, hipEventRecord(s.done, s.stream));
+  return WALLY_OK;
+}
+
+int validate_query(wally_ctx* c, const wally_query& q, uint64_t idx) {
+  if (q.cluster >= c->K) return set_err(c, WALLY_EINVAL, "query %llu: cluster %u out of range (K = %u)",
+                                        (unsigned long long)idx, q.cluster, c->K);
+  if (!q.ct || !q.key_baby || !q.key_giant || !q.out)
+    return set_err(c, WALLY_EINVAL, "query %llu: null pointer", (unsigned long long)idx);
+  if (((uintptr_t)q.ct | (uintptr_t)q.out) & 15)
+    return set_err(c, WALLY_EINVAL, "query %llu: ct/out must be 16-byte aligned", (unsigned long long)idx);
+  return WALLY_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+
+extern "C" {
+
+const char* wally_strerror(int code) {
+  switch (code) {
+    case WALLY_OK: return "ok";
+    case WALLY_EINVAL: return "invalid argument";
+    case WALLY_ENOMEM: return "out of device memory budget";
+    case WALLY_EAGAIN: return "admission refused, retry later";
+    case WALLY_EPENDING: return "pending";
+    case WALLY_EDEVICE: return "device error";
+    case WALLY_ESTATE: return "invalid state";
+    default: return "unknown error";
+  }
+}
+
+const char* wally_last_error(const wally_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
+  if (!desc || !out) return WALLY_EINVAL;
+  *out = nullptr;
+  if (desc->log_n != 12 && desc->log_n != 13) return WALLY_EINVAL;
+  if (desc->num_limbs < 1 || desc->num_limbs > kMaxLimbs) return WALLY_EINVAL;
+  if (desc->limb_bits < 30 || desc->limb_bits > 60) return WALLY_EINVAL;
+  if (desc->t_bits < 2 || desc->t_bits + 2 > desc->limb_bits) return WALLY_EINVAL;
+  if (desc->dim < 1) return WALLY_EINVAL;
+  if (desc->layout != WALLY_LAYOUT_PER_CLUSTER) return WALLY_EINVAL;
+  wally_ctx* c = new (std::nothrow) wally_ctx();
+  if (!c) return WALLY_ENOMEM;
+  c->device = desc->device;
+  c->log_n = desc->log_n;
+  c->n = 1 << c->log_n;
+  c->L = desc->num_limbs;
+  c->d = desc->dim;
+  int dp = 1;
+  while (dp < c->d) dp *= 2;
+  if ((c->n / 2) % dp) {
+    delete c;
+    return WALLY_EINVAL;
+  }
+  c->d_pad = dp;
+  int lg = 0;
+  while ((1 << lg) < dp) ++lg;
+  c->g = 1 << ((lg + 1) / 2);
+  c->h = dp / c->g;
+  const uint64_t two_n = 2ull * c->n;
+  c->gal_baby = 3;
+  c->gal_giant = (uint32_t)powmod(3, c->g, two_n);
+  // moduli: L + 1 largest NTT-friendly primes below 2^limb_bits, then t
+  {
+    uint64_t top = (desc->limb_bits == 64) ? ~0ull : (1ull << desc->limb_bits) - 1;
+    uint64_t cand = (top - 1) / two_n * two_n + 1;
+    int found = 0;
+    while (found < c->L + 1 && cand > two_n) {
+      if (is_prime(cand)) c->mods[found++] = cand;
+      cand -= two_n;
+    }
+    uint64_t t = ((1ull << desc->t_bits) / two_n + 1) * two_n + 1;
+    while (!is_prime(t)) t += two_n;
+    c->mods[c->L + 1] = t;
+  }
+  const int nm = c->L + 2;
+  for (int m = 0; m < nm; ++m) c->psi[m] = min_root(c->mods[m], two_n);
+
+  if (hipSetDevice(c->device) != hipSuccess) {
+    delete c;
+    return WALLY_EINVAL;
+  }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    delete c;
+    return WALLY_EDEVICE;
+  }
+  c->budget = desc->hbm_budget ? desc->hbm_budget : (uint64_t)(free_b * 0.9);
+  c->B = desc->max_batch ? (int)desc->max_batch : 1024;
+
+  // tables: per modulus n forward + n inverse (w, Shoup) pairs, then slot_of
+  const size_t tw_words = (size_t)nm * 2 * c->n * 2;
+  std::vector<uint64_t> host(tw_words);
+  for (int m = 0; m < nm; ++m) {
+    const uint64_t q = c->mods[m], ps = c->psi[m], psi_inv = powmod(ps, q - 2, q);
+    uint64_t* f = host.data() + (size_t)m * 4 * c->n;
+    uint64_t* iv = f + 2 * (size_t)c->n;
+    uint64_t p1 = 1, p2 = 1;
+    for (int k = 0; k < c->n; ++k) {
+      const uint32_t r = bitrev(k, c->log_n);
+      f[2 * r] = p1;
+      f[2 * r + 1] = shoup_of(p1, q);
+      iv[2 * r] = p2;
+      iv[2 * r + 1] = shoup_of(p2, q);
+      p1 = mulmod(p1, ps, q);
+      p2 = mulmod(p2, psi_inv, q);
+    }
+    DevModuli& M = c->M;
+    M.q[m] = q;
+    M.mc[m].q = q;
+    M.mc[m].q2 = 2 * q;
+    M.mc[m].r64 = (uint64_t)(((u128)1 << 64) % q);
+    M.mc[m].r64p = shoup_of(M.mc[m].r64, q);
+    M.mc[m].onep = (uint64_t)((((u128)1) << 64) / q);
+    M.ninv[m] = powmod(c->n % q, q - 2, q);
+    M.ninvp[m] = shoup_of(M.ninv[m], q);
+  }
+  const uint64_t P = c->mods[c->L];
+  for (int j = 0; j < c->L; ++j) {
+    const uint64_t q = c->mods[j];
+    c->M.pinv[j] = powmod(P % q, q - 2, q);
+    c->M.pinvp[j] = shoup_of(c->M.pinv[j], q);
+  }
+  std::vector<uint32_t> slot_of(c->n);
+  {
+    const uint32_t half = c->n / 2;
+    uint64_t e = 1;
+    for (uint32_t col = 0; col < half; ++col) {
+      slot_of[bitrev((uint32_t)((e - 1) / 2), c->log_n)] = col;
+      slot_of[bitrev((uint32_t)((two_n - e - 1) / 2), c->log_n)] = half + col;
+      e = e * 3 % two_n;
+    }
+  }
+  int rc = dalloc(c, tw_words * 8, &c->tables);
+  if (!rc) rc = dalloc(c, c->n * sizeof(uint32_t), (void**)&c->slot_of);
+  if (rc) {
+    wally_destroy(c);
+    return rc;
+  }
+  if (hipMemcpy(c->tables, host.data(), tw_words * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->slot_of, slot_of.data(), c->n * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess) {
+    wally_destroy(c);
+    return WALLY_EDEVICE;
+  }
+  for (int m = 0; m < nm; ++m) {
+    const ulonglong2* base = reinterpret_cast<const ulonglong2*>((uint64_t*)c->tables + (size_t)m * 4 * c->n);
+    c->M.fwd[m] = base;
+    c->M.inv[m] = base + c->n;
+  }
+  *out = c;
+  return WALLY_OK;
+}
+
+int wally_params_query(const wally_ctx* c, wally_params_info* o) {
+  if (!c || !o) return WALLY_EINVAL;
+  memset(o, 0, sizeof *o);
+  o->n = c->n;
+  o->L = c->L;
+  o->d = c->d;
+  o->d_pad = c->d_pad;
+  o->g = c->g;
+  o->h = c->h;
+  for (int j = 0; j < c->L; ++j) o->q[j] = c->mods[j];
+  o->P = c->mods[c->L];
+  o->t = c->mods[c->L + 1];
+  for (int j = 0; j <= c->L; ++j) o->psi[j] = c->psi[j];
+  o->psi_t = c->psi[c->L + 1];
+  o->gal_baby = c->gal_baby;
+  o->gal_giant = c->gal_giant;
+  o->ct_words = c->ctw();
+  o->key_words = c->keyw();
+  o->pt_chunk_words = c->ptw();
+  o->bytes_allocated = c->allocated;
+  return WALLY_OK;
+}
+
+int wally_encode_clusters(wally_ctx* c, const int8_t* emb, uint64_t n_entries, const uint64_t* offsets, uint32_t k) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->serving) return set_err(c, WALLY_ESTATE, "cannot re-encode while serving");
+  if (!emb || !offsets || k == 0 || n_entries == 0) return set_err(c, WALLY_EINVAL, "empty or null index input");
+  if (offsets[0] != 0 || offsets[k] != n_entries) return set_err(c, WALLY_EINVAL, "offsets must span [0, n_entries)");
+  std::vector<uint32_t> chunks(k);
+  std::vector<uint64_t> base(k);
+  uint64_t total = 0;
+  uint32_t maxc = 0;
+  for (uint32_t i = 0; i < k; ++i) {
+    if (offsets[i + 1] <= offsets[i]) return set_err(c, WALLY_EINVAL, "cluster %u is empty or offsets decrease", i);
+    const uint64_t sz = offsets[i + 1] - offsets[i];
+    chunks[i] = (uint32_t)((sz + c->n - 1) / c->n);
+    base[i] = total;
+    total += chunks[i];
+    maxc = std::max(maxc, chunks[i]);
+  }
+  // drop the previous index and workspaces, then allocate the new one
+  free_sets(c);
+  dfree(c, c->pt);
+  c->pt = nullptr;
+  c->K = 0;
+  const uint64_t ptw = c->ptw();
+  if ((rc = dalloc(c, total * ptw * 8, (void**)&c->pt))) return rc;
+  int8_t* demb = nullptr;
+  EncodeJob* djobs = nullptr;
+  if ((rc = dalloc(c, n_entries * c->d, (void**)&demb))) return rc;
+  if ((rc = dalloc(c, total * sizeof(EncodeJob), (void**)&djobs))) {
+    dfree(c, demb);
+    return rc;
+  }
+  std::vector<EncodeJob> jobs(total);
+  for (uint32_t i = 0; i < k; ++i)
+    for (uint32_t ch = 0; ch < chunks[i]; ++ch) {
+      const uint64_t first = offsets[i] + (uint64_t)ch * c->n;
+      jobs[base[i] + ch] = EncodeJob{demb + first * c->d, std::min<uint64_t>(c->n, offsets[i + 1] - first),
+                                     c->pt + (base[i] + ch) * ptw};
+    }
+  hipError_t e = hipMemcpy(demb, emb, n_entries * c->d, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(djobs, jobs.data(), total * sizeof(EncodeJob), hipMemcpyHostToDevice);
+  EncodeArgs a{c->log_n, c->L, (uint32_t)c->d, (uint32_t)c->d_pad, (uint32_t)c->g, c->slot_of};
+  const uint64_t step = 4096;
+  for (uint64_t j0 = 0; e == hipSuccess && j0 < total; j0 += step)
+    e = launch_encode(djobs + j0, (int)std::min(step, total - j0), a, c->M, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  dfree(c, demb);
+  dfree(c, djobs);
+  if (e != hipSuccess) return set_err(c, WALLY_EDEVICE, "encode failed: %s", hipGetErrorString(e));
+  c->K = k;
+  c->chunks = chunks;
+  c->chunk_base = base;
+  c->max_chunks = maxc;
+  return WALLY_OK;
+}
+
+int wally_cluster_info(const wally_ctx* c, uint32_t cl, uint32_t* n_chunks, const uint64_t** plaintexts) {
+  if (!c || cl >= c->K) return WALLY_EINVAL;
+  if (n_chunks) *n_chunks = c->chunks[cl];
+  if (plaintexts) *plaintexts = c->pt + c->chunk_base[cl] * c->ptw();
+  return WALLY_OK;
+}
+
+int wally_score_batch(wally_ctx* c, const wally_query* q, uint64_t nq, int path, void* hip_stream) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->K == 0) return set_err(c, WALLY_ESTATE, "no clusters encoded");
+  if (path != WALLY_PATH_BATCHED && path != WALLY_PATH_PLAIN) return set_err(c, WALLY_EINVAL, "unknown path %d", path);
+  if (nq == 0) return WALLY_OK;
+  if (!q) return set_err(c, WALLY_EINVAL, "null query array");
+  for (uint64_t i = 0; i < nq; ++i)
+    if ((rc = validate_query(c, q[i], i))) return rc;
+  if ((rc = ensure_sets(c))) return rc;
+  hipStream_t user = (hipStream_t)hip_stream;
+  // order queries by cluster so a wave touches few plaintext chunks
+  std::vector<const wally_query*> ord(nq);
+  for (uint64_t i = 0; i < nq; ++i) ord[i] = &q[i];
+  std::stable_sort(ord.begin(), ord.end(), [](const wally_query* a, const wally_query* b) { return a->cluster < b->cluster; });
+  // waves
+  std::vector<std::pair<uint64_t, uint64_t>> waves;
+  for (uint64_t i = 0; i < nq;) {
+    uint64_t j = i;
+    while (j < nq && j - i < (uint64_t)c->B && (path == WALLY_PATH_BATCHED || ord[j]->cluster == ord[i]->cluster)) ++j;
+    waves.push_back({i, j});
+    i = j;
+  }
+  // fork: every set stream waits for the caller's stream
+  HIP_OK(c, hipEventRecord(c->fork, user));
+  for (auto& s : c->sets) HIP_OK(c, hipStreamWaitEvent(s.stream, c->fork, 0));
+  for (size_t wv = 0; wv < waves.size(); ++wv) {
+    WaveWork& s = c->sets[wv % c->sets.size()];
+    if ((rc = enqueue_wave(c, s, ord.data() + waves[wv].first, (int)(waves[wv].second - waves[wv].first)))) return rc;
+  }
+  // join
+  for (auto& s : c->sets) {
+    HIP_OK(c, hipEventRecord(s.done, s.stream));
+    HIP_OK(c, hipStreamWaitEvent(user, s.done, 0));
+  }
+  return WALLY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// serving: continuous batching over the workspace sets.  A wave is launched
+// whenever a set is idle and requests are pending; poll() retires finished
+// waves and launches the next ones.
+
+namespace {
+int serve_pump(wally_ctx* c) {
+  int rc;
+  for (auto& s : c->sets) {
+    if (s.busy) {
+      hipError_t e = hipEventQuery(s.done);
+      if (e == hipErrorNotReady) continue;
+      if (e != hipSuccess) return set_err(c, WALLY_EDEVICE, "serving wave failed: %s", hipGetErrorString(e));
+      for (uint64_t t : s.tickets) c->finished.push_back(t);
+      s.tickets.clear();
+      s.busy = false;
+    }
+    if (!s.busy && !c->pending.empty()) {
+      std::vector<const wally_query*> qs;
+      std::vector<ServeReq> taken;
+      while (!c->pending.empty() && (int)taken.size() < c->B) {
+        taken.push_back(c->pending.front());
+        c->pending.pop_front();
+      }
+      for (auto& r : taken) qs.push_back(&r.q);
+      if ((rc = enqueue_wave(c, s, qs.data(), (int)qs.size()))) return rc;
+      // descriptors are copied by the enqueue; the request copies may go
+      for (auto& r : taken) s.tickets.push_back(r.ticket);
+      s.busy = true;
+    }
+  }
+  return WALLY_OK;
+}
+}  // namespace
+
+int wally_serve_start(wally_ctx* c, void* hip_stream) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->serving) return set_err(c, WALLY_ESTATE, "already serving");
+  if (c->K == 0) return set_err(c, WALLY_ESTATE, "no clusters encoded");
+  if ((rc = ensure_sets(c))) return rc;
+  c->serve_stream = (hipStream_t)hip_stream;
+  HIP_OK(c, hipEventRecord(c->fork, c->serve_stream));
+  for (auto& s : c->sets) HIP_OK(c, hipStreamWaitEvent(s.stream, c->fork, 0));
+  c->pending.clear();
+  c->finished.clear();
+  // admission: in flight = one wave per set; waiting = the same again
+  c->max_pending = (uint64_t)c->B * c->sets.size();
+  c->serving = true;
+  return WALLY_OK;
+}
+
+int wally_serve_submit(wally_ctx* c, const wally_query* q, uint64_t* ticket) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->serving) return set_err(c, WALLY_ESTATE, "not serving");
+  if (!q || !ticket) return set_err(c, WALLY_EINVAL, "null argument");
+  if ((rc = validate_query(c, *q, 0))) return rc;
+  if (c->pending.size() >= c->max_pending) {
+    if ((rc = serve_pump(c))) return rc;
+    if (c->pending.size() >= c->max_pending) return WALLY_EAGAIN;
+  }
+  *ticket = c->next_ticket++;
+  c->pending.push_back(ServeReq{*q, *ticket});
+  return serve_pump(c);
+}
+
+int wally_serve_poll(wally_ctx* c, uint64_t* done, uint32_t max, uint32_t* n_done) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->serving) return set_err(c, WALLY_ESTATE, "not serving");
+  if (!n_done || (max && !done)) return set_err(c, WALLY_EINVAL, "null argument");
+  if ((rc = serve_pump(c))) return rc;
+  uint32_t k = 0;
+  while (k < max && !c->finished.empty()) {
+    done[k++] = c->finished.front();
+    c->finished.pop_front();
+  }
+  *n_done = k;
+  return WALLY_OK;
+}
+
+int wally_serve_stop(wally_ctx* c) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->serving) return set_err(c, WALLY_ESTATE, "not serving");
+  while (!c->pending.empty() || std::any_of(c->sets.begin(), c->sets.end(), [](const WaveWork& s) { return s.busy; })) {
+    if ((rc = serve_pump(c))) return rc;
+    for (auto& s : c->sets)
+      if (s.busy) HIP_OK(c, hipEventSynchronize(s.done));
+  }
+  for (auto& s : c->sets) {
+    HIP_OK(c, hipEventRecord(s.done, s.stream));
+    HIP_OK(c, hipStreamWaitEvent(c->serve_stream, s.done, 0));
+  }
+  c->serving = false;
+  return WALLY_OK;
+}
+
+void wally_destroy(wally_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  free_sets(c);
+  while (!c->allocs.empty()) dfree(c, c->allocs.back().first);
+  if (c->fork) (void)hipEventDestroy(c->fork);
+  delete c;
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics
+
+int wally_diag_ntt(wally_ctx* c, uint32_t mi, uint64_t* data, uint64_t rows, int inverse, void* hip_stream) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  if (mi > (uint32_t)c->L + 1 || !data) return set_err(c, WALLY_EINVAL, "bad modulus index or null data");
+  for (uint64_t r0 = 0; r0 < rows; r0 += 65535)
+    HIP_OK(c, launch_ntt_rows(data + r0 * c->n, (int)std::min<uint64_t>(65535, rows - r0), c->log_n, (int)mi,
+                              inverse ? 1 : 0, c->M, (hipStream_t)hip_stream));
+  return WALLY_OK;
+}
+
+int wally_diag_rotate(wally_ctx* c, const uint64_t* in, const uint64_t* keys, uint64_t* out, uint64_t count,
+                      int which, void* hip_stream) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!in || !keys || !out) return set_err(c, WALLY_EINVAL, "null pointer");
+  if (which != 0 && which != 1) return set_err(c, WALLY_EINVAL, "which must be 0 or 1");
+  if ((rc = ensure_sets(c))) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  WaveWork& s = c->sets[0];
+  const uint64_t ctw = c->ctw();
+  for (uint64_t i0 = 0; i0 < count; i0 += c->B) {
+    const int w = (int)std::min<uint64_t>(c->B, count - i0);
+    HIP_OK(c, hipStreamSynchronize(st));
+    HIP_OK(c, hipStreamSynchronize(s.stream));
+    for (int k = 0; k < w; ++k)
+      s.baby_host[k] = KsItem{keys + (i0 + k) * c->keyw(), const_cast<uint64_t*>(in) + (i0 + k) * ctw,
+                              out + (i0 + k) * ctw, nullptr, nullptr, nullptr};
+    HIP_OK(c, hipMemcpyAsync(s.baby_dev, s.baby_host, w * sizeof(KsItem), hipMemcpyHostToDevice, st));
+    KsArgs a = base_args(c, s);
+    a.gal = which ? c->gal_giant : c->gal_baby;
+    a.in_sel = 0;
+    a.out_sel = 1;
+    HIP_OK(c, launch_keyswitch(s.baby_dev, w, a, c->M, st));
+  }
+  return WALLY_OK;
+}
+
+}  // extern "C"

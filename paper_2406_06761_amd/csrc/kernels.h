@@ -1,0 +1,76 @@
+// Shared declarations between the host library and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wally {
+
+constexpr int kMaxLimbs = 8;
+constexpr int kMaxMod = kMaxLimbs + 2;  // q_0..q_{L-1}, P, t
+
+struct ModConst {
+  uint64_t q, q2;
+  uint64_t r64, r64p;  // 2^64 mod q, Shoup factor
+  uint64_t onep;       // floor(2^64 / q)
+};
+
+// Everything a kernel needs about the moduli, passed by value.
+// Index m: 0..L-1 ciphertext primes, L the special prime P, L+1 the plaintext modulus t.
+struct DevModuli {
+  uint64_t q[kMaxMod];
+  ModConst mc[kMaxMod];
+  uint64_t ninv[kMaxMod], ninvp[kMaxMod];  // n^-1 mod q and Shoup factor
+  uint64_t pinv[kMaxMod], pinvp[kMaxMod];  // P^-1 mod q_j (j < L) and Shoup factor
+  const ulonglong2* fwd[kMaxMod];          // (psi^brv(k), Shoup) for k < n
+  const ulonglong2* inv[kMaxMod];          // (psi^-brv(k), Shoup)
+};
+
+// One key switch (CtRotate) work item.  Input and output are chosen by the
+// launch (KsArgs::in_sel / out_sel): 0 = buf0 + off, 1 = buf1 + off, 2 = fin + off.
+struct KsItem {
+  const uint64_t* key;   // [L][2][L+1][n]
+  uint64_t* buf0;
+  uint64_t* buf1;
+  uint64_t* fin;
+  const uint64_t* pt;    // plaintexts of the chunk [d_pad][L][n] (giant steps)
+  const uint64_t* ctp;   // rotated query copies [g][2][L][n] (giant steps)
+};
+
+struct KsArgs {
+  int log_n, L;
+  uint32_t gal;
+  int in_sel, out_sel;
+  uint64_t in_off, out_off;
+  int giant;   // giant-step index i to fuse acc_i, or -1
+  int g;
+  uint64_t* X;  // scratch [items][L][n]
+  uint64_t* U;  // scratch [items][2][L][n]
+  uint64_t* Y;  // scratch [items][2][n]
+  uint64_t* D;  // scratch [items][L+1][L][n]: extended digits
+};
+
+struct CopyItem {
+  const uint64_t* src;
+  uint64_t* dst;
+};
+
+struct EncodeJob {
+  const int8_t* emb;    // first entry of the chunk, row-major [.][d]
+  uint64_t n_entries;   // entries of the cluster in this chunk (<= n)
+  uint64_t* out;        // [d_pad][L][n]
+};
+
+struct EncodeArgs {
+  int log_n, L;
+  uint32_t d, d_pad, g;
+  const uint32_t* slot_of;  // NTT index -> slot
+};
+
+hipError_t launch_keyswitch(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
+hipError_t launch_mac_init(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
+hipError_t launch_copy_ct(const CopyItem* items, int n_items, uint64_t words, hipStream_t st);
+hipError_t launch_encode(const EncodeJob* jobs, int n_jobs, const EncodeArgs& a, const DevModuli& M, hipStream_t st);
+hipError_t launch_ntt_rows(uint64_t* data, int rows, int log_n, int mi, int inverse, const DevModuli& M,
+                           hipStream_t st);
+
+}  // namespace wally

@@ -1,0 +1,179 @@
+// Workgroup-resident negacyclic NTT for one polynomial of n = 2^LOGN words.
+//
+// The transform is the one of the scheme: entry i of the forward transform of
+// a(X) mod q is a(psi^(2 brv(i) + 1)), psi the smallest primitive 2n-th root.
+// It is evaluated as Cooley-Tukey stages s = 0..LOGN-1 (stage s: 2^s groups,
+// butterfly distance n / 2^(s+1), twiddle psi^brv(2^s + group)) with Harvey's
+// lazy butterflies (paper §7.1): values stay in [0, 4q) between stages and
+// twiddle products use Shoup's precomputed quotient.  The inverse runs the
+// Gentleman-Sande butterflies of the same stages in reverse order.
+//
+// Layout on gfx950: T = n/16 threads, 16 elements per thread in registers.
+// Stages are grouped in passes of four (radix 16) done entirely in registers;
+// between passes the polynomial goes through LDS (n words plus padding).
+// Element e of thread tid in the pass starting at stage S0 (window of RW
+// stages, combos of 2^RW elements) has index
+//     idx = (high << (LOGN - S0)) | (w << LOWB) | low,
+//     e = c * 2^RW + w, combo = tid + T * c, high = combo >> LOWB,
+//     low = combo mod 2^LOWB, LOWB = LOGN - S0 - RW.
+// The first pass is the natural order (idx = (e << (LOGN-4)) | tid: lanes read
+// consecutive words), the last pass leaves each thread with contiguous
+// elements of the transform.
+#pragma once
+#include "arith.h"
+
+namespace wally {
+
+template <int LOGN>
+struct NttShape {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int E = 16;
+  static constexpr int RB = 4;
+  static constexpr int T = N / E;
+  static constexpr int NPASS = (LOGN + RB - 1) / RB;
+  static constexpr int LAST_S0 = RB * (NPASS - 1);
+  static constexpr int LDS_WORDS = N + N / 32;
+  __device__ static __forceinline__ int lds(int idx) { return idx + (idx >> 5); }
+};
+
+template <int LOGN, int S0>
+struct PassMap {
+  static constexpr int RW = (LOGN - S0) < 4 ? (LOGN - S0) : 4;
+  static constexpr int LOWB = LOGN - S0 - RW;
+  static constexpr int COMBOS = 16 >> RW;
+  static constexpr int T = NttShape<LOGN>::T;
+  // index of register e of thread tid
+  __device__ static __forceinline__ uint32_t idx(int tid, int e) {
+    const uint32_t c = e >> RW, w = e & ((1 << RW) - 1);
+    const uint32_t combo = tid + T * c;
+    const uint32_t high = combo >> LOWB, low = combo & ((1u << LOWB) - 1);
+    return (high << (LOGN - S0)) | (w << LOWB) | low;
+  }
+};
+
+template <int LOGN>
+using FirstMap = PassMap<LOGN, 0>;
+template <int LOGN>
+using LastMap = PassMap<LOGN, NttShape<LOGN>::LAST_S0>;
+
+// Cooley-Tukey butterfly, inputs and outputs in [0, 4q).
+__device__ __forceinline__ void ct_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, uint64_t q, uint64_t q2) {
+  const uint64_t x = X >= q2 ? X - q2 : X;
+  const uint64_t t = shoup(Y, W.x, W.y, q);
+  X = x + t;
+  Y = x - t + q2;
+}
+
+// Gentleman-Sande butterfly, inputs and outputs in [0, 2q).
+__device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, uint64_t q, uint64_t q2) {
+  const uint64_t u = X + Y;
+  const uint64_t v = X - Y + q2;
+  X = u >= q2 ? u - q2 : u;
+  Y = shoup(v, W.x, W.y, q);
+}
+
+template <int LOGN, int S0>
+__device__ __forceinline__ void ct_pass(uint64_t (&x)[16], const ulonglong2* __restrict__ tw, uint64_t q, uint64_t q2,
+                                        int tid) {
+  using M = PassMap<LOGN, S0>;
+#pragma unroll
+  for (int c = 0; c < M::COMBOS; ++c) {
+    const uint32_t combo = tid + M::T * c;
+    const uint32_t high = combo >> M::LOWB;
+#pragma unroll
+    for (int ls = 0; ls < M::RW; ++ls) {
+      const int half = 1 << (M::RW - 1 - ls);
+#pragma unroll
+      for (int w = 0; w < (1 << M::RW); ++w) {
+        if (w & half) continue;
+        const uint32_t grp = ((high << M::RW) | (uint32_t)w) >> (M::RW - ls);
+        const ulonglong2 W = tw[(1u << (S0 + ls)) + grp];
+        ct_bfly(x[c * (1 << M::RW) + w], x[c * (1 << M::RW) + w + half], W, q, q2);
+      }
+    }
+  }
+}
+
+template <int LOGN, int S0>
+__device__ __forceinline__ void gs_pass(uint64_t (&x)[16], const ulonglong2* __restrict__ itw, uint64_t q, uint64_t q2,
+                                        int tid) {
+  using M = PassMap<LOGN, S0>;
+#pragma unroll
+  for (int c = 0; c < M::COMBOS; ++c) {
+    const uint32_t combo = tid + M::T * c;
+    const uint32_t high = combo >> M::LOWB;
+#pragma unroll
+    for (int ls = M::RW - 1; ls >= 0; --ls) {
+      const int half = 1 << (M::RW - 1 - ls);
+#pragma unroll
+      for (int w = 0; w < (1 << M::RW); ++w) {
+        if (w & half) continue;
+        const uint32_t grp = ((high << M::RW) | (uint32_t)w) >> (M::RW - ls);
+        const ulonglong2 W = itw[(1u << (S0 + ls)) + grp];
+        gs_bfly(x[c * (1 << M::RW) + w], x[c * (1 << M::RW) + w + half], W, q, q2);
+      }
+    }
+  }
+}
+
+// Move the polynomial from the register mapping of pass A to that of pass B.
+// Ends with a barrier so the buffer can be reused right away.
+template <int LOGN, int SA, int SB>
+__device__ __forceinline__ void exchange(uint64_t (&x)[16], uint64_t* lds, int tid) {
+  using S = NttShape<LOGN>;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) lds[S::lds(PassMap<LOGN, SA>::idx(tid, e))] = x[e];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 16; ++e) x[e] = lds[S::lds(PassMap<LOGN, SB>::idx(tid, e))];
+  __syncthreads();
+}
+
+template <int LOGN, int P>
+__device__ __forceinline__ void fwd_passes(uint64_t (&x)[16], uint64_t* lds, const ulonglong2* tw, uint64_t q,
+                                           uint64_t q2, int tid) {
+  constexpr int S0 = 4 * P;
+  if constexpr (S0 < LOGN) {
+    if constexpr (P > 0) exchange<LOGN, 4 * (P - 1), S0>(x, lds, tid);
+    ct_pass<LOGN, S0>(x, tw, q, q2, tid);
+    fwd_passes<LOGN, P + 1>(x, lds, tw, q, q2, tid);
+  }
+}
+
+template <int LOGN, int P>
+__device__ __forceinline__ void inv_passes(uint64_t (&x)[16], uint64_t* lds, const ulonglong2* itw, uint64_t q,
+                                           uint64_t q2, int tid) {
+  if constexpr (P >= 0) {
+    constexpr int S0 = 4 * P;
+    if constexpr (P < NttShape<LOGN>::NPASS - 1) exchange<LOGN, 4 * (P + 1), S0>(x, lds, tid);
+    gs_pass<LOGN, S0>(x, itw, q, q2, tid);
+    inv_passes<LOGN, P - 1>(x, lds, itw, q, q2, tid);
+  }
+}
+
+// Forward transform.  In: FirstMap order, values < 4q.  Out: LastMap order, [0, 4q).
+template <int LOGN>
+__device__ __forceinline__ void ntt_fwd(uint64_t (&x)[16], uint64_t* lds, const ulonglong2* tw, uint64_t q,
+                                        int tid) {
+  fwd_passes<LOGN, 0>(x, lds, tw, q, 2 * q, tid);
+}
+
+// Inverse transform without the n^-1 factor.  In: LastMap order, values < 2q.
+// Out: FirstMap order, [0, 2q).
+template <int LOGN>
+__device__ __forceinline__ void ntt_inv(uint64_t (&x)[16], uint64_t* lds, const ulonglong2* itw, uint64_t q,
+                                        int tid) {
+  inv_passes<LOGN, NttShape<LOGN>::NPASS - 1>(x, lds, itw, q, 2 * q, tid);
+}
+
+// Source index of NTT entry i under X -> X^gal: entry i holds a(psi^(2 brv(i)+1)),
+// so sigma(a) at i is a at psi^(gal (2 brv(i) + 1)).
+template <int LOGN>
+__device__ __forceinline__ uint32_t galois_src(uint32_t i, uint32_t gal) {
+  const uint32_t mask2n = (2u << LOGN) - 1;
+  const uint32_t e = 2u * (__brev(i) >> (32 - LOGN)) + 1u;
+  const uint32_t f = (e * gal) & mask2n;
+  return __brev((f - 1u) >> 1) >> (32 - LOGN);
+}
+
+}  // namespace wally

@@ -1,0 +1,169 @@
+"""GPU parity: the HIP path against the CPU oracle, word for word.
+
+Integer arithmetic throughout, so the bar is bit-exact equality of every
+uint64 word (ciphertexts, keys, plaintexts, transforms) and exact equality of
+decrypted scores with int64 dot products mod t.
+"""
+import numpy as np
+import pytest
+
+from oracle.bfv import Oracle
+from oracle.params import Params, preset
+from paper_2406_06761_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _ctx(name, **kw):
+    from paper_2406_06761_amd.wally import Context
+
+    return Context.preset(name, **kw)
+
+
+@pytest.fixture(scope="module", params=["tiny", "paper"])
+def pair(request):
+    name = request.param
+    c = _ctx(name, max_batch=8)
+    o = Oracle(preset(name))
+    yield name, c, o
+    c.close()
+
+
+def test_params_agree_with_oracle(pair):
+    _, c, o = pair
+    i, p = c.info, o.p
+    assert [i.q[j] for j in range(i.L)] == p.q and i.P == p.P and i.t == p.t
+    assert [i.psi[j] for j in range(i.L + 1)] == p.psi and i.psi_t == p.psi_t
+    assert (i.d_pad, i.g, i.h, i.gal_baby, i.gal_giant) == (p.d_pad, p.g, p.h, p.gal_baby, p.gal_giant)
+
+
+def test_ntt_parity(pair):
+    from paper_2406_06761_amd.wally import to_device, to_host
+
+    _, c, o = pair
+    rng = np.random.default_rng(1)
+    mods = o.p.moduli + [o.p.t]
+    for mi, m in enumerate(mods):
+        rows = rng.integers(0, m, (5, o.n), dtype=np.uint64)
+        rows[0] = 0
+        rows[1] = m - 1
+        d = to_device(rows)
+        c.diag_ntt(mi, d)
+        torch.cuda.synchronize()
+        got = to_host(d)
+        assert (got == o.ntt(rows, mi)).all(), mi
+        c.diag_ntt(mi, d, inverse=True)
+        torch.cuda.synchronize()
+        assert (to_host(d) == rows).all(), mi
+
+
+def test_rotate_parity(pair):
+    from paper_2406_06761_amd.wally import to_device, to_host
+
+    _, c, o = pair
+    p = o.p
+    rng = np.random.default_rng(2)
+    count = 3
+    ct = np.stack([o.uniform(rng, p.q, count=2) for _ in range(count)])
+    keys = np.stack([o.uniform(rng, p.moduli, count=2 * p.L).reshape(p.L, 2, p.L + 1, p.n) for _ in range(count)])
+    for which, gal in ((0, p.gal_baby), (1, p.gal_giant)):
+        dct, dk = to_device(ct), to_device(keys)
+        dout = torch.empty_like(dct)
+        c.diag_rotate(dct, dk, dout, which)
+        torch.cuda.synchronize()
+        got = to_host(dout)
+        for k in range(count):
+            assert (got[k] == o.rotate(ct[k], keys[k], gal)).all(), (which, k)
+
+
+def test_rotate_real_key_decrypts(pair):
+    from paper_2406_06761_amd.wally import to_device, to_host
+
+    _, c, o = pair
+    p = o.p
+    rng = np.random.default_rng(3)
+    s = o.secret_key(rng)
+    v = rng.integers(0, p.t, p.n)
+    ct = o.encrypt(s, v, rng)
+    key = o.galois_key(s, p.gal_baby, rng)
+    dout = torch.empty((2, p.L, p.n), dtype=torch.int64, device="cuda")
+    c.diag_rotate(to_device(ct), to_device(key), dout, 0)
+    torch.cuda.synchronize()
+    dec = o.decrypt(s, to_host(dout)).astype(np.int64)
+    half = p.n // 2
+    assert (dec == np.concatenate([np.roll(v[:half], -1), np.roll(v[half:], -1)])).all()
+
+
+def test_encode_parity(pair):
+    name, c, o = pair
+    p = o.p
+    sizes = np.array([100, p.n + 37, 5, 2 * p.n], dtype=np.int64)
+    emb = synth.embeddings(int(sizes.sum()), p.dim, seed=31, norm="l2")
+    offs = synth.offsets(sizes)
+    c.encode_clusters(emb, offs)
+    for k in range(len(sizes)):
+        chunks, ptr = c.cluster_info(k)
+        want = o.encode_cluster(emb[int(offs[k]) : int(offs[k + 1])])
+        assert chunks == want.shape[0]
+        words = want.size
+        got = _read_device(ptr, words).reshape(want.shape)
+        assert (got == want).all(), k
+
+
+def _read_device(ptr, words):
+    """Copy `words` uint64 from a device address into host memory."""
+    import ctypes
+
+    host = np.empty(words, dtype=np.uint64)
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    rc = hip.hipMemcpy(host.ctypes.data, ctypes.c_void_p(ptr), words * 8, 2)  # device to host
+    assert rc == 0
+    return host
+
+
+@pytest.fixture(scope="module")
+def tiny_workload():
+    p = preset("tiny")
+    o = Oracle(p)
+    w = synth.tiny_workload()
+    emb = synth.embeddings(w.n_entries, w.dim, norm=w.norm)
+    offs = synth.offsets(w.sizes)
+    pts = [o.encode_cluster(emb[int(offs[k]) : int(offs[k + 1])]) for k in range(len(w.sizes))]
+    qv = synth.query_vectors(len(w.targets), w.dim, w.norm)
+    rng = np.random.default_rng(synth.SEED_CRYPTO)
+    packets = [o.make_query(qv[i], rng) for i in range(len(w.targets))]
+    ref = o.score_many([(ct, kb, kg, pts[int(w.targets[i])]) for i, (ct, kb, kg, _) in enumerate(packets)], threads=4)
+    return o, w, emb, offs, qv, packets, ref
+
+
+@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("max_batch", [16, 5])
+def test_tiny_end_to_end(tiny_workload, path, max_batch):
+    from paper_2406_06761_amd.wally import query_array, to_device, to_host
+
+    o, w, emb, offs, qv, packets, ref = tiny_workload
+    c = _ctx("tiny", max_batch=max_batch)
+    try:
+        c.encode_clusters(emb, offs)
+        nq = len(w.targets)
+        cts = to_device(np.stack([pk[0] for pk in packets]))
+        kbs = to_device(np.stack([pk[1] for pk in packets]))
+        kgs = to_device(np.stack([pk[2] for pk in packets]))
+        outs = torch.zeros((nq, 1, 2, o.L, o.n), dtype=torch.int64, device="cuda")
+        q = query_array(w.targets, [cts[i].data_ptr() for i in range(nq)], [kbs[i].data_ptr() for i in range(nq)],
+                        [kgs[i].data_ptr() for i in range(nq)], [outs[i].data_ptr() for i in range(nq)])
+        c.score_batch(q, path=path)
+        torch.cuda.synchronize()
+        got = to_host(outs)
+        for i in range(nq):
+            assert (got[i] == ref[i]).all(), i
+            s = packets[i][3]
+            dec = o.decrypt(s, got[i][0]).astype(np.int64)
+            k = int(w.targets[i])
+            rows = emb[int(offs[k]) : int(offs[k + 1])].astype(np.int64)
+            assert (dec[: len(rows)] == (rows @ qv[i].astype(np.int64)) % o.p.t).all()
+    finally:
+        c.close()
