@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Throughput of server-side encrypted scoring on one MI355X.
+
+One step = one batch of the paper-scale workload scored through the C ABI
+(wally_score_batch): 3,200,000 int8 entries of dim 192 in 1,800 lognormal
+clusters (sigma 0.8), resident in HBM as NTT-form plaintexts; 50,000 real
+queries on Zipf(1.1) clusters plus NB(2, 0.5) fake queries per cluster.
+Every query is scored against every entry of its cluster: baby-step
+rotations, plaintext products, giant-step rotations (Server Computation
+algorithm of the paper, §5).
+
+Query packets (ciphertext + two Galois keys) come from a device-resident pool
+of uniformly random residues: the server's work does not depend on their
+values (RLWE ciphertexts and keys are indistinguishable from uniform), and the
+pool is far larger than the caches.  Parity of the same launch configuration
+with real encryptions is checked by the GPU tests against the CPU oracle.
+
+Prints one JSON line (see the keys below); progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 39.3e12 lane-instructions/s
+INSTR_PER_MODMUL = 20                       # VALU instructions of one 54-bit Shoup butterfly
+HBM_PEAK = 8.0e12
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def per_item_work(kernel, n, L, g):
+    """Algorithmic modular multiply(-accumulate)s per work item of each kernel.
+    One NTT = (n/2) log2 n butterflies; an inverse NTT adds n scalings."""
+    bf = n // 2 * int(math.log2(n))
+    if kernel == "ks_digits":
+        return L * (bf + n)
+    if kernel == "ks_modup":
+        return L * L * bf + 2 * (bf + n) + 2 * L * (L + 1) * n
+    if kernel == "ks_moddown":
+        return 2 * L * bf + 2 * L * n
+    if kernel == "mac_init":
+        return 2 * g * L * n
+    return 0
+
+
+def cpu_baseline(workload, sample, threads, params_name):
+    """The oracle as it is, on host cores, on a seeded sample of the batch's
+    queries (uniform-residue packets like the GPU run)."""
+    from oracle.bfv import Oracle
+    from oracle.params import preset
+    from paper_2406_06761_amd import synth
+
+    p = preset(params_name)
+    o = Oracle(p)
+    rng = np.random.default_rng(99)
+    idx = np.sort(rng.choice(len(workload.targets), size=sample, replace=False))
+    offs = synth.offsets(workload.sizes)
+    clusters = sorted(set(int(workload.targets[i]) for i in idx))
+    log(f"cpu baseline: encoding {len(clusters)} clusters with the oracle (untimed)")
+    pts = {}
+    for c in clusters:
+        emb = synth.embeddings(int(workload.sizes[c]), workload.dim, norm=workload.norm, row_start=int(offs[c]))
+        pts[c] = o.encode_cluster(emb)
+    jobs = []
+    for i in idx:
+        ct = o.uniform(rng, p.q, count=2)
+        kb = o.uniform(rng, p.moduli, count=2 * p.L).reshape(p.L, 2, p.L + 1, p.n)
+        kg = o.uniform(rng, p.moduli, count=2 * p.L).reshape(p.L, 2, p.L + 1, p.n)
+        jobs.append((ct, kb, kg, pts[int(workload.targets[i])]))
+    log(f"cpu baseline: scoring {sample} queries on {threads} threads")
+    t0 = time.perf_counter()
+    o.score_many(jobs, threads=threads)
+    dt = time.perf_counter() - t0
+    scores = int(sum(workload.sizes[int(workload.targets[i])] for i in idx))
+    return {"value": scores / dt, "unit": "scores/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample} seeded queries of the batch ({scores} scores), {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
+    ap.add_argument("--real", type=int, default=50_000, help="real queries per batch (paper workload)")
+    ap.add_argument("--max-batch", type=int, default=0)
+    ap.add_argument("--wave-sets", type=int, default=0)
+    ap.add_argument("--pool", type=int, default=2048, help="distinct query packets resident on the device")
+    ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-cluster path (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="do not record per-launch events")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the scoring path has no cross-GPU step "
+              "(sharding by cluster is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2406_06761_amd import synth
+    from paper_2406_06761_amd.wally import PATH_BATCHED, PATH_PLAIN, Context, query_array
+
+    torch.cuda.set_device(0)
+    t_setup = time.perf_counter()
+    if args.workload == "paper":
+        w = synth.paper_workload(n_real=args.real)
+        preset_name = "paper"
+        log(f"generating {w.n_entries} x {w.dim} int8 entries")
+        emb = synth.embeddings_parallel(w.n_entries, w.dim, norm=w.norm, threads=16)
+    else:
+        w = synth.tiny_workload()
+        preset_name = "tiny"
+        emb = synth.embeddings(w.n_entries, w.dim, norm=w.norm)
+    ctx = Context.preset(preset_name, max_batch=args.max_batch, wave_sets=args.wave_sets)
+    info = ctx.info
+    n, L = info.n, info.L
+    log(f"params n={n} L={L} d_pad={info.d_pad} g={info.g} h={info.h}")
+    t0 = time.perf_counter()
+    ctx.encode_clusters(emb, synth.offsets(w.sizes))
+    torch.cuda.synchronize()
+    encode_s = time.perf_counter() - t0
+    chunks = (w.sizes + n - 1) // n
+    log(f"encoded {len(w.sizes)} clusters, {int(chunks.sum())} chunks, "
+        f"{ctx.bytes_allocated / 2**30:.1f} GiB resident, {encode_s:.2f} s")
+    del emb
+
+    # query packets: device-resident pool of uniform residues
+    pool = min(args.pool, len(w.targets))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(synth.SEED_CRYPTO)
+    qs = [info.q[j] for j in range(L)]
+    mods = qs + [info.P]
+    cts = synth.uniform_residues(gen, (pool, 2), qs, n, device="cuda")
+    kbs = synth.uniform_residues(gen, (pool, L, 2), mods, n, device="cuda")
+    kgs = synth.uniform_residues(gen, (pool, L, 2), mods, n, device="cuda")
+    nq = len(w.targets)
+    q_chunks = chunks[w.targets].astype(np.int64)
+    out_off = np.zeros(nq, dtype=np.int64)
+    out_off[1:] = np.cumsum(q_chunks)[:-1]
+    ctw = int(info.ct_words)
+    outs = torch.empty(int(q_chunks.sum()) * ctw, dtype=torch.int64, device="cuda")
+    pidx = np.arange(nq) % pool
+    q = query_array(w.targets, cts.data_ptr() + pidx * cts[0].numel() * 8, kbs.data_ptr() + pidx * kbs[0].numel() * 8,
+                    kgs.data_ptr() + pidx * kgs[0].numel() * 8, outs.data_ptr() + out_off * ctw * 8)
+    scores = int(w.sizes[w.targets].sum())
+    real_scores = int(w.sizes[w.targets[: w.n_real]].sum())
+    log(f"{nq} queries ({w.n_real} real), {scores} scores per step, pool {pool} packets, "
+        f"setup {time.perf_counter() - t_setup:.1f} s")
+
+    for i in range(args.warmup):
+        t0 = time.perf_counter()
+        ctx.score_batch(q, path=PATH_BATCHED)
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {time.perf_counter() - t0:.3f} s")
+
+    timing = not args.no_timing
+    if timing:
+        ctx.kernel_timing(True)
+        ctx.kernel_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.score_batch(q, path=PATH_BATCHED)
+        log(f"step {i} enqueued at {time.perf_counter() - t0:.3f} s")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    value = scores * args.steps / dt
+    log(f"batched: {ms_per_step:.1f} ms/step, {value:.4g} scores/s")
+
+    roofline = None
+    kstats = {}
+    if timing:
+        kstats = ctx.kernel_stats()
+        ctx.kernel_timing(False)
+        work = {k: per_item_work(k, n, L, info.g) for k in kstats}
+        # the giant-step launches of moddown also fuse the plaintext sum
+        dom = max((k for k in kstats if work[k] > 0), key=lambda k: kstats[k][2])
+        launches, items, total_ms = kstats[dom]
+        avg_ms = total_ms / max(launches, 1)
+        items_per_launch = items / max(launches, 1)
+        achieved = work[dom] * items_per_launch / (avg_ms * 1e-3)
+        peak = PEAK_VALU_LANE_OPS / INSTR_PER_MODMUL
+        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e9, "peak": peak / 1e9,
+                    "unit": "Gmodmul/s", "frac": achieved / peak, "traffic": None,
+                    "avg_launch_ms": avg_ms, "items_per_launch": items_per_launch,
+                    "work_per_item": work[dom]}
+        for k, (nl, it, ms) in kstats.items():
+            log(f"  {k:11s} launches {nl:7d} items {it:9d} total {ms:9.1f} ms avg {ms / max(nl, 1):.3f} ms")
+
+    plain = None
+    if args.plain_steps > 0:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.plain_steps):
+            ctx.score_batch(q, path=PATH_PLAIN)
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t0
+        plain = scores * args.plain_steps / pdt
+        log(f"plain per-cluster path: {pdt / args.plain_steps * 1e3:.1f} ms/step, {plain:.4g} scores/s")
+
+    cpu = None
+    if not args.no_cpu and args.cpu_sample > 0:
+        threads = min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(w, args.cpu_sample if args.workload == "paper" else min(16, nq), threads, preset_name)
+        log(f"cpu oracle: {cpu['value']:.4g} scores/s on {threads} threads")
+
+    line = {
+        "metric": "encrypted query-entry scores/sec (batched path)",
+        "value": value,
+        "unit": "scores/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "3.2M x 192 int8, 1800 lognormal(0.8) clusters, 50k Zipf(1.1) queries + NB(2,0.5) fakes"
+                   if args.workload == "paper" else "4096 x 64 int8, 4 clusters, 16 queries",
+                   "params": f"n={n}, L={L} x {54 if n == 8192 else 36}-bit limbs, t={info.t}",
+                   "queries": nq, "real_queries": w.n_real, "scores_per_step": scores,
+                   "real_scores_per_step": real_scores, "pool_packets": pool,
+                   "max_batch": args.max_batch or 1024, "wave_sets": args.wave_sets or 2},
+        "real_scores_per_s": real_scores * args.steps / dt,
+        "queries_per_s": nq * args.steps / dt,
+        "plain_path_scores_per_s": plain,
+        "speedup_vs_plain": (value / plain) if plain else None,
+        "encode_s": encode_s,
+        "roofline": roofline,
+        "kernels_ms": {k: v[2] for k, v in kstats.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

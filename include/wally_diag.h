@@ -29,6 +29,27 @@ int wally_diag_ntt(wally_ctx* ctx, uint32_t mi, uint64_t* data, uint64_t rows, i
 int wally_diag_rotate(wally_ctx* ctx, const uint64_t* in, const uint64_t* keys, uint64_t* out, uint64_t count,
                       int which, void* hip_stream);
 
+/* Per-launch timing.  When enabled, every kernel launch of the scoring path
+ * is bracketed by HIP events recorded on the stream it is launched on;
+ * wally_diag_kernel_stats waits for the recorded launches, sums the elapsed
+ * times per kernel (index = WALLY_KERNEL_*) into out[0..n), and clears the
+ * records. */
+#define WALLY_KERNEL_DIGITS 0   /* key switch: INTT of the digits           */
+#define WALLY_KERNEL_MODUP 1    /* key switch: extension + key inner product */
+#define WALLY_KERNEL_MODDOWN 2  /* key switch: division by P (+ giant sum)  */
+#define WALLY_KERNEL_MAC_INIT 3 /* first giant-step sum                     */
+#define WALLY_KERNEL_COPY 4     /* query copy into the baby-step buffer     */
+#define WALLY_KERNEL_COUNT 5
+
+typedef struct {
+  uint64_t launches;
+  uint64_t items;   /* work items over all launches (items x grid.y blocks) */
+  double total_ms;
+} wally_kernel_stat;
+
+int wally_diag_kernel_timing(wally_ctx* ctx, int enable);
+int wally_diag_kernel_stats(wally_ctx* ctx, wally_kernel_stat* out, uint32_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -116,6 +116,12 @@ struct ServeReq {
   uint64_t ticket;
 };
 
+struct TimerRec {
+  int kernel;
+  uint64_t items;
+  hipEvent_t a, b;
+};
+
 }  // namespace
 
 struct wally_ctx {
@@ -150,6 +156,10 @@ struct wally_ctx {
   std::deque<uint64_t> finished;
   uint64_t next_ticket = 1;
   uint64_t max_pending = 0;
+  // optional per-launch timing (events on the launch stream)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<TimerRec> timers;
 
   uint64_t ctw() const { return 2ull * L * n; }
   uint64_t keyw() const { return (uint64_t)L * 2 * (L + 1) * n; }
@@ -206,6 +216,38 @@ int check_live(wally_ctx* c) {
   if (c->dead) return WALLY_EDEVICE;
   HIP_OK(c, hipSetDevice(c->device));
   return WALLY_OK;
+}
+
+hipEvent_t pool_event(wally_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch through `fn`, bracketed by timing events on `st` when timing is on.
+template <class F>
+hipError_t timed(wally_ctx* c, hipStream_t st, int kernel, uint64_t items, F fn) {
+  if (!c->timing) return fn();
+  hipEvent_t a = pool_event(c), b = pool_event(c);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, st);
+  if (e == hipSuccess) e = fn();
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  c->timers.push_back(TimerRec{kernel, items, a, b});
+  return e;
+}
+
+hipError_t keyswitch(wally_ctx* c, const KsItem* items, int n, const KsArgs& a, hipStream_t st) {
+  hipError_t e = timed(c, st, WALLY_KERNEL_DIGITS, n, [&] { return launch_ks_digits(items, n, a, c->M, st); });
+  if (e == hipSuccess) e = timed(c, st, WALLY_KERNEL_MODUP, n, [&] { return launch_ks_modup(items, n, a, c->M, st); });
+  if (e == hipSuccess)
+    e = timed(c, st, WALLY_KERNEL_MODDOWN, n, [&] { return launch_ks_moddown(items, n, a, c->M, st); });
+  return e;
 }
 
 void free_sets(wally_ctx* c) {
@@ -309,7 +351,7 @@ int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w)
   HIP_OK(c, hipEventRecord(s.staged, s.stream));
 
   // baby steps: ct'_0 = ct, ct'_j = Rot(ct'_{j-1}, 1)
-  HIP_OK(c, launch_copy_ct(s.copy_dev, w, ctw, s.stream));
+  HIP_OK(c, timed(c, s.stream, WALLY_KERNEL_COPY, w, [&] { return launch_copy_ct(s.copy_dev, w, ctw, s.stream); }));
   for (int j = 1; j < c->g; ++j) {
     KsArgs a = base_args(c, s);
     a.gal = c->gal_baby;
@@ -317,7 +359,7 @@ int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w)
     a.in_off = (uint64_t)(j - 1) * ctw;
     a.out_sel = 0;
     a.out_off = (uint64_t)j * ctw;
-    HIP_OK(c, launch_keyswitch(s.baby_dev, w, a, c->M, s.stream));
+    HIP_OK(c, keyswitch(c, s.baby_dev, w, a, s.stream));
   }
   // giant steps per (query, chunk): R = acc_{h-1}; R = acc_i + Rot(R, g), i = h-2..0
   for (size_t g0 = 0; g0 < ng; g0 += c->B) {
@@ -326,7 +368,7 @@ int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w)
     KsArgs a = base_args(c, s);
     a.giant = c->h - 1;
     a.out_sel = c->h == 1 ? 2 : 0;
-    HIP_OK(c, launch_mac_init(items, cnt, a, c->M, s.stream));
+    HIP_OK(c, timed(c, s.stream, WALLY_KERNEL_MAC_INIT, cnt, [&] { return launch_mac_init(items, cnt, a, c->M, s.stream); }));
     int cur = 0;
     for (int i = c->h - 2; i >= 0; --i) {
       KsArgs b = base_args(c, s);
@@ -334,7 +376,7 @@ int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w)
       b.in_sel = cur;
       b.out_sel = i == 0 ? 2 : 1 - cur;
       b.giant = i;
-      HIP_OK(c, launch_keyswitch(items, cnt, b, c->M, s.stream));
+      HIP_OK(c, keyswitch(c, items, cnt, b, s.stream));
       cur = 1 - cur;
     }
   }
@@ -431,6 +473,8 @@ int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
   }
   c->budget = desc->hbm_budget ? desc->hbm_budget : (uint64_t)(free_b * 0.9);
   c->B = desc->max_batch ? (int)desc->max_batch : 1024;
+  c->n_sets = desc->wave_sets ? (int)desc->wave_sets : 2;
+  if (c->n_sets > 8) c->n_sets = 8;
 
   // tables: per modulus n forward + n inverse (w, Shoup) pairs, then slot_of
   const size_t tw_words = (size_t)nm * 2 * c->n * 2;
@@ -732,6 +776,8 @@ void wally_destroy(wally_ctx* c) {
   free_sets(c);
   while (!c->allocs.empty()) dfree(c, c->allocs.back().first);
   if (c->fork) (void)hipEventDestroy(c->fork);
+  for (auto& t : c->timers) c->ev_pool.push_back(t.a), c->ev_pool.push_back(t.b);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -771,8 +817,38 @@ int wally_diag_rotate(wally_ctx* c, const uint64_t* in, const uint64_t* keys, ui
     a.gal = which ? c->gal_giant : c->gal_baby;
     a.in_sel = 0;
     a.out_sel = 1;
-    HIP_OK(c, launch_keyswitch(s.baby_dev, w, a, c->M, st));
+    HIP_OK(c, keyswitch(c, s.baby_dev, w, a, st));
   }
+  return WALLY_OK;
+}
+
+int wally_diag_kernel_timing(wally_ctx* c, int enable) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->timing = enable != 0;
+  return WALLY_OK;
+}
+
+int wally_diag_kernel_stats(wally_ctx* c, wally_kernel_stat* out, uint32_t n) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!out && n) return set_err(c, WALLY_EINVAL, "null output");
+  for (uint32_t k = 0; k < n; ++k) out[k] = wally_kernel_stat{0, 0, 0.0};
+  for (auto& t : c->timers) {
+    HIP_OK(c, hipEventSynchronize(t.b));
+    float ms = 0.f;
+    HIP_OK(c, hipEventElapsedTime(&ms, t.a, t.b));
+    if (t.kernel >= 0 && (uint32_t)t.kernel < n) {
+      out[t.kernel].launches += 1;
+      out[t.kernel].items += t.items;
+      out[t.kernel].total_ms += ms;
+    }
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->timers.clear();
   return WALLY_OK;
 }
 

@@ -66,7 +66,10 @@ struct EncodeArgs {
   const uint32_t* slot_of;  // NTT index -> slot
 };
 
-hipError_t launch_keyswitch(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
+// the three key-switching kernels (launch order: digits, modup, moddown)
+hipError_t launch_ks_digits(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
+hipError_t launch_ks_modup(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
+hipError_t launch_ks_moddown(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
 hipError_t launch_mac_init(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
 hipError_t launch_copy_ct(const CopyItem* items, int n_items, uint64_t words, hipStream_t st);
 hipError_t launch_encode(const EncodeJob* jobs, int n_jobs, const EncodeArgs& a, const DevModuli& M, hipStream_t st);

@@ -296,23 +296,29 @@ __global__ __launch_bounds__(NttShape<LOGN>::T) void k_ntt_rows(uint64_t* data, 
 // ---------------------------------------------------------------------------
 // launchers
 
-template <int LOGN>
-static hipError_t launch_ks_t(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M,
-                              hipStream_t st) {
-  constexpr int T = NttShape<LOGN>::T;
-  hipLaunchKernelGGL(k_ks_digits<LOGN>, dim3(n_items, a.L), dim3(T), 0, st, items, a, M);
-  hipLaunchKernelGGL(k_ks_modup<LOGN>, dim3(n_items, a.L + 1), dim3(T), 0, st, items, a, M);
-  hipLaunchKernelGGL(k_ks_moddown<LOGN>, dim3(n_items, a.L), dim3(T), 0, st, items, a, M);
+#define WALLY_DISPATCH_LOGN(KERNEL, GRID, ...)                                                     \
+  switch (a.log_n) {                                                                               \
+    case 12: hipLaunchKernelGGL(KERNEL<12>, GRID, dim3(NttShape<12>::T), 0, st, __VA_ARGS__); break; \
+    case 13: hipLaunchKernelGGL(KERNEL<13>, GRID, dim3(NttShape<13>::T), 0, st, __VA_ARGS__); break; \
+    default: return hipErrorInvalidValue;                                                          \
+  }
+
+hipError_t launch_ks_digits(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  WALLY_DISPATCH_LOGN(k_ks_digits, dim3(n_items, a.L), items, a, M);
   return hipGetLastError();
 }
 
-hipError_t launch_keyswitch(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
+hipError_t launch_ks_modup(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  switch (a.log_n) {
-    case 12: return launch_ks_t<12>(items, n_items, a, M, st);
-    case 13: return launch_ks_t<13>(items, n_items, a, M, st);
-    default: return hipErrorInvalidValue;
-  }
+  WALLY_DISPATCH_LOGN(k_ks_modup, dim3(n_items, a.L + 1), items, a, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_ks_moddown(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  WALLY_DISPATCH_LOGN(k_ks_moddown, dim3(n_items, a.L), items, a, M);
+  return hipGetLastError();
 }
 
 hipError_t launch_mac_init(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {

@@ -32,7 +32,8 @@ class WallyError(RuntimeError):
 class ParamsDesc(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("num_limbs", ctypes.c_uint32), ("limb_bits", ctypes.c_uint32),
                 ("t_bits", ctypes.c_uint32), ("dim", ctypes.c_uint32), ("layout", ctypes.c_uint32),
-                ("device", ctypes.c_int32), ("max_batch", ctypes.c_uint32), ("hbm_budget", ctypes.c_uint64)]
+                ("device", ctypes.c_int32), ("max_batch", ctypes.c_uint32), ("wave_sets", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("hbm_budget", ctypes.c_uint64)]
 
 
 class ParamsInfo(ctypes.Structure):
@@ -55,8 +56,15 @@ assert ctypes.sizeof(Query) == QUERY_DTYPE.itemsize
 SYMBOLS = [
     "wally_params_init", "wally_params_query", "wally_encode_clusters", "wally_cluster_info", "wally_score_batch",
     "wally_serve_start", "wally_serve_submit", "wally_serve_poll", "wally_serve_stop", "wally_strerror",
-    "wally_last_error", "wally_destroy", "wally_diag_ntt", "wally_diag_rotate",
+    "wally_last_error", "wally_destroy", "wally_diag_ntt", "wally_diag_rotate", "wally_diag_kernel_timing",
+    "wally_diag_kernel_stats",
 ]
+
+KERNELS = ["ks_digits", "ks_modup", "ks_moddown", "mac_init", "copy_ct"]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("items", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
 _lib = None
 
@@ -89,6 +97,8 @@ def load():
         "wally_destroy": ([vp], None),
         "wally_diag_ntt": ([vp, u32, vp, u64, i32, vp], i32),
         "wally_diag_rotate": ([vp, vp, vp, vp, u64, i32, vp], i32),
+        "wally_diag_kernel_timing": ([vp, i32], i32),
+        "wally_diag_kernel_stats": ([vp, ctypes.POINTER(KernelStat), u32], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -113,9 +123,10 @@ def _ptr(t):
 class Context:
     """One parameter set on one device (wally_params_init ... wally_destroy)."""
 
-    def __init__(self, log_n, num_limbs, limb_bits, t_bits, dim, device=0, max_batch=0, hbm_budget=0):
+    def __init__(self, log_n, num_limbs, limb_bits, t_bits, dim, device=0, max_batch=0, hbm_budget=0, wave_sets=0):
         self.lib = load()
-        d = ParamsDesc(log_n, num_limbs, limb_bits, t_bits, dim, LAYOUT_PER_CLUSTER, device, max_batch, hbm_budget)
+        d = ParamsDesc(log_n, num_limbs, limb_bits, t_bits, dim, LAYOUT_PER_CLUSTER, device, max_batch, wave_sets, 0,
+                       hbm_budget)
         h = ctypes.c_void_p()
         rc = self.lib.wally_params_init(ctypes.byref(d), ctypes.byref(h))
         if rc:
@@ -195,6 +206,15 @@ class Context:
         count = ct.numel() // self.info.ct_words
         self._check(self.lib.wally_diag_rotate(self.h, _ptr(ct), _ptr(keys), _ptr(out), count, which,
                                                _stream_handle(stream)), "wally_diag_rotate")
+
+    def kernel_timing(self, enable=True):
+        self._check(self.lib.wally_diag_kernel_timing(self.h, 1 if enable else 0), "wally_diag_kernel_timing")
+
+    def kernel_stats(self):
+        """{kernel: (launches, items, total_ms)} since the last call (waits for the launches)."""
+        arr = (KernelStat * len(KERNELS))()
+        self._check(self.lib.wally_diag_kernel_stats(self.h, arr, len(KERNELS)), "wally_diag_kernel_stats")
+        return {k: (arr[i].launches, arr[i].items, arr[i].total_ms) for i, k in enumerate(KERNELS)}
 
     def close(self):
         if getattr(self, "h", None):

@@ -36,8 +36,8 @@ def test_struct_layouts_match_header():
     # wally_query: two uint32 then four pointers
     assert ctypes.sizeof(wally.Query) == 40
     assert wally.Query.ct.offset == 8 and wally.Query.out.offset == 32
-    # wally_params_desc: 8 x 32-bit fields then the 64-bit budget
-    assert ctypes.sizeof(wally.ParamsDesc) == 40 and wally.ParamsDesc.hbm_budget.offset == 32
+    # wally_params_desc: 10 x 32-bit fields then the 64-bit budget
+    assert ctypes.sizeof(wally.ParamsDesc) == 48 and wally.ParamsDesc.hbm_budget.offset == 40
     assert wally.ParamsInfo.q.offset == 24
 
 
@@ -50,8 +50,8 @@ def test_error_strings_and_null_handling():
     lib.wally_destroy(None)  # no-op
     assert lib.wally_last_error(None) == b"null context"
     # unsupported sizes are rejected before any device call
-    d = wally.ParamsDesc(11, 3, 36, 20, 64, 0, 0, 0, 0)
+    d = wally.ParamsDesc(11, 3, 36, 20, 64, 0, 0, 0, 0, 0, 0)
     h = ctypes.c_void_p()
     assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL
-    d = wally.ParamsDesc(12, 3, 36, 20, 4096, 0, 0, 0, 0)  # d_pad does not divide n/2
+    d = wally.ParamsDesc(12, 3, 36, 20, 4096, 0, 0, 0, 0, 0, 0)  # d_pad does not divide n/2
     assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL
