@@ -40,18 +40,22 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def per_item_work(kernel, n, L, g):
+def per_item_work(kernel, n, L, g, h):
     """Algorithmic modular multiply(-accumulate)s per work item of each kernel.
     One NTT = (n/2) log2 n butterflies; an inverse NTT adds n scalings."""
     bf = n // 2 * int(math.log2(n))
     if kernel == "ks_digits":
         return L * (bf + n)
-    if kernel == "ks_modup":
-        return L * L * bf + 2 * (bf + n) + 2 * L * (L + 1) * n
+    if kernel == "ks_extend":
+        return L * L * bf
+    if kernel == "ks_inner":
+        return 2 * L * (L + 1) * n
+    if kernel == "ks_pinv":
+        return 2 * (bf + n)
     if kernel == "ks_moddown":
         return 2 * L * bf + 2 * L * n
-    if kernel == "mac_init":
-        return 2 * g * L * n
+    if kernel == "mac":
+        return 2 * g * L * n * h
     return 0
 
 
@@ -188,8 +192,7 @@ def main():
     if timing:
         kstats = ctx.kernel_stats()
         ctx.kernel_timing(False)
-        work = {k: per_item_work(k, n, L, info.g) for k in kstats}
-        # the giant-step launches of moddown also fuse the plaintext sum
+        work = {k: per_item_work(k, n, L, info.g, info.h) for k in kstats}
         dom = max((k for k in kstats if work[k] > 0), key=lambda k: kstats[k][2])
         launches, items, total_ms = kstats[dom]
         avg_ms = total_ms / max(launches, 1)

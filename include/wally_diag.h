@@ -34,12 +34,14 @@ int wally_diag_rotate(wally_ctx* ctx, const uint64_t* in, const uint64_t* keys, 
  * wally_diag_kernel_stats waits for the recorded launches, sums the elapsed
  * times per kernel (index = WALLY_KERNEL_*) into out[0..n), and clears the
  * records. */
-#define WALLY_KERNEL_DIGITS 0   /* key switch: INTT of the digits           */
-#define WALLY_KERNEL_MODUP 1    /* key switch: extension + key inner product */
-#define WALLY_KERNEL_MODDOWN 2  /* key switch: division by P (+ giant sum)  */
-#define WALLY_KERNEL_MAC_INIT 3 /* first giant-step sum                     */
-#define WALLY_KERNEL_COPY 4     /* query copy into the baby-step buffer     */
-#define WALLY_KERNEL_COUNT 5
+#define WALLY_KERNEL_DIGITS 0   /* key switch: INTT of the digits            */
+#define WALLY_KERNEL_EXTEND 1   /* key switch: NTT of the extended digits    */
+#define WALLY_KERNEL_INNER 2    /* key switch: key inner product             */
+#define WALLY_KERNEL_PINV 3     /* key switch: INTT of the P part            */
+#define WALLY_KERNEL_MODDOWN 4  /* key switch: division by P (+ acc_i)       */
+#define WALLY_KERNEL_MAC 5      /* giant-step sums (plaintext products)      */
+#define WALLY_KERNEL_COPY 6     /* query copy into the baby-step buffer      */
+#define WALLY_KERNEL_COUNT 7
 
 typedef struct {
   uint64_t launches;

@@ -24,26 +24,26 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> Path:
+def build(verbose: bool = False, out: Path = LIB, extra=()) -> Path:
     """Compile every source (always: the caller asks for a fresh build)."""
     objs = []
-    tmpdir = HERE / "_build"
-    tmpdir.mkdir(exist_ok=True)
+    tmpdir = HERE / "_build" / ("default" if not extra else "_".join(x.strip("-").replace("=", "") for x in extra))
+    tmpdir.mkdir(parents=True, exist_ok=True)
     for src in SOURCES:
         obj = tmpdir / (src.name + ".o")
         lang = ["-x", "hip"] if src.suffix == ".hip" else ["-x", "hip"]
-        cmd = [HIPCC, *FLAGS, *lang, "-c", str(src), "-o", str(obj)]
+        cmd = [HIPCC, *FLAGS, *extra, *lang, "-c", str(src), "-o", str(obj)]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB.with_suffix(".so.tmp%d" % os.getpid())
+    tmp = out.with_suffix(".so.tmp%d" % os.getpid())
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *map(str, objs), "-o", str(tmp)]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

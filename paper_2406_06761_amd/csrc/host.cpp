@@ -20,6 +20,9 @@
 using namespace wally;
 typedef unsigned __int128 u128;
 
+// giant items per plaintext-sharing tile of the sum kernel
+static constexpr uint32_t kTileItems = 16;
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -91,11 +94,12 @@ struct WaveWork {
   // one workspace set: buffers for one wave of queries in flight
   uint64_t* ctp = nullptr;  // [B][g][2][L][n]
   uint64_t* X = nullptr;    // [B][L][n]
-  uint64_t* U = nullptr;    // [B][2][L][n]
+  uint64_t* U = nullptr;    // [B][2][L+1][n]
   uint64_t* Y = nullptr;    // [B][2][n]
   uint64_t* D = nullptr;    // [B][L+1][L][n]
   uint64_t* R0 = nullptr;   // [B][2][L][n]
   uint64_t* R1 = nullptr;
+  uint64_t* ACC = nullptr;  // [B][h][2][L][n] giant-step sums
   // descriptors: copy items, baby items, giant items
   CopyItem* copy_dev = nullptr;
   KsItem* baby_dev = nullptr;
@@ -103,6 +107,8 @@ struct WaveWork {
   CopyItem* copy_host = nullptr;
   KsItem* baby_host = nullptr;
   KsItem* giant_host = nullptr;
+  MacTile* tile_dev = nullptr;
+  MacTile* tile_host = nullptr;
   size_t giant_cap = 0;
   hipStream_t stream = nullptr;
   hipEvent_t staged = nullptr;  // host descriptors copied
@@ -244,7 +250,9 @@ hipError_t timed(wally_ctx* c, hipStream_t st, int kernel, uint64_t items, F fn)
 
 hipError_t keyswitch(wally_ctx* c, const KsItem* items, int n, const KsArgs& a, hipStream_t st) {
   hipError_t e = timed(c, st, WALLY_KERNEL_DIGITS, n, [&] { return launch_ks_digits(items, n, a, c->M, st); });
-  if (e == hipSuccess) e = timed(c, st, WALLY_KERNEL_MODUP, n, [&] { return launch_ks_modup(items, n, a, c->M, st); });
+  if (e == hipSuccess) e = timed(c, st, WALLY_KERNEL_EXTEND, n, [&] { return launch_ks_extend(items, n, a, c->M, st); });
+  if (e == hipSuccess) e = timed(c, st, WALLY_KERNEL_INNER, n, [&] { return launch_ks_inner(items, n, a, c->M, st); });
+  if (e == hipSuccess) e = timed(c, st, WALLY_KERNEL_PINV, n, [&] { return launch_ks_pinv(n, a, c->M, st); });
   if (e == hipSuccess)
     e = timed(c, st, WALLY_KERNEL_MODDOWN, n, [&] { return launch_ks_moddown(items, n, a, c->M, st); });
   return e;
@@ -260,6 +268,9 @@ void free_sets(wally_ctx* c) {
     dfree(c, s.D);
     dfree(c, s.R0);
     dfree(c, s.R1);
+    dfree(c, s.ACC);
+    dfree(c, s.tile_dev);
+    if (s.tile_host) (void)hipHostFree(s.tile_host);
     dfree(c, s.copy_dev);
     dfree(c, s.baby_dev);
     dfree(c, s.giant_dev);
@@ -286,11 +297,14 @@ int ensure_sets(wally_ctx* c) {
     int rc;
     if ((rc = dalloc(c, B * c->g * c->ctw() * w8, (void**)&s.ctp))) return rc;
     if ((rc = dalloc(c, B * c->L * c->n * w8, (void**)&s.X))) return rc;
-    if ((rc = dalloc(c, B * c->ctw() * w8, (void**)&s.U))) return rc;
+    if ((rc = dalloc(c, B * 2 * (c->L + 1) * c->n * w8, (void**)&s.U))) return rc;
     if ((rc = dalloc(c, B * 2 * c->n * w8, (void**)&s.Y))) return rc;
     if ((rc = dalloc(c, B * (c->L + 1) * c->L * c->n * w8, (void**)&s.D))) return rc;
     if ((rc = dalloc(c, B * c->ctw() * w8, (void**)&s.R0))) return rc;
     if ((rc = dalloc(c, B * c->ctw() * w8, (void**)&s.R1))) return rc;
+    if ((rc = dalloc(c, B * c->h * c->ctw() * w8, (void**)&s.ACC))) return rc;
+    if ((rc = dalloc(c, giant_cap * sizeof(MacTile), (void**)&s.tile_dev))) return rc;
+    HIP_OK(c, hipHostMalloc((void**)&s.tile_host, giant_cap * sizeof(MacTile), hipHostMallocDefault));
     if ((rc = dalloc(c, B * sizeof(CopyItem), (void**)&s.copy_dev))) return rc;
     if ((rc = dalloc(c, B * sizeof(KsItem), (void**)&s.baby_dev))) return rc;
     if ((rc = dalloc(c, giant_cap * sizeof(KsItem), (void**)&s.giant_dev))) return rc;
@@ -324,30 +338,54 @@ int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w)
   const uint64_t ctw = c->ctw(), ptw = c->ptw();
   // host descriptors may be rewritten only after the previous copy landed
   HIP_OK(c, hipEventSynchronize(s.staged));
-  size_t ng = 0;
+  // giant items (query, chunk), ordered by plaintext chunk so tiles share it
+  std::vector<std::pair<uint64_t, uint32_t>> order;  // (global chunk index, item)
+  std::vector<std::pair<int, uint32_t>> gq;           // (query slot, chunk)
   for (int k = 0; k < w; ++k) {
     const wally_query& q = *qs[k];
     uint64_t* ctp = s.ctp + (uint64_t)k * c->g * ctw;
     s.copy_host[k] = CopyItem{q.ct, ctp};
-    s.baby_host[k] = KsItem{q.key_baby, ctp, nullptr, nullptr, nullptr, nullptr};
+    s.baby_host[k] = KsItem{q.key_baby, ctp, nullptr, nullptr, nullptr, nullptr, nullptr};
     for (uint32_t ch = 0; ch < c->chunks[q.cluster]; ++ch) {
-      KsItem gi{};
-      gi.key = q.key_giant;
-      gi.fin = q.out + (uint64_t)ch * ctw;
-      gi.pt = c->pt + (c->chunk_base[q.cluster] + ch) * ptw;
-      gi.ctp = ctp;
-      s.giant_host[ng++] = gi;
+      order.push_back({c->chunk_base[q.cluster] + ch, (uint32_t)gq.size()});
+      gq.push_back({k, ch});
     }
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<uint64_t, uint32_t>& a, const std::pair<uint64_t, uint32_t>& b) {
+                     return a.first < b.first;
+                   });
+  const size_t ng = order.size();
+  // sub-waves of up to B giant items; slot = position inside the sub-wave
+  size_t nt = 0;
+  std::vector<std::pair<size_t, size_t>> sub_tiles;  // per sub-wave: [first tile, end tile)
+  for (size_t g0 = 0; g0 < ng; g0 += c->B) {
+    const size_t g1 = std::min(ng, g0 + (size_t)c->B);
+    const size_t t0 = nt;
+    for (size_t k = g0; k < g1; ++k) {
+      const auto& gi = gq[order[k].second];
+      const wally_query& q = *qs[gi.first];
+      const size_t slot = k - g0;
+      KsItem it{};
+      it.key = q.key_giant;
+      it.fin = q.out + (uint64_t)gi.second * ctw;
+      it.pt = c->pt + order[k].first * ptw;
+      it.ctp = s.ctp + (uint64_t)gi.first * c->g * ctw;
+      it.buf0 = s.R0 + slot * ctw;
+      it.buf1 = s.R1 + slot * ctw;
+      it.acc = c->h == 1 ? it.fin : s.ACC + slot * c->h * ctw;
+      s.giant_host[k] = it;
+      // tiles: runs of one plaintext chunk, at most kTileItems items, inside the sub-wave
+      const bool start = k == g0 || order[k].first != order[k - 1].first || s.tile_host[nt - 1].count >= kTileItems;
+      if (start) s.tile_host[nt++] = MacTile{(uint32_t)(k - g0), 0};
+      s.tile_host[nt - 1].count++;
+    }
+    sub_tiles.push_back({t0, nt});
   }
   HIP_OK(c, hipMemcpyAsync(s.copy_dev, s.copy_host, w * sizeof(CopyItem), hipMemcpyHostToDevice, s.stream));
   HIP_OK(c, hipMemcpyAsync(s.baby_dev, s.baby_host, w * sizeof(KsItem), hipMemcpyHostToDevice, s.stream));
-  // giant items: R ping-pong slots are assigned per sub-wave on the device copy
-  for (size_t k = 0; k < ng; ++k) {
-    const size_t slot = k % (size_t)c->B;
-    s.giant_host[k].buf0 = s.R0 + slot * ctw;
-    s.giant_host[k].buf1 = s.R1 + slot * ctw;
-  }
   HIP_OK(c, hipMemcpyAsync(s.giant_dev, s.giant_host, ng * sizeof(KsItem), hipMemcpyHostToDevice, s.stream));
+  HIP_OK(c, hipMemcpyAsync(s.tile_dev, s.tile_host, nt * sizeof(MacTile), hipMemcpyHostToDevice, s.stream));
   HIP_OK(c, hipEventRecord(s.staged, s.stream));
 
   // baby steps: ct'_0 = ct, ct'_j = Rot(ct'_{j-1}, 1)
@@ -361,23 +399,31 @@ int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w)
     a.out_off = (uint64_t)j * ctw;
     HIP_OK(c, keyswitch(c, s.baby_dev, w, a, s.stream));
   }
-  // giant steps per (query, chunk): R = acc_{h-1}; R = acc_i + Rot(R, g), i = h-2..0
-  for (size_t g0 = 0; g0 < ng; g0 += c->B) {
+  // giant steps per (query, chunk): acc_i for all i, then
+  // R = acc_{h-1}; R = acc_i + Rot(R, g) for i = h-2 .. 0
+  for (size_t sw = 0; sw < sub_tiles.size(); ++sw) {
+    const size_t g0 = sw * (size_t)c->B;
     const int cnt = (int)std::min<size_t>(c->B, ng - g0);
     const KsItem* items = s.giant_dev + g0;
+    const MacTile* tiles = s.tile_dev + sub_tiles[sw].first;
+    const int ntile = (int)(sub_tiles[sw].second - sub_tiles[sw].first);
     KsArgs a = base_args(c, s);
-    a.giant = c->h - 1;
-    a.out_sel = c->h == 1 ? 2 : 0;
-    HIP_OK(c, timed(c, s.stream, WALLY_KERNEL_MAC_INIT, cnt, [&] { return launch_mac_init(items, cnt, a, c->M, s.stream); }));
-    int cur = 0;
+    HIP_OK(c, timed(c, s.stream, WALLY_KERNEL_MAC, cnt,
+                    [&] { return launch_mac_tiles(items, tiles, ntile, a, c->h, c->M, s.stream); }));
+    int cur = 3;  // acc
+    uint64_t cur_off = (uint64_t)(c->h - 1) * ctw;
+    int next = 0;
     for (int i = c->h - 2; i >= 0; --i) {
       KsArgs b = base_args(c, s);
       b.gal = c->gal_giant;
       b.in_sel = cur;
-      b.out_sel = i == 0 ? 2 : 1 - cur;
+      b.in_off = cur_off;
+      b.out_sel = i == 0 ? 2 : next;
       b.giant = i;
       HIP_OK(c, keyswitch(c, items, cnt, b, s.stream));
-      cur = 1 - cur;
+      cur = next;
+      cur_off = 0;
+      next = 1 - next;
     }
   }
   HIP_OK(c, hipEventRecord(s.done, s.stream));
@@ -811,7 +857,7 @@ int wally_diag_rotate(wally_ctx* c, const uint64_t* in, const uint64_t* keys, ui
     HIP_OK(c, hipStreamSynchronize(s.stream));
     for (int k = 0; k < w; ++k)
       s.baby_host[k] = KsItem{keys + (i0 + k) * c->keyw(), const_cast<uint64_t*>(in) + (i0 + k) * ctw,
-                              out + (i0 + k) * ctw, nullptr, nullptr, nullptr};
+                              out + (i0 + k) * ctw, nullptr, nullptr, nullptr, nullptr};
     HIP_OK(c, hipMemcpyAsync(s.baby_dev, s.baby_host, w * sizeof(KsItem), hipMemcpyHostToDevice, st));
     KsArgs a = base_args(c, s);
     a.gal = which ? c->gal_giant : c->gal_baby;

@@ -34,6 +34,12 @@ struct KsItem {
   uint64_t* fin;
   const uint64_t* pt;    // plaintexts of the chunk [d_pad][L][n] (giant steps)
   const uint64_t* ctp;   // rotated query copies [g][2][L][n] (giant steps)
+  uint64_t* acc;         // giant-step sums [h][2][L][n] (giant steps); sel 3 reads it
+};
+
+// A tile of giant items that share one plaintext chunk (consecutive items).
+struct MacTile {
+  uint32_t first, count;
 };
 
 struct KsArgs {
@@ -44,7 +50,7 @@ struct KsArgs {
   int giant;   // giant-step index i to fuse acc_i, or -1
   int g;
   uint64_t* X;  // scratch [items][L][n]
-  uint64_t* U;  // scratch [items][2][L][n]
+  uint64_t* U;  // scratch [items][2][L+1][n]: key inner products (m = L: the P part)
   uint64_t* Y;  // scratch [items][2][n]
   uint64_t* D;  // scratch [items][L+1][L][n]: extended digits
 };
@@ -66,11 +72,15 @@ struct EncodeArgs {
   const uint32_t* slot_of;  // NTT index -> slot
 };
 
-// the three key-switching kernels (launch order: digits, modup, moddown)
+// the key-switching kernels, in launch order
 hipError_t launch_ks_digits(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
-hipError_t launch_ks_modup(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
+hipError_t launch_ks_extend(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
+hipError_t launch_ks_inner(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
+hipError_t launch_ks_pinv(int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
 hipError_t launch_ks_moddown(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
-hipError_t launch_mac_init(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
+// acc_i = sum_{j<g} PT[g i + j] * ct'_j for every giant index i of every item
+hipError_t launch_mac_tiles(const KsItem* items, const MacTile* tiles, int n_tiles, const KsArgs& a, int h,
+                            const DevModuli& M, hipStream_t st);
 hipError_t launch_copy_ct(const CopyItem* items, int n_items, uint64_t words, hipStream_t st);
 hipError_t launch_encode(const EncodeJob* jobs, int n_jobs, const EncodeArgs& a, const DevModuli& M, hipStream_t st);
 hipError_t launch_ntt_rows(uint64_t* data, int rows, int log_n, int mi, int inverse, const DevModuli& M,

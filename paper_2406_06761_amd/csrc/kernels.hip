@@ -7,21 +7,30 @@
 //
 // Key switching for CtRotate (paper §2.1) follows the hybrid RNS method of
 // paper §7.1 with one digit per ciphertext limb and one special prime P:
-//   ks_digits : x_i = INTT_{q_i}(sigma(c1)_i)                    (L per item)
-//   ks_modup  : u_t[m] = sum_i NTT_m(x_i mod m) * key[i][t][m]     (L+1 per item)
-//               for m = P also y_t = INTT_P(u_t[P])
+//   ks_digits : x_i = INTT_{q_i}(sigma(c1)_i)                      (L per item)
+//   ks_extend : D[m][i] = NTT_m(x_i mod m), m in {q_0..q_{L-1}, P}   (L(L+1) per item)
+//   ks_inner  : u_t[m] = sum_i D[m][i] * key[i][t][m]               (elementwise)
+//   ks_pinv   : y_t = INTT_P(u_t[P])                                (2 per item)
 //   ks_moddown: out_t[j] = (u_t[j] - NTT_j([y_t]_centred mod q_j)) * P^-1
-//               (+ sigma(c0)_j for t = 0) (+ the giant-step sum)    (L per item)
-// The giant-step sum acc_i = sum_j PT[g i + j] * ct'_j (Server Computation
-// algorithm, paper §5) is fused into ks_moddown, so one Horner step
-// R <- acc_i + Rot(R, g) is three launches.
+//               (+ sigma(c0)_j for t = 0) (+ acc_i)                (2L per item)
+// Each transform kernel does one NTT per workgroup with natural-order global
+// I/O, so the compute-bound transforms stay light on registers and the
+// memory-bound inner product runs at full occupancy.  The giant-step sums
+// acc_i = sum_j PT[g i + j] * ct'_j (Server Computation algorithm, paper §5)
+// are computed for all i by one tiled kernel; a Horner step
+// R <- acc_i + Rot(R, g) adds acc_i inside ks_moddown.
 #include "kernels.h"
 #include "ntt.h"
+
+// elements per thread (2^WALLY_KS_LOGE) of the key-switching transforms
+#ifndef WALLY_KS_LOGE
+#define WALLY_KS_LOGE 4
+#endif
 
 namespace wally {
 
 __device__ __forceinline__ const uint64_t* sel_in(const KsItem& it, int sel, uint64_t off) {
-  return sel == 0 ? it.buf0 + off : (sel == 1 ? it.buf1 + off : it.fin + off);
+  return sel == 0 ? it.buf0 + off : (sel == 1 ? it.buf1 + off : (sel == 2 ? it.fin + off : it.acc + off));
 }
 __device__ __forceinline__ uint64_t* sel_out(const KsItem& it, int sel, uint64_t off) {
   return sel == 0 ? it.buf0 + off : (sel == 1 ? it.buf1 + off : it.fin + off);
@@ -30,178 +39,192 @@ __device__ __forceinline__ uint64_t* sel_out(const KsItem& it, int sel, uint64_t
 // ---------------------------------------------------------------------------
 // key switching, step 1: digits
 // grid (items, L); block T
-template <int LOGN>
-__global__ __launch_bounds__(NttShape<LOGN>::T) void k_ks_digits(const KsItem* __restrict__ items, KsArgs a,
-                                                                 DevModuli M) {
-  using S = NttShape<LOGN>;
+template <int LOGN, int LOGE>
+__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_digits(const KsItem* __restrict__ items, KsArgs a,
+                                                                         DevModuli M) {
+  using S = NttShape<LOGN, LOGE>;
+  using FM = FirstMap<LOGN, LOGE>;
   __shared__ uint64_t lds[S::LDS_WORDS];
   const int tid = threadIdx.x;
   const int b = blockIdx.x, i = blockIdx.y;
   const KsItem it = items[b];
   const uint64_t* c1 = sel_in(it, a.in_sel, a.in_off) + ((uint64_t)a.L + i) * S::N;
   const uint64_t q = M.q[i];
-  uint64_t x[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) x[e] = c1[galois_src<LOGN>(LastMap<LOGN>::idx(tid, e), a.gal)];
-  ntt_inv<LOGN>(x, lds, M.inv[i], q, tid);
+  uint64_t x[S::E];
+  gather_galois<LOGN, LOGE, LastMap<LOGN, LOGE>>(x, c1, lds, a.gal, tid);  // sigma(c1)_i, INTT input order
+  ntt_inv<LOGN, LOGE>(x, lds, M.inv[i], q, tid);
   uint64_t* X = a.X + ((uint64_t)b * a.L + i) * S::N;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) X[FirstMap<LOGN>::idx(tid, e)] = csub(shoup(x[e], M.ninv[i], M.ninvp[i], q), q);
+  for (int e = 0; e < S::E; ++e) X[FM::idx(tid, e)] = csub(shoup(x[e], M.ninv[i], M.ninvp[i], q), q);
 }
 
 // ---------------------------------------------------------------------------
-// key switching, step 2: extension to every modulus and key inner product
-// grid (items, L+1); block T
-template <int LOGN>
-__global__ __launch_bounds__(NttShape<LOGN>::T) void k_ks_modup(const KsItem* __restrict__ items, KsArgs a,
-                                                                DevModuli M) {
-  using S = NttShape<LOGN>;
+// key switching, step 2: extended digits D[m][i] = NTT_m(x_i mod m); for
+// i = m the extended digit is sigma(c1)_m itself (a permuted copy).
+// grid (items, (L+1) * L), blockIdx.y = m * L + i; block T
+template <int LOGN, int LOGE>
+__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const KsItem* __restrict__ items, KsArgs a,
+                                                                         DevModuli M) {
+  using S = NttShape<LOGN, LOGE>;
+  using FM = FirstMap<LOGN, LOGE>;
   __shared__ uint64_t lds[S::LDS_WORDS];
   const int tid = threadIdx.x;
-  const int b = blockIdx.x, m = blockIdx.y;
-  const int L = a.L, MM = a.L + 1;
-  const KsItem it = items[b];
-  const uint64_t* c1 = sel_in(it, a.in_sel, a.in_off) + (uint64_t)L * S::N;
-  const uint64_t q = M.q[m], q2 = 2 * q;
-  // extended digits NTT_m(x_i mod m), i != m; each thread later reads back
-  // only the words it wrote, so no barrier is needed between the phases
-  uint64_t* D = a.D + ((uint64_t)b * MM + m) * L * S::N;
-  for (int i = 0; i < L; ++i) {
-    if (i == m) continue;
-    const uint64_t* X = a.X + ((uint64_t)b * L + i) * S::N;
-    uint64_t d[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) d[e] = X[FirstMap<LOGN>::idx(tid, e)];  // < q_i < 2 q_m
-    ntt_fwd<LOGN>(d, lds, M.fwd[m], q, tid);
-#pragma unroll
-    for (int e = 0; e < 16; ++e) D[(uint64_t)i * S::N + LastMap<LOGN>::idx(tid, e)] = reduce4(d[e], q, q2);
-  }
-  // key inner product, 128-bit lazy accumulation per element
-  const ModConst mc = M.mc[m];
-  uint64_t u0[16], u1[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const uint32_t p = LastMap<LOGN>::idx(tid, e);
-    u128w acc0{0, 0}, acc1{0, 0};
-    for (int i = 0; i < L; ++i) {
-      const uint64_t d = (i == m) ? c1[(uint64_t)i * S::N + galois_src<LOGN>(p, a.gal)] : D[(uint64_t)i * S::N + p];
-      mac128(acc0, d, it.key[(((uint64_t)i * 2 + 0) * MM + m) * S::N + p]);
-      mac128(acc1, d, it.key[(((uint64_t)i * 2 + 1) * MM + m) * S::N + p]);
-    }
-    u0[e] = reduce128(acc0, q, mc.r64, mc.r64p, mc.onep);
-    u1[e] = reduce128(acc1, q, mc.r64, mc.r64p, mc.onep);
-  }
-  if (m < L) {
-    uint64_t* U0 = a.U + (((uint64_t)b * 2 + 0) * L + m) * S::N;
-    uint64_t* U1 = a.U + (((uint64_t)b * 2 + 1) * L + m) * S::N;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const uint32_t p = LastMap<LOGN>::idx(tid, e);
-      U0[p] = u0[e];
-      U1[p] = u1[e];
-    }
-  } else {
-    // the P part back to coefficients, kept in [0, P); centred by the consumer
-    ntt_inv<LOGN>(u0, lds, M.inv[m], q, tid);
-    ntt_inv<LOGN>(u1, lds, M.inv[m], q, tid);
-    uint64_t* Y0 = a.Y + ((uint64_t)b * 2 + 0) * S::N;
-    uint64_t* Y1 = a.Y + ((uint64_t)b * 2 + 1) * S::N;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const uint32_t p = FirstMap<LOGN>::idx(tid, e);
-      Y0[p] = csub(shoup(u0[e], M.ninv[m], M.ninvp[m], q), q);
-      Y1[p] = csub(shoup(u1[e], M.ninv[m], M.ninvp[m], q), q);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// key switching, step 3: division by P, sigma(c0), optional giant-step sum
-// grid (items, L); block T
-template <int LOGN>
-__global__ __launch_bounds__(NttShape<LOGN>::T) void k_ks_moddown(const KsItem* __restrict__ items, KsArgs a,
-                                                                  DevModuli M) {
-  using S = NttShape<LOGN>;
-  __shared__ uint64_t lds[S::LDS_WORDS];
-  const int tid = threadIdx.x;
-  const int b = blockIdx.x, j = blockIdx.y;
+  const int b = blockIdx.x, m = blockIdx.y / a.L, i = blockIdx.y % a.L;
   const int L = a.L;
-  const KsItem it = items[b];
-  const uint64_t* c0 = sel_in(it, a.in_sel, a.in_off) + (uint64_t)j * S::N;
-  const uint64_t q = M.q[j], q2 = 2 * q;
+  uint64_t* D = a.D + (((uint64_t)b * (L + 1) + m) * L + i) * S::N;
+  uint64_t d[S::E];
+  if (i == m) {
+    const KsItem it = items[b];
+    gather_galois<LOGN, LOGE, FM>(d, sel_in(it, a.in_sel, a.in_off) + ((uint64_t)L + m) * S::N, lds, a.gal, tid);
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) D[FM::idx(tid, e)] = d[e];
+    return;
+  }
+  const uint64_t q = M.q[m];
+  const uint64_t* X = a.X + ((uint64_t)b * L + i) * S::N;
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) d[e] = X[FM::idx(tid, e)];  // < q_i < 2 q_m: a valid lazy input
+  ntt_fwd_nat<LOGN, LOGE>(d, lds, M.fwd[m], q, tid);
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) D[FM::idx(tid, e)] = reduce4(d[e], q, 2 * q);
+}
+
+// ---------------------------------------------------------------------------
+// key switching, step 3: key inner product u_t[m] = sum_i D[m][i] * key[i][t][m]
+// with one 128-bit lazy sum per output word (elementwise, memory bound).
+// grid (n / 256, L+1, items); block 256
+__global__ __launch_bounds__(256) void k_ks_inner(const KsItem* __restrict__ items, KsArgs a, DevModuli M) {
+  const int m = blockIdx.y, b = blockIdx.z;
+  const int L = a.L, MM = a.L + 1;
+  const uint64_t n = 1ull << a.log_n;
+  const uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t* key = items[b].key;
+  const uint64_t* D = a.D + ((uint64_t)b * MM + m) * L * n + p;
+  const ModConst mc = M.mc[m];
+  u128w acc0{0, 0}, acc1{0, 0};
+  for (int i = 0; i < L; ++i) {
+    const uint64_t d = D[(uint64_t)i * n];
+    mac128(acc0, d, key[(((uint64_t)i * 2 + 0) * MM + m) * n + p]);
+    mac128(acc1, d, key[(((uint64_t)i * 2 + 1) * MM + m) * n + p]);
+  }
+  uint64_t* U = a.U + ((uint64_t)b * 2 * MM + m) * n + p;  // U[b][t][m], m = L is the P part
+  U[0] = reduce128(acc0, mc.q, mc.r64, mc.r64p, mc.onep);
+  U[(uint64_t)MM * n] = reduce128(acc1, mc.q, mc.r64, mc.r64p, mc.onep);
+}
+
+// ---------------------------------------------------------------------------
+// key switching, step 4: y_t = INTT_P(u_t[P]), kept in [0, P) (centred by
+// the consumer).  grid (items, 2); block T
+template <int LOGN, int LOGE>
+__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_pinv(KsArgs a, DevModuli M) {
+  using S = NttShape<LOGN, LOGE>;
+  using FM = FirstMap<LOGN, LOGE>;
+  __shared__ uint64_t lds[S::LDS_WORDS];
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x, t = blockIdx.y;
+  const int L = a.L, MM = a.L + 1;
+  const uint64_t P = M.q[L];
+  const uint64_t* U = a.U + (((uint64_t)b * 2 + t) * MM + L) * S::N;
+  uint64_t y[S::E];
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) y[e] = U[FM::idx(tid, e)];
+  ntt_inv_nat<LOGN, LOGE>(y, lds, M.inv[L], P, tid);
+  uint64_t* Y = a.Y + ((uint64_t)b * 2 + t) * S::N;
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) Y[FM::idx(tid, e)] = csub(shoup(y[e], M.ninv[L], M.ninvp[L], P), P);
+}
+
+// ---------------------------------------------------------------------------
+// key switching, step 5: division by P and the rest of CtRotate:
+//   out_t[j] = (u_t[j] - NTT_j([y_t]_centred mod q_j)) * P^-1
+//              (+ sigma(c0)_j for t = 0) (+ acc_i in a Horner step)
+// grid (items, L, 2); block T
+template <int LOGN, int LOGE>
+__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_waves_per_eu(4))) void k_ks_moddown(const KsItem* __restrict__ items, KsArgs a,
+                                                                          DevModuli M) {
+  using S = NttShape<LOGN, LOGE>;
+  using FM = FirstMap<LOGN, LOGE>;
+  __shared__ uint64_t lds[S::LDS_WORDS];
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x, j = blockIdx.y, t = blockIdx.z;
+  const int L = a.L, MM = a.L + 1;
+  const uint64_t q = M.q[j];
   const uint64_t P = M.q[L];
   const uint64_t halfP = (P - 1) / 2;
-  uint64_t res[2][16];
-  for (int t = 0; t < 2; ++t) {
-    const uint64_t* Y = a.Y + ((uint64_t)b * 2 + t) * S::N;
-    uint64_t z[16];
+  const uint64_t* Y = a.Y + ((uint64_t)b * 2 + t) * S::N;
+  uint64_t z[S::E];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const uint64_t y = Y[FirstMap<LOGN>::idx(tid, e)];
-      z[e] = y > halfP ? y + (q - P) : y;  // centred lift, then mod q_j (P < q_j)
-    }
-    ntt_fwd<LOGN>(z, lds, M.fwd[j], q, tid);
-    const uint64_t* U = a.U + (((uint64_t)b * 2 + t) * L + j) * S::N;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const uint32_t p = LastMap<LOGN>::idx(tid, e);
-      const uint64_t v = submod(U[p], reduce4(z[e], q, q2), q);
-      uint64_t r = csub(shoup(v, M.pinv[j], M.pinvp[j], q), q);
-      if (t == 0) r = addmod(r, c0[galois_src<LOGN>(p, a.gal)], q);
-      res[t][e] = r;
-    }
+  for (int e = 0; e < S::E; ++e) {
+    const uint64_t y = Y[FM::idx(tid, e)];
+    z[e] = y > halfP ? y + (q - P) : y;  // centred lift, then mod q_j (P < q_j)
   }
-  if (a.giant >= 0) {
-    // acc_i = sum_{jj < g} PT[g i + jj] * ct'_jj, for both polynomials
-    const ModConst mc = M.mc[j];
-    const uint64_t ctw = 2ull * L * S::N;
-    const uint64_t* pt = it.pt + ((uint64_t)a.g * a.giant * L + j) * S::N;
-    const uint64_t* cp = it.ctp + (uint64_t)j * S::N;
+  ntt_fwd_nat<LOGN, LOGE>(z, lds, M.fwd[j], q, tid);
+  const KsItem it = items[b];
+  const uint64_t* U = a.U + (((uint64_t)b * 2 + t) * MM + j) * S::N;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const uint32_t p = LastMap<LOGN>::idx(tid, e);
-      u128w s0{0, 0}, s1{0, 0};
-      for (int jj = 0; jj < a.g; ++jj) {
-        const uint64_t w = pt[(uint64_t)jj * L * S::N + p];
-        mac128(s0, w, cp[jj * ctw + p]);
-        mac128(s1, w, cp[jj * ctw + (uint64_t)L * S::N + p]);
-      }
-      res[0][e] = addmod(res[0][e], reduce128(s0, q, mc.r64, mc.r64p, mc.onep), q);
-      res[1][e] = addmod(res[1][e], reduce128(s1, q, mc.r64, mc.r64p, mc.onep), q);
-    }
+  for (int e = 0; e < S::E; ++e) {
+    const uint64_t v = submod(U[FM::idx(tid, e)], reduce4(z[e], q, 2 * q), q);
+    z[e] = csub(shoup(v, M.pinv[j], M.pinvp[j], q), q);
   }
-  uint64_t* out = sel_out(it, a.out_sel, a.out_off) + (uint64_t)j * S::N;
+  if (t == 0) {
+    uint64_t c0s[S::E];
+    gather_galois<LOGN, LOGE, FM>(c0s, sel_in(it, a.in_sel, a.in_off) + (uint64_t)j * S::N, lds, a.gal, tid);
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const uint32_t p = LastMap<LOGN>::idx(tid, e);
-    out[p] = res[0][e];
-    out[(uint64_t)L * S::N + p] = res[1][e];
+    for (int e = 0; e < S::E; ++e) z[e] = addmod(z[e], c0s[e], q);
   }
+  const uint64_t toff = ((uint64_t)t * L + j) * S::N;
+  if (a.giant >= 0) {  // Horner step: + acc_i
+    const uint64_t* acc = it.acc + (uint64_t)a.giant * 2 * L * S::N + toff;
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) z[e] = addmod(z[e], acc[FM::idx(tid, e)], q);
+  }
+  uint64_t* out = sel_out(it, a.out_sel, a.out_off) + toff;
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) out[FM::idx(tid, e)] = z[e];
 }
 
 // ---------------------------------------------------------------------------
-// first giant-step accumulator R = acc_{h-1} (no rotation), elementwise
-// grid (items, L); block 256
-__global__ __launch_bounds__(256) void k_mac_init(const KsItem* __restrict__ items, KsArgs a, DevModuli M) {
-  const int b = blockIdx.x, j = blockIdx.y;
+// giant-step sums (Server Computation algorithm, paper §5: for each giant
+// step i, the g products of a plaintext with a rotated query copy, summed):
+//   acc_i[t][l][x] = sum_{j<g} PT[g i + j][l][x] * ct'_j[t][l][x]  for all i < h.
+// Per coefficient this is a (queries x g) by (g x h) product over Z_q; the
+// items of a tile share one plaintext chunk, so PT is read once per tile while
+// each item's g rotated copies are read once into registers.  Sums of g
+// products (< g 2^108) are kept in 128 bits and reduced once.
+// grid (n / 64, L, tiles); block 256 = 64 coefficients x 4 item lanes
+template <int G>
+__global__ __launch_bounds__(256) void k_mac_tiles(const KsItem* __restrict__ items, const MacTile* __restrict__ tiles,
+                                                   KsArgs a, int h, DevModuli M) {
+  const MacTile tl = tiles[blockIdx.z];
+  const int j = blockIdx.y;
   const int L = a.L;
   const uint64_t n = 1ull << a.log_n;
-  const KsItem it = items[b];
+  const uint64_t x = (uint64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int lane = threadIdx.x >> 6;
   const ModConst mc = M.mc[j];
   const uint64_t q = mc.q;
   const uint64_t ctw = 2ull * L * n;
-  const uint64_t* pt = it.pt + ((uint64_t)a.g * a.giant * L + j) * n;
-  const uint64_t* cp = it.ctp + (uint64_t)j * n;
-  uint64_t* out = sel_out(it, a.out_sel, a.out_off) + (uint64_t)j * n;
-  for (uint64_t p = threadIdx.x; p < n; p += blockDim.x) {
-    u128w s0{0, 0}, s1{0, 0};
-    for (int jj = 0; jj < a.g; ++jj) {
-      const uint64_t w = pt[(uint64_t)jj * L * n + p];
-      mac128(s0, w, cp[jj * ctw + p]);
-      mac128(s1, w, cp[jj * ctw + (uint64_t)L * n + p]);
+  const uint64_t* pt = items[tl.first].pt + (uint64_t)j * n + x;  // PT[m][j][x] at m * L * n
+  for (uint32_t k = lane; k < tl.count; k += 4) {
+    const KsItem it = items[tl.first + k];
+    uint64_t c0[G], c1[G];
+#pragma unroll
+    for (int jj = 0; jj < G; ++jj) {
+      c0[jj] = it.ctp[jj * ctw + (uint64_t)j * n + x];
+      c1[jj] = it.ctp[jj * ctw + ((uint64_t)L + j) * n + x];
     }
-    out[p] = reduce128(s0, q, mc.r64, mc.r64p, mc.onep);
-    out[(uint64_t)L * n + p] = reduce128(s1, q, mc.r64, mc.r64p, mc.onep);
+    for (int i = 0; i < h; ++i) {
+      u128w s0{0, 0}, s1{0, 0};
+#pragma unroll
+      for (int jj = 0; jj < G; ++jj) {
+        const uint64_t w = pt[(uint64_t)(G * i + jj) * L * n];
+        mac128(s0, w, c0[jj]);
+        mac128(s1, w, c1[jj]);
+      }
+      uint64_t* acc = it.acc + (uint64_t)i * ctw + (uint64_t)j * n + x;
+      acc[0] = reduce128(s0, q, mc.r64, mc.r64p, mc.onep);
+      acc[(uint64_t)L * n] = reduce128(s1, q, mc.r64, mc.r64p, mc.onep);
+    }
   }
 }
 
@@ -224,9 +247,9 @@ __global__ __launch_bounds__(256) void k_copy_ct(const CopyItem* __restrict__ it
 //   NTT index holding it); centred lift; NTT in every ciphertext limb.
 // grid (jobs, d_pad); block T
 template <int LOGN>
-__global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode(const EncodeJob* __restrict__ jobs, EncodeArgs a,
-                                                              DevModuli M) {
-  using S = NttShape<LOGN>;
+__global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_encode(const EncodeJob* __restrict__ jobs, EncodeArgs a,
+                                                                 DevModuli M) {
+  using S = NttShape<LOGN, 4>;
   __shared__ uint64_t lds[S::LDS_WORDS];
   const int tid = threadIdx.x;
   const EncodeJob jb = jobs[blockIdx.x];
@@ -239,7 +262,7 @@ __global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode(const EncodeJob* _
   uint64_t x[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
-    const uint32_t pos = LastMap<LOGN>::idx(tid, e);
+    const uint32_t pos = LastMap<LOGN, 4>::idx(tid, e);
     const uint32_t s = a.slot_of[pos];  // slot whose value sits at NTT index pos
     const uint32_t row = s / half, c = s % half;
     const uint32_t s2 = row * half + (c + half - rot) % half;  // pre-rotation (right by g*i)
@@ -249,7 +272,7 @@ __global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode(const EncodeJob* _
     if (entry < jb.n_entries && coord < d) v = jb.emb[entry * d + coord];
     x[e] = v < 0 ? (uint64_t)((int64_t)t + v) : (uint64_t)v;
   }
-  ntt_inv<LOGN>(x, lds, M.inv[it], t, tid);
+  ntt_inv<LOGN, 4>(x, lds, M.inv[it], t, tid);
   int64_t cc[16];
   const uint64_t halft = (t - 1) / 2;
 #pragma unroll
@@ -261,18 +284,18 @@ __global__ __launch_bounds__(NttShape<LOGN>::T) void k_encode(const EncodeJob* _
     const uint64_t q = M.q[l];
 #pragma unroll
     for (int e = 0; e < 16; ++e) x[e] = cc[e] < 0 ? (uint64_t)((int64_t)q + cc[e]) : (uint64_t)cc[e];
-    ntt_fwd<LOGN>(x, lds, M.fwd[l], q, tid);
+    ntt_fwd_nat<LOGN, 4>(x, lds, M.fwd[l], q, tid);
     uint64_t* out = jb.out + ((uint64_t)m * a.L + l) * S::N;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) out[LastMap<LOGN>::idx(tid, e)] = reduce4(x[e], q, 2 * q);
+    for (int e = 0; e < 16; ++e) out[FirstMap<LOGN, 4>::idx(tid, e)] = reduce4(x[e], q, 2 * q);
   }
 }
 
 // ---------------------------------------------------------------------------
 // diagnostics: in-place NTT / INTT of rows (canonical order) mod modulus `mi`
 template <int LOGN>
-__global__ __launch_bounds__(NttShape<LOGN>::T) void k_ntt_rows(uint64_t* data, int mi, int inverse, DevModuli M) {
-  using S = NttShape<LOGN>;
+__global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_ntt_rows(uint64_t* data, int mi, int inverse, DevModuli M) {
+  using S = NttShape<LOGN, 4>;
   __shared__ uint64_t lds[S::LDS_WORDS];
   const int tid = threadIdx.x;
   uint64_t* row = data + (uint64_t)blockIdx.x * S::N;
@@ -280,50 +303,71 @@ __global__ __launch_bounds__(NttShape<LOGN>::T) void k_ntt_rows(uint64_t* data, 
   uint64_t x[16];
   if (!inverse) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) x[e] = row[FirstMap<LOGN>::idx(tid, e)];
-    ntt_fwd<LOGN>(x, lds, M.fwd[mi], q, tid);
+    for (int e = 0; e < 16; ++e) x[e] = row[FirstMap<LOGN, 4>::idx(tid, e)];
+    ntt_fwd_nat<LOGN, 4>(x, lds, M.fwd[mi], q, tid);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) row[LastMap<LOGN>::idx(tid, e)] = reduce4(x[e], q, 2 * q);
+    for (int e = 0; e < 16; ++e) row[FirstMap<LOGN, 4>::idx(tid, e)] = reduce4(x[e], q, 2 * q);
   } else {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) x[e] = row[LastMap<LOGN>::idx(tid, e)];
-    ntt_inv<LOGN>(x, lds, M.inv[mi], q, tid);
+    for (int e = 0; e < 16; ++e) x[e] = row[FirstMap<LOGN, 4>::idx(tid, e)];
+    ntt_inv_nat<LOGN, 4>(x, lds, M.inv[mi], q, tid);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) row[FirstMap<LOGN>::idx(tid, e)] = csub(shoup(x[e], M.ninv[mi], M.ninvp[mi], q), q);
+    for (int e = 0; e < 16; ++e) row[FirstMap<LOGN, 4>::idx(tid, e)] = csub(shoup(x[e], M.ninv[mi], M.ninvp[mi], q), q);
   }
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 
-#define WALLY_DISPATCH_LOGN(KERNEL, GRID, ...)                                                     \
-  switch (a.log_n) {                                                                               \
-    case 12: hipLaunchKernelGGL(KERNEL<12>, GRID, dim3(NttShape<12>::T), 0, st, __VA_ARGS__); break; \
-    case 13: hipLaunchKernelGGL(KERNEL<13>, GRID, dim3(NttShape<13>::T), 0, st, __VA_ARGS__); break; \
-    default: return hipErrorInvalidValue;                                                          \
+// KERNEL<LOGN, LOGE> with T = n / 2^LOGE threads
+#define WALLY_DISPATCH_LOGN(KERNEL, LOGE, GRID, ...)                                                            \
+  switch (a.log_n) {                                                                                          \
+    case 12: hipLaunchKernelGGL((KERNEL<12, LOGE>), GRID, dim3(NttShape<12, LOGE>::T), 0, st, __VA_ARGS__); break; \
+    case 13: hipLaunchKernelGGL((KERNEL<13, LOGE>), GRID, dim3(NttShape<13, LOGE>::T), 0, st, __VA_ARGS__); break; \
+    default: return hipErrorInvalidValue;                                                                     \
   }
 
 hipError_t launch_ks_digits(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  WALLY_DISPATCH_LOGN(k_ks_digits, dim3(n_items, a.L), items, a, M);
+  WALLY_DISPATCH_LOGN(k_ks_digits, WALLY_KS_LOGE, dim3(n_items, a.L), items, a, M);
   return hipGetLastError();
 }
 
-hipError_t launch_ks_modup(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
+hipError_t launch_ks_extend(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  WALLY_DISPATCH_LOGN(k_ks_modup, dim3(n_items, a.L + 1), items, a, M);
+  WALLY_DISPATCH_LOGN(k_ks_extend, WALLY_KS_LOGE, dim3(n_items, (a.L + 1) * a.L), items, a, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_ks_inner(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ks_inner, dim3((1u << a.log_n) / 256, a.L + 1, n_items), dim3(256), 0, st, items, a, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_ks_pinv(int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  WALLY_DISPATCH_LOGN(k_ks_pinv, WALLY_KS_LOGE, dim3(n_items, 2), a, M);
   return hipGetLastError();
 }
 
 hipError_t launch_ks_moddown(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  WALLY_DISPATCH_LOGN(k_ks_moddown, dim3(n_items, a.L), items, a, M);
+  WALLY_DISPATCH_LOGN(k_ks_moddown, WALLY_KS_LOGE, dim3(n_items, a.L, 2), items, a, M);
   return hipGetLastError();
 }
 
-hipError_t launch_mac_init(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
-  if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mac_init, dim3(n_items, a.L), dim3(256), 0, st, items, a, M);
+hipError_t launch_mac_tiles(const KsItem* items, const MacTile* tiles, int n_tiles, const KsArgs& a, int h,
+                            const DevModuli& M, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  const dim3 grid((1u << a.log_n) / 64, a.L, n_tiles);
+  switch (a.g) {
+    case 4: hipLaunchKernelGGL(k_mac_tiles<4>, grid, dim3(256), 0, st, items, tiles, a, h, M); break;
+    case 8: hipLaunchKernelGGL(k_mac_tiles<8>, grid, dim3(256), 0, st, items, tiles, a, h, M); break;
+    case 16: hipLaunchKernelGGL(k_mac_tiles<16>, grid, dim3(256), 0, st, items, tiles, a, h, M); break;
+    case 32: hipLaunchKernelGGL(k_mac_tiles<32>, grid, dim3(256), 0, st, items, tiles, a, h, M); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -337,10 +381,10 @@ hipError_t launch_encode(const EncodeJob* jobs, int n_jobs, const EncodeArgs& a,
   if (n_jobs <= 0) return hipSuccess;
   switch (a.log_n) {
     case 12:
-      hipLaunchKernelGGL(k_encode<12>, dim3(n_jobs, a.d_pad), dim3(NttShape<12>::T), 0, st, jobs, a, M);
+      hipLaunchKernelGGL(k_encode<12>, dim3(n_jobs, a.d_pad), dim3(NttShape<12, 4>::T), 0, st, jobs, a, M);
       break;
     case 13:
-      hipLaunchKernelGGL(k_encode<13>, dim3(n_jobs, a.d_pad), dim3(NttShape<13>::T), 0, st, jobs, a, M);
+      hipLaunchKernelGGL(k_encode<13>, dim3(n_jobs, a.d_pad), dim3(NttShape<13, 4>::T), 0, st, jobs, a, M);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -351,8 +395,8 @@ hipError_t launch_ntt_rows(uint64_t* data, int rows, int log_n, int mi, int inve
                            hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   switch (log_n) {
-    case 12: hipLaunchKernelGGL(k_ntt_rows<12>, dim3(rows), dim3(NttShape<12>::T), 0, st, data, mi, inverse, M); break;
-    case 13: hipLaunchKernelGGL(k_ntt_rows<13>, dim3(rows), dim3(NttShape<13>::T), 0, st, data, mi, inverse, M); break;
+    case 12: hipLaunchKernelGGL(k_ntt_rows<12>, dim3(rows), dim3(NttShape<12, 4>::T), 0, st, data, mi, inverse, M); break;
+    case 13: hipLaunchKernelGGL(k_ntt_rows<13>, dim3(rows), dim3(NttShape<13, 4>::T), 0, st, data, mi, inverse, M); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -8,40 +8,39 @@
 // twiddle products use Shoup's precomputed quotient.  The inverse runs the
 // Gentleman-Sande butterflies of the same stages in reverse order.
 //
-// Layout on gfx950: T = n/16 threads, 16 elements per thread in registers.
-// Stages are grouped in passes of four (radix 16) done entirely in registers;
-// between passes the polynomial goes through LDS (n words plus padding).
-// Element e of thread tid in the pass starting at stage S0 (window of RW
-// stages, combos of 2^RW elements) has index
+// Layout on gfx950: T = n/E threads, E = 2^LOGE elements per thread in
+// registers.  Stages are grouped in passes of LOGE (radix E) done entirely in
+// registers; between passes the polynomial goes through LDS (n words plus
+// padding).  Element e of thread tid in the pass starting at stage S0
+// (window of RW stages, combos of 2^RW elements) has index
 //     idx = (high << (LOGN - S0)) | (w << LOWB) | low,
 //     e = c * 2^RW + w, combo = tid + T * c, high = combo >> LOWB,
 //     low = combo mod 2^LOWB, LOWB = LOGN - S0 - RW.
-// The first pass is the natural order (idx = (e << (LOGN-4)) | tid: lanes read
-// consecutive words), the last pass leaves each thread with contiguous
+// The first pass is the natural order (idx = (e << (LOGN-LOGE)) | tid: lanes
+// read consecutive words), the last pass leaves each thread with contiguous
 // elements of the transform.
 #pragma once
 #include "arith.h"
 
 namespace wally {
 
-template <int LOGN>
+template <int LOGN, int LOGE>
 struct NttShape {
   static constexpr int N = 1 << LOGN;
-  static constexpr int E = 16;
-  static constexpr int RB = 4;
+  static constexpr int E = 1 << LOGE;
   static constexpr int T = N / E;
-  static constexpr int NPASS = (LOGN + RB - 1) / RB;
-  static constexpr int LAST_S0 = RB * (NPASS - 1);
+  static constexpr int NPASS = (LOGN + LOGE - 1) / LOGE;
+  static constexpr int LAST_S0 = LOGE * (NPASS - 1);
   static constexpr int LDS_WORDS = N + N / 32;
   __device__ static __forceinline__ int lds(int idx) { return idx + (idx >> 5); }
 };
 
-template <int LOGN, int S0>
+template <int LOGN, int LOGE, int S0>
 struct PassMap {
-  static constexpr int RW = (LOGN - S0) < 4 ? (LOGN - S0) : 4;
+  static constexpr int RW = (LOGN - S0) < LOGE ? (LOGN - S0) : LOGE;
   static constexpr int LOWB = LOGN - S0 - RW;
-  static constexpr int COMBOS = 16 >> RW;
-  static constexpr int T = NttShape<LOGN>::T;
+  static constexpr int COMBOS = (1 << LOGE) >> RW;
+  static constexpr int T = NttShape<LOGN, LOGE>::T;
   // index of register e of thread tid
   __device__ static __forceinline__ uint32_t idx(int tid, int e) {
     const uint32_t c = e >> RW, w = e & ((1 << RW) - 1);
@@ -51,10 +50,10 @@ struct PassMap {
   }
 };
 
-template <int LOGN>
-using FirstMap = PassMap<LOGN, 0>;
-template <int LOGN>
-using LastMap = PassMap<LOGN, NttShape<LOGN>::LAST_S0>;
+template <int LOGN, int LOGE>
+using FirstMap = PassMap<LOGN, LOGE, 0>;
+template <int LOGN, int LOGE>
+using LastMap = PassMap<LOGN, LOGE, NttShape<LOGN, LOGE>::LAST_S0>;
 
 // Cooley-Tukey butterfly, inputs and outputs in [0, 4q).
 __device__ __forceinline__ void ct_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, uint64_t q, uint64_t q2) {
@@ -72,10 +71,10 @@ __device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, 
   Y = shoup(v, W.x, W.y, q);
 }
 
-template <int LOGN, int S0>
-__device__ __forceinline__ void ct_pass(uint64_t (&x)[16], const ulonglong2* __restrict__ tw, uint64_t q, uint64_t q2,
-                                        int tid) {
-  using M = PassMap<LOGN, S0>;
+template <int LOGN, int LOGE, int S0>
+__device__ __forceinline__ void ct_pass(uint64_t (&x)[1 << LOGE], const ulonglong2* __restrict__ tw, uint64_t q,
+                                        uint64_t q2, int tid) {
+  using M = PassMap<LOGN, LOGE, S0>;
 #pragma unroll
   for (int c = 0; c < M::COMBOS; ++c) {
     const uint32_t combo = tid + M::T * c;
@@ -94,10 +93,10 @@ __device__ __forceinline__ void ct_pass(uint64_t (&x)[16], const ulonglong2* __r
   }
 }
 
-template <int LOGN, int S0>
-__device__ __forceinline__ void gs_pass(uint64_t (&x)[16], const ulonglong2* __restrict__ itw, uint64_t q, uint64_t q2,
-                                        int tid) {
-  using M = PassMap<LOGN, S0>;
+template <int LOGN, int LOGE, int S0>
+__device__ __forceinline__ void gs_pass(uint64_t (&x)[1 << LOGE], const ulonglong2* __restrict__ itw, uint64_t q,
+                                        uint64_t q2, int tid) {
+  using M = PassMap<LOGN, LOGE, S0>;
 #pragma unroll
   for (int c = 0; c < M::COMBOS; ++c) {
     const uint32_t combo = tid + M::T * c;
@@ -118,52 +117,70 @@ __device__ __forceinline__ void gs_pass(uint64_t (&x)[16], const ulonglong2* __r
 
 // Move the polynomial from the register mapping of pass A to that of pass B.
 // Ends with a barrier so the buffer can be reused right away.
-template <int LOGN, int SA, int SB>
-__device__ __forceinline__ void exchange(uint64_t (&x)[16], uint64_t* lds, int tid) {
-  using S = NttShape<LOGN>;
+template <int LOGN, int LOGE, int SA, int SB>
+__device__ __forceinline__ void exchange(uint64_t (&x)[1 << LOGE], uint64_t* lds, int tid) {
+  using S = NttShape<LOGN, LOGE>;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) lds[S::lds(PassMap<LOGN, SA>::idx(tid, e))] = x[e];
+  for (int e = 0; e < S::E; ++e) lds[S::lds(PassMap<LOGN, LOGE, SA>::idx(tid, e))] = x[e];
   __syncthreads();
 #pragma unroll
-  for (int e = 0; e < 16; ++e) x[e] = lds[S::lds(PassMap<LOGN, SB>::idx(tid, e))];
+  for (int e = 0; e < S::E; ++e) x[e] = lds[S::lds(PassMap<LOGN, LOGE, SB>::idx(tid, e))];
   __syncthreads();
 }
 
-template <int LOGN, int P>
-__device__ __forceinline__ void fwd_passes(uint64_t (&x)[16], uint64_t* lds, const ulonglong2* tw, uint64_t q,
+template <int LOGN, int LOGE, int P>
+__device__ __forceinline__ void fwd_passes(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* tw, uint64_t q,
                                            uint64_t q2, int tid) {
-  constexpr int S0 = 4 * P;
+  constexpr int S0 = LOGE * P;
   if constexpr (S0 < LOGN) {
-    if constexpr (P > 0) exchange<LOGN, 4 * (P - 1), S0>(x, lds, tid);
-    ct_pass<LOGN, S0>(x, tw, q, q2, tid);
-    fwd_passes<LOGN, P + 1>(x, lds, tw, q, q2, tid);
+    if constexpr (P > 0) exchange<LOGN, LOGE, LOGE * (P - 1), S0>(x, lds, tid);
+    ct_pass<LOGN, LOGE, S0>(x, tw, q, q2, tid);
+    fwd_passes<LOGN, LOGE, P + 1>(x, lds, tw, q, q2, tid);
   }
 }
 
-template <int LOGN, int P>
-__device__ __forceinline__ void inv_passes(uint64_t (&x)[16], uint64_t* lds, const ulonglong2* itw, uint64_t q,
+template <int LOGN, int LOGE, int P>
+__device__ __forceinline__ void inv_passes(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* itw, uint64_t q,
                                            uint64_t q2, int tid) {
   if constexpr (P >= 0) {
-    constexpr int S0 = 4 * P;
-    if constexpr (P < NttShape<LOGN>::NPASS - 1) exchange<LOGN, 4 * (P + 1), S0>(x, lds, tid);
-    gs_pass<LOGN, S0>(x, itw, q, q2, tid);
-    inv_passes<LOGN, P - 1>(x, lds, itw, q, q2, tid);
+    constexpr int S0 = LOGE * P;
+    if constexpr (P < NttShape<LOGN, LOGE>::NPASS - 1) exchange<LOGN, LOGE, LOGE * (P + 1), S0>(x, lds, tid);
+    gs_pass<LOGN, LOGE, S0>(x, itw, q, q2, tid);
+    inv_passes<LOGN, LOGE, P - 1>(x, lds, itw, q, q2, tid);
   }
 }
 
 // Forward transform.  In: FirstMap order, values < 4q.  Out: LastMap order, [0, 4q).
-template <int LOGN>
-__device__ __forceinline__ void ntt_fwd(uint64_t (&x)[16], uint64_t* lds, const ulonglong2* tw, uint64_t q,
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void ntt_fwd(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* tw, uint64_t q,
                                         int tid) {
-  fwd_passes<LOGN, 0>(x, lds, tw, q, 2 * q, tid);
+  fwd_passes<LOGN, LOGE, 0>(x, lds, tw, q, 2 * q, tid);
 }
 
 // Inverse transform without the n^-1 factor.  In: LastMap order, values < 2q.
 // Out: FirstMap order, [0, 2q).
-template <int LOGN>
-__device__ __forceinline__ void ntt_inv(uint64_t (&x)[16], uint64_t* lds, const ulonglong2* itw, uint64_t q,
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void ntt_inv(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* itw, uint64_t q,
                                         int tid) {
-  inv_passes<LOGN, NttShape<LOGN>::NPASS - 1>(x, lds, itw, q, 2 * q, tid);
+  inv_passes<LOGN, LOGE, NttShape<LOGN, LOGE>::NPASS - 1>(x, lds, itw, q, 2 * q, tid);
+}
+
+// Forward transform with natural-order I/O: in and out in FirstMap order
+// (lane-consecutive words for every register), out in [0, 4q).
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void ntt_fwd_nat(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* tw, uint64_t q,
+                                            int tid) {
+  fwd_passes<LOGN, LOGE, 0>(x, lds, tw, q, 2 * q, tid);
+  exchange<LOGN, LOGE, NttShape<LOGN, LOGE>::LAST_S0, 0>(x, lds, tid);
+}
+
+// Inverse transform (no n^-1) with natural-order I/O: in and out in FirstMap
+// order, in < 2q, out in [0, 2q).
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void ntt_inv_nat(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* itw, uint64_t q,
+                                            int tid) {
+  exchange<LOGN, LOGE, 0, NttShape<LOGN, LOGE>::LAST_S0>(x, lds, tid);
+  inv_passes<LOGN, LOGE, NttShape<LOGN, LOGE>::NPASS - 1>(x, lds, itw, q, 2 * q, tid);
 }
 
 // Source index of NTT entry i under X -> X^gal: entry i holds a(psi^(2 brv(i)+1)),
@@ -174,6 +191,25 @@ __device__ __forceinline__ uint32_t galois_src(uint32_t i, uint32_t gal) {
   const uint32_t e = 2u * (__brev(i) >> (32 - LOGN)) + 1u;
   const uint32_t f = (e * gal) & mask2n;
   return __brev((f - 1u) >> 1) >> (32 - LOGN);
+}
+
+// x <- sigma_gal(src) in the register mapping MAP: the row is read with
+// coalesced loads into LDS and permuted there (a direct gather from global
+// memory would touch a different cache line in every lane).
+template <int LOGN, int LOGE, class MAP>
+__device__ __forceinline__ void gather_galois(uint64_t (&x)[1 << LOGE], const uint64_t* __restrict__ src,
+                                              uint64_t* lds, uint32_t gal, int tid) {
+  using S = NttShape<LOGN, LOGE>;
+  using FM = FirstMap<LOGN, LOGE>;
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) {
+    const uint32_t i = FM::idx(tid, e);
+    lds[S::lds(i)] = src[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) x[e] = lds[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))];
+  __syncthreads();
 }
 
 }  // namespace wally

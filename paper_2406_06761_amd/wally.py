@@ -60,7 +60,7 @@ SYMBOLS = [
     "wally_diag_kernel_stats",
 ]
 
-KERNELS = ["ks_digits", "ks_modup", "ks_moddown", "mac_init", "copy_ct"]
+KERNELS = ["ks_digits", "ks_extend", "ks_inner", "ks_pinv", "ks_moddown", "mac", "copy_ct"]
 
 
 class KernelStat(ctypes.Structure):
