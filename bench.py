@@ -92,6 +92,83 @@ def cpu_baseline(workload, sample, threads, params_name):
             "sample": f"{sample} seeded queries of the batch ({scores} scores), {dt:.1f} s wall"}
 
 
+def serve_rates(ctx, w, chunks, cts, kbs, kgs, pool, rates, duration, log_every=1.0):
+    """Serving through wally_serve_*: Poisson arrivals at each rate; a query is
+    submitted when it arrives (retried while admission refuses it), latency is
+    arrival -> the poll that reports it done."""
+    import torch
+
+    from paper_2406_06761_amd import synth
+
+    n_info = ctx.info
+    ctw = int(n_info.ct_words)
+    max_chunks = int(chunks.max())
+    ring = 16384
+    outs = torch.empty((ring, max_chunks * ctw), dtype=torch.int64, device="cuda")
+    rng = np.random.default_rng(synth.SEED_ARRIVALS)
+    results = []
+    for rate in rates:
+        arrivals = synth.poisson_arrivals(rate, duration, seed=synth.SEED_ARRIVALS + int(rate))
+        # each arrival targets a cluster of the batch's real+fake stream
+        picks = rng.integers(0, len(w.targets), len(arrivals))
+        ctx.serve_start()
+        busy = np.zeros(ring, dtype=bool)
+        t_arr = {}
+        lat = []
+        scores_done = 0
+        refused = 0        # submissions refused by admission (retried)
+        deferred = set()   # arrivals refused at least once
+        k = 0
+        slot = 0
+        start = time.perf_counter()
+        last_log = start
+        while True:
+            now = time.perf_counter() - start
+            while k < len(arrivals) and arrivals[k] <= now:
+                if busy[slot]:
+                    break  # ring full: wait for completions
+                q = int(picks[k])
+                pi = q % pool
+                c = int(w.targets[q])
+                t = ctx.serve_submit(c, cts[pi].data_ptr(), kbs[pi].data_ptr(), kgs[pi].data_ptr(), outs[slot].data_ptr())
+                if t is None:
+                    refused += 1
+                    deferred.add(k)
+                    break
+                t_arr[t] = (arrivals[k], slot, int(w.sizes[c]))
+                busy[slot] = True
+                slot = (slot + 1) % ring
+                k += 1
+            done = ctx.serve_poll(8192)
+            now = time.perf_counter() - start
+            for t in done:
+                a, sl, sc = t_arr.pop(t)
+                busy[sl] = False
+                lat.append(now - a)
+                scores_done += sc
+            if k >= len(arrivals) and not t_arr:
+                break
+            if now - (last_log - start) > log_every:
+                last_log = time.perf_counter()
+                log(f"  serve {rate:.0f}/s: t={now:.1f}s submitted {k} done {len(lat)} in flight {len(t_arr)}")
+            if now > duration * 6 + 30:
+                log("  serve: stopping, backlog too large")
+                break
+        ctx.serve_stop()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - start
+        lat_ms = np.array(lat) * 1e3
+        r = {"rate_qps": rate, "duration_s": duration, "arrivals": int(len(arrivals)), "completed": len(lat),
+             "p50_ms": float(np.percentile(lat_ms, 50)) if len(lat) else None,
+             "p99_ms": float(np.percentile(lat_ms, 99)) if len(lat) else None,
+             "sustained_scores_per_s": scores_done / elapsed, "sustained_qps": len(lat) / elapsed,
+             "deferred_arrivals": len(deferred), "admission_refusals": refused, "wall_s": elapsed}
+        log(f"serve {rate:.0f} QPS: p50 {r['p50_ms']:.1f} ms p99 {r['p99_ms']:.1f} ms, "
+            f"{r['sustained_qps']:.0f} QPS sustained, {len(deferred)} arrivals deferred by admission")
+        results.append(r)
+    return results
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +183,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-launch events")
+    ap.add_argument("--serve-rates", default="5000,20000,50000", help="Poisson arrival rates (QPS), '' = skip")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -217,6 +296,11 @@ def main():
         plain = scores * args.plain_steps / pdt
         log(f"plain per-cluster path: {pdt / args.plain_steps * 1e3:.1f} ms/step, {plain:.4g} scores/s")
 
+    serving = None
+    if args.serve_rates:
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        serving = serve_rates(ctx, w, chunks, cts, kbs, kgs, pool, rates, args.serve_seconds)
+
     cpu = None
     if not args.no_cpu and args.cpu_sample > 0:
         threads = min(16, os.cpu_count() or 1)
@@ -247,6 +331,7 @@ def main():
         "plain_path_scores_per_s": plain,
         "speedup_vs_plain": (value / plain) if plain else None,
         "encode_s": encode_s,
+        "serving": serving,
         "roofline": roofline,
         "kernels_ms": {k: v[2] for k, v in kstats.items()},
         "cpu_baseline": cpu,

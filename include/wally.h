@@ -57,7 +57,7 @@ typedef struct wally_ctx wally_ctx;
 typedef struct {
   uint32_t log_n;      /* 12 or 13                                          */
   uint32_t num_limbs;  /* L, 1..8                                           */
-  uint32_t limb_bits;  /* 30..60 bits per ciphertext prime                  */
+  uint32_t limb_bits;  /* 30..54 bits per ciphertext prime                  */
   uint32_t t_bits;     /* plaintext modulus just above 2^t_bits (< limb_bits)*/
   uint32_t dim;        /* embedding dimension d                             */
   uint32_t layout;     /* WALLY_LAYOUT_PER_CLUSTER                          */

@@ -38,6 +38,11 @@ __device__ __forceinline__ uint64_t reduce4(uint64_t x, uint64_t q, uint64_t q2)
   return x >= q ? x - q : x;
 }
 
+// any x < 2^64 -> [0, q), given onep = floor(2^64 / q) (Shoup with w = 1)
+__device__ __forceinline__ uint64_t reduce_lazy(uint64_t x, uint64_t q, uint64_t onep) {
+  return csub(x - mulhi64(x, onep) * q, q);
+}
+
 __device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) { return csub(a + b, q); }
 __device__ __forceinline__ uint64_t submod(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
 

@@ -467,7 +467,7 @@ int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
   *out = nullptr;
   if (desc->log_n != 12 && desc->log_n != 13) return WALLY_EINVAL;
   if (desc->num_limbs < 1 || desc->num_limbs > kMaxLimbs) return WALLY_EINVAL;
-  if (desc->limb_bits < 30 || desc->limb_bits > 60) return WALLY_EINVAL;
+  if (desc->limb_bits < 30 || desc->limb_bits > 54) return WALLY_EINVAL;  // 27-bit halves in the sums
   if (desc->t_bits < 2 || desc->t_bits + 2 > desc->limb_bits) return WALLY_EINVAL;
   if (desc->dim < 1) return WALLY_EINVAL;
   if (desc->layout != WALLY_LAYOUT_PER_CLUSTER) return WALLY_EINVAL;
@@ -548,6 +548,8 @@ int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
     M.mc[m].onep = (uint64_t)((((u128)1) << 64) / q);
     M.ninv[m] = powmod(c->n % q, q - 2, q);
     M.ninvp[m] = shoup_of(M.ninv[m], q);
+    M.c27[m] = (1ull << 27) % q;
+    M.c27p[m] = shoup_of(M.c27[m], q);
   }
   const uint64_t P = c->mods[c->L];
   for (int j = 0; j < c->L; ++j) {

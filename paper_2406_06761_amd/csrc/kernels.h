@@ -21,6 +21,7 @@ struct DevModuli {
   ModConst mc[kMaxMod];
   uint64_t ninv[kMaxMod], ninvp[kMaxMod];  // n^-1 mod q and Shoup factor
   uint64_t pinv[kMaxMod], pinvp[kMaxMod];  // P^-1 mod q_j (j < L) and Shoup factor
+  uint64_t c27[kMaxMod], c27p[kMaxMod];    // 2^27 mod q and Shoup factor
   const ulonglong2* fwd[kMaxMod];          // (psi^brv(k), Shoup) for k < n
   const ulonglong2* inv[kMaxMod];          // (psi^-brv(k), Shoup)
 };

@@ -84,9 +84,9 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const K
   const uint64_t* X = a.X + ((uint64_t)b * L + i) * S::N;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) d[e] = X[FM::idx(tid, e)];  // < q_i < 2 q_m: a valid lazy input
-  ntt_fwd_nat<LOGN, LOGE>(d, lds, M.fwd[m], q, tid);
+  ntt_fwd_nat<LOGN, LOGE>(d, lds, M.fwd[m], q, tid);  // out < 28 q
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) D[FM::idx(tid, e)] = reduce4(d[e], q, 2 * q);
+  for (int e = 0; e < S::E; ++e) D[FM::idx(tid, e)] = reduce_lazy(d[e], q, M.mc[m].onep);
 }
 
 // ---------------------------------------------------------------------------
@@ -163,7 +163,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_wa
   const uint64_t* U = a.U + (((uint64_t)b * 2 + t) * MM + j) * S::N;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) {
-    const uint64_t v = submod(U[FM::idx(tid, e)], reduce4(z[e], q, 2 * q), q);
+    const uint64_t v = submod(U[FM::idx(tid, e)], reduce_lazy(z[e], q, M.mc[j].onep), q);
     z[e] = csub(shoup(v, M.pinv[j], M.pinvp[j], q), q);
   }
   if (t == 0) {
@@ -189,8 +189,20 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_wa
 //   acc_i[t][l][x] = sum_{j<g} PT[g i + j][l][x] * ct'_j[t][l][x]  for all i < h.
 // Per coefficient this is a (queries x g) by (g x h) product over Z_q; the
 // items of a tile share one plaintext chunk, so PT is read once per tile while
-// each item's g rotated copies are read once into registers.  Sums of g
-// products (< g 2^108) are kept in 128 bits and reduced once.
+// each item's g rotated copies are read once into registers.
+// Exact lazy accumulation: both factors (< 2^54) are split into 27-bit halves,
+// a = a1 2^27 + a0, so a*b = a0 b0 + (a0 b1 + a1 b0) 2^27 + a1 b1 2^54 and the
+// three partial sums of g <= 32 products stay below 2^60 in 64-bit words (one
+// v_mad_u64_u32 per partial product, no carries); they are reduced once.
+__device__ __forceinline__ uint64_t fold27(uint64_t s0, uint64_t s1, uint64_t s2, const ModConst& mc,
+                                           uint64_t c27, uint64_t c27p) {
+  const uint64_t q = mc.q;
+  // ((s2 2^27 mod q) + s1) 2^27 + s0  (mod q); each Shoup result is below 2q
+  const uint64_t u = shoup(s2, c27, c27p, q) + s1;        // < 2q + 2^60
+  const uint64_t v = shoup(u, c27, c27p, q) + s0;         // < 2q + 2^59
+  return csub(v - mulhi64(v, mc.onep) * q, q);            // v mod q
+}
+
 // grid (n / 64, L, tiles); block 256 = 64 coefficients x 4 item lanes
 template <int G>
 __global__ __launch_bounds__(256) void k_mac_tiles(const KsItem* __restrict__ items, const MacTile* __restrict__ tiles,
@@ -202,28 +214,38 @@ __global__ __launch_bounds__(256) void k_mac_tiles(const KsItem* __restrict__ it
   const uint64_t x = (uint64_t)blockIdx.x * 64 + (threadIdx.x & 63);
   const int lane = threadIdx.x >> 6;
   const ModConst mc = M.mc[j];
-  const uint64_t q = mc.q;
+  const uint64_t c27 = M.c27[j], c27p = M.c27p[j];
   const uint64_t ctw = 2ull * L * n;
   const uint64_t* pt = items[tl.first].pt + (uint64_t)j * n + x;  // PT[m][j][x] at m * L * n
+  const uint64_t M27 = (1ull << 27) - 1;
   for (uint32_t k = lane; k < tl.count; k += 4) {
     const KsItem it = items[tl.first + k];
-    uint64_t c0[G], c1[G];
+    uint32_t c0l[G], c0h[G], c1l[G], c1h[G];
 #pragma unroll
     for (int jj = 0; jj < G; ++jj) {
-      c0[jj] = it.ctp[jj * ctw + (uint64_t)j * n + x];
-      c1[jj] = it.ctp[jj * ctw + ((uint64_t)L + j) * n + x];
+      const uint64_t v0 = it.ctp[jj * ctw + (uint64_t)j * n + x];
+      const uint64_t v1 = it.ctp[jj * ctw + ((uint64_t)L + j) * n + x];
+      c0l[jj] = (uint32_t)(v0 & M27);
+      c0h[jj] = (uint32_t)(v0 >> 27);
+      c1l[jj] = (uint32_t)(v1 & M27);
+      c1h[jj] = (uint32_t)(v1 >> 27);
     }
     for (int i = 0; i < h; ++i) {
-      u128w s0{0, 0}, s1{0, 0};
+      uint64_t a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
 #pragma unroll
       for (int jj = 0; jj < G; ++jj) {
         const uint64_t w = pt[(uint64_t)(G * i + jj) * L * n];
-        mac128(s0, w, c0[jj]);
-        mac128(s1, w, c1[jj]);
+        const uint32_t wl = (uint32_t)(w & M27), wh = (uint32_t)(w >> 27);
+        a0 += (uint64_t)wl * c0l[jj];
+        a1 += (uint64_t)wl * c0h[jj] + (uint64_t)wh * c0l[jj];
+        a2 += (uint64_t)wh * c0h[jj];
+        b0 += (uint64_t)wl * c1l[jj];
+        b1 += (uint64_t)wl * c1h[jj] + (uint64_t)wh * c1l[jj];
+        b2 += (uint64_t)wh * c1h[jj];
       }
       uint64_t* acc = it.acc + (uint64_t)i * ctw + (uint64_t)j * n + x;
-      acc[0] = reduce128(s0, q, mc.r64, mc.r64p, mc.onep);
-      acc[(uint64_t)L * n] = reduce128(s1, q, mc.r64, mc.r64p, mc.onep);
+      acc[0] = fold27(a0, a1, a2, mc, c27, c27p);
+      acc[(uint64_t)L * n] = fold27(b0, b1, b2, mc, c27, c27p);
     }
   }
 }
@@ -287,7 +309,7 @@ __global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_encode(const EncodeJ
     ntt_fwd_nat<LOGN, 4>(x, lds, M.fwd[l], q, tid);
     uint64_t* out = jb.out + ((uint64_t)m * a.L + l) * S::N;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) out[FirstMap<LOGN, 4>::idx(tid, e)] = reduce4(x[e], q, 2 * q);
+    for (int e = 0; e < 16; ++e) out[FirstMap<LOGN, 4>::idx(tid, e)] = reduce_lazy(x[e], q, M.mc[l].onep);
   }
 }
 
@@ -306,7 +328,7 @@ __global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_ntt_rows(uint64_t* d
     for (int e = 0; e < 16; ++e) x[e] = row[FirstMap<LOGN, 4>::idx(tid, e)];
     ntt_fwd_nat<LOGN, 4>(x, lds, M.fwd[mi], q, tid);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) row[FirstMap<LOGN, 4>::idx(tid, e)] = reduce4(x[e], q, 2 * q);
+    for (int e = 0; e < 16; ++e) row[FirstMap<LOGN, 4>::idx(tid, e)] = reduce_lazy(x[e], q, M.mc[mi].onep);
   } else {
 #pragma unroll
     for (int e = 0; e < 16; ++e) x[e] = row[FirstMap<LOGN, 4>::idx(tid, e)];

@@ -3,10 +3,14 @@
 // The transform is the one of the scheme: entry i of the forward transform of
 // a(X) mod q is a(psi^(2 brv(i) + 1)), psi the smallest primitive 2n-th root.
 // It is evaluated as Cooley-Tukey stages s = 0..LOGN-1 (stage s: 2^s groups,
-// butterfly distance n / 2^(s+1), twiddle psi^brv(2^s + group)) with Harvey's
-// lazy butterflies (paper §7.1): values stay in [0, 4q) between stages and
-// twiddle products use Shoup's precomputed quotient.  The inverse runs the
-// Gentleman-Sande butterflies of the same stages in reverse order.
+// butterfly distance n / 2^(s+1), twiddle psi^brv(2^s + group)) with lazy
+// reduction (paper §7.1): twiddle products use Shoup's precomputed quotient
+// and give values in [0, 2q); the forward butterfly X' = X + t,
+// Y' = X + 2q - t does no other reduction, so a bound B on the inputs grows to
+// B + 2q per stage.  With q < 2^54 and inputs below 2q, all 13 stages of an
+// n = 8192 transform stay below 28q < 2^59, and the outputs are reduced once.
+// The inverse runs Gentleman-Sande butterflies of the same stages in reverse
+// order, keeping values in [0, 2q) (Harvey's bounds).
 //
 // Layout on gfx950: T = n/E threads, E = 2^LOGE elements per thread in
 // registers.  Stages are grouped in passes of LOGE (radix E) done entirely in
@@ -55,12 +59,11 @@ using FirstMap = PassMap<LOGN, LOGE, 0>;
 template <int LOGN, int LOGE>
 using LastMap = PassMap<LOGN, LOGE, NttShape<LOGN, LOGE>::LAST_S0>;
 
-// Cooley-Tukey butterfly, inputs and outputs in [0, 4q).
+// Cooley-Tukey butterfly without reduction: inputs below B, outputs below B + 2q.
 __device__ __forceinline__ void ct_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, uint64_t q, uint64_t q2) {
-  const uint64_t x = X >= q2 ? X - q2 : X;
   const uint64_t t = shoup(Y, W.x, W.y, q);
-  X = x + t;
-  Y = x - t + q2;
+  Y = X + q2 - t;
+  X = X + t;
 }
 
 // Gentleman-Sande butterfly, inputs and outputs in [0, 2q).
@@ -150,7 +153,8 @@ __device__ __forceinline__ void inv_passes(uint64_t (&x)[1 << LOGE], uint64_t* l
   }
 }
 
-// Forward transform.  In: FirstMap order, values < 4q.  Out: LastMap order, [0, 4q).
+// Forward transform.  In: FirstMap order, values < 2q.  Out: LastMap order,
+// values below (2 + 2 LOGN) q (reduce with reduce_lazy).
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void ntt_fwd(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* tw, uint64_t q,
                                         int tid) {
@@ -166,7 +170,7 @@ __device__ __forceinline__ void ntt_inv(uint64_t (&x)[1 << LOGE], uint64_t* lds,
 }
 
 // Forward transform with natural-order I/O: in and out in FirstMap order
-// (lane-consecutive words for every register), out in [0, 4q).
+// (lane-consecutive words for every register); same bounds as ntt_fwd.
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void ntt_fwd_nat(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* tw, uint64_t q,
                                             int tid) {
