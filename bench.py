@@ -278,10 +278,13 @@ def main():
         items_per_launch = items / max(launches, 1)
         achieved = work[dom] * items_per_launch / (avg_ms * 1e-3)
         peak = PEAK_VALU_LANE_OPS / INSTR_PER_MODMUL
+        step_work = sum(kstats[k][1] * work[k] for k in kstats) / args.steps
         roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e9, "peak": peak / 1e9,
                     "unit": "Gmodmul/s", "frac": achieved / peak, "traffic": None,
                     "avg_launch_ms": avg_ms, "items_per_launch": items_per_launch,
-                    "work_per_item": work[dom]}
+                    "work_per_item": work[dom],
+                    "path_gmodmul_per_s": step_work / (ms_per_step * 1e-3) / 1e9,
+                    "path_frac": step_work / (ms_per_step * 1e-3) / peak}
         for k, (nl, it, ms) in kstats.items():
             log(f"  {k:11s} launches {nl:7d} items {it:9d} total {ms:9.1f} ms avg {ms / max(nl, 1):.3f} ms")
 

@@ -29,6 +29,19 @@ __device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t wp, u
   return a * w - qh * q;
 }
 
+// a * w mod q in [0, 4q) for any a < 2^64, w < q, wp = floor(w 2^64 / q).
+// Shoup's quotient floor(a wp / 2^64) without the low x low partial product
+// and without the carry between the two middle ones:
+//   a wp = a1 w1 2^64 + (a0 w1 + a1 w0) 2^32 + a0 w0, and the dropped parts add
+//   less than 3 to the quotient, so qh is exact or up to 2 below it.
+__device__ __forceinline__ uint64_t shoup4(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t w0 = (uint32_t)wp, w1 = (uint32_t)(wp >> 32);
+  const uint64_t mid = (uint64_t)__umulhi(a0, w1) + __umulhi(a1, w0);
+  const uint64_t qh = (uint64_t)a1 * w1 + mid;
+  return a * w - qh * q;
+}
+
 // x in [0, 2q) -> [0, q)
 __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t q) { return x >= q ? x - q : x; }
 

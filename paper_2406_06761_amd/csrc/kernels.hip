@@ -84,7 +84,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const K
   const uint64_t* X = a.X + ((uint64_t)b * L + i) * S::N;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) d[e] = X[FM::idx(tid, e)];  // < q_i < 2 q_m: a valid lazy input
-  ntt_fwd_nat<LOGN, LOGE>(d, lds, M.fwd[m], q, tid);  // out < 28 q
+  ntt_fwd_nat<LOGN, LOGE>(d, lds, M.fwd[m], q, tid);  // out < 54 q
 #pragma unroll
   for (int e = 0; e < S::E; ++e) D[FM::idx(tid, e)] = reduce_lazy(d[e], q, M.mc[m].onep);
 }

@@ -4,13 +4,15 @@
 // a(X) mod q is a(psi^(2 brv(i) + 1)), psi the smallest primitive 2n-th root.
 // It is evaluated as Cooley-Tukey stages s = 0..LOGN-1 (stage s: 2^s groups,
 // butterfly distance n / 2^(s+1), twiddle psi^brv(2^s + group)) with lazy
-// reduction (paper §7.1): twiddle products use Shoup's precomputed quotient
-// and give values in [0, 2q); the forward butterfly X' = X + t,
-// Y' = X + 2q - t does no other reduction, so a bound B on the inputs grows to
-// B + 2q per stage.  With q < 2^54 and inputs below 2q, all 13 stages of an
-// n = 8192 transform stay below 28q < 2^59, and the outputs are reduced once.
+// reduction (paper §7.1): the twiddle product t = W Y mod q uses a Shoup
+// quotient without its low partial products (t in [0, 4q), shoup4), and the
+// forward butterfly X' = X + t, Y' = X + 4q - t does no other reduction, so a
+// bound B on the inputs grows to B + 4q per stage.  With q < 2^54 and inputs
+// below 2q, all 13 stages of an n = 8192 transform stay below 54q < 2^60, and
+// the outputs are reduced once.
 // The inverse runs Gentleman-Sande butterflies of the same stages in reverse
-// order, keeping values in [0, 2q) (Harvey's bounds).
+// order, keeping values in [0, 4q): X' = X + Y (minus 4q when above),
+// Y' = W (X - Y + 4q) with the same quotient.
 //
 // Layout on gfx950: T = n/E threads, E = 2^LOGE elements per thread in
 // registers.  Stages are grouped in passes of LOGE (radix E) done entirely in
@@ -59,24 +61,25 @@ using FirstMap = PassMap<LOGN, LOGE, 0>;
 template <int LOGN, int LOGE>
 using LastMap = PassMap<LOGN, LOGE, NttShape<LOGN, LOGE>::LAST_S0>;
 
-// Cooley-Tukey butterfly without reduction: inputs below B, outputs below B + 2q.
-__device__ __forceinline__ void ct_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, uint64_t q, uint64_t q2) {
-  const uint64_t t = shoup(Y, W.x, W.y, q);
-  Y = X + q2 - t;
+// Cooley-Tukey butterfly without reduction: inputs below B, outputs below B + 4q
+// (q4 = 4q).
+__device__ __forceinline__ void ct_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, uint64_t q, uint64_t q4) {
+  const uint64_t t = shoup4(Y, W.x, W.y, q);
+  Y = X + q4 - t;
   X = X + t;
 }
 
-// Gentleman-Sande butterfly, inputs and outputs in [0, 2q).
-__device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, uint64_t q, uint64_t q2) {
+// Gentleman-Sande butterfly, inputs and outputs in [0, 4q) (q4 = 4q).
+__device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, uint64_t q, uint64_t q4) {
   const uint64_t u = X + Y;
-  const uint64_t v = X - Y + q2;
-  X = u >= q2 ? u - q2 : u;
-  Y = shoup(v, W.x, W.y, q);
+  const uint64_t v = X - Y + q4;
+  X = u >= q4 ? u - q4 : u;
+  Y = shoup4(v, W.x, W.y, q);
 }
 
 template <int LOGN, int LOGE, int S0>
 __device__ __forceinline__ void ct_pass(uint64_t (&x)[1 << LOGE], const ulonglong2* __restrict__ tw, uint64_t q,
-                                        uint64_t q2, int tid) {
+                                        uint64_t q4, int tid) {
   using M = PassMap<LOGN, LOGE, S0>;
 #pragma unroll
   for (int c = 0; c < M::COMBOS; ++c) {
@@ -90,7 +93,7 @@ __device__ __forceinline__ void ct_pass(uint64_t (&x)[1 << LOGE], const ulonglon
         if (w & half) continue;
         const uint32_t grp = ((high << M::RW) | (uint32_t)w) >> (M::RW - ls);
         const ulonglong2 W = tw[(1u << (S0 + ls)) + grp];
-        ct_bfly(x[c * (1 << M::RW) + w], x[c * (1 << M::RW) + w + half], W, q, q2);
+        ct_bfly(x[c * (1 << M::RW) + w], x[c * (1 << M::RW) + w + half], W, q, q4);
       }
     }
   }
@@ -98,7 +101,7 @@ __device__ __forceinline__ void ct_pass(uint64_t (&x)[1 << LOGE], const ulonglon
 
 template <int LOGN, int LOGE, int S0>
 __device__ __forceinline__ void gs_pass(uint64_t (&x)[1 << LOGE], const ulonglong2* __restrict__ itw, uint64_t q,
-                                        uint64_t q2, int tid) {
+                                        uint64_t q4, int tid) {
   using M = PassMap<LOGN, LOGE, S0>;
 #pragma unroll
   for (int c = 0; c < M::COMBOS; ++c) {
@@ -112,7 +115,7 @@ __device__ __forceinline__ void gs_pass(uint64_t (&x)[1 << LOGE], const ulonglon
         if (w & half) continue;
         const uint32_t grp = ((high << M::RW) | (uint32_t)w) >> (M::RW - ls);
         const ulonglong2 W = itw[(1u << (S0 + ls)) + grp];
-        gs_bfly(x[c * (1 << M::RW) + w], x[c * (1 << M::RW) + w + half], W, q, q2);
+        gs_bfly(x[c * (1 << M::RW) + w], x[c * (1 << M::RW) + w + half], W, q, q4);
       }
     }
   }
@@ -133,40 +136,40 @@ __device__ __forceinline__ void exchange(uint64_t (&x)[1 << LOGE], uint64_t* lds
 
 template <int LOGN, int LOGE, int P>
 __device__ __forceinline__ void fwd_passes(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* tw, uint64_t q,
-                                           uint64_t q2, int tid) {
+                                           uint64_t q4, int tid) {
   constexpr int S0 = LOGE * P;
   if constexpr (S0 < LOGN) {
     if constexpr (P > 0) exchange<LOGN, LOGE, LOGE * (P - 1), S0>(x, lds, tid);
-    ct_pass<LOGN, LOGE, S0>(x, tw, q, q2, tid);
-    fwd_passes<LOGN, LOGE, P + 1>(x, lds, tw, q, q2, tid);
+    ct_pass<LOGN, LOGE, S0>(x, tw, q, q4, tid);
+    fwd_passes<LOGN, LOGE, P + 1>(x, lds, tw, q, q4, tid);
   }
 }
 
 template <int LOGN, int LOGE, int P>
 __device__ __forceinline__ void inv_passes(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* itw, uint64_t q,
-                                           uint64_t q2, int tid) {
+                                           uint64_t q4, int tid) {
   if constexpr (P >= 0) {
     constexpr int S0 = LOGE * P;
     if constexpr (P < NttShape<LOGN, LOGE>::NPASS - 1) exchange<LOGN, LOGE, LOGE * (P + 1), S0>(x, lds, tid);
-    gs_pass<LOGN, LOGE, S0>(x, itw, q, q2, tid);
-    inv_passes<LOGN, LOGE, P - 1>(x, lds, itw, q, q2, tid);
+    gs_pass<LOGN, LOGE, S0>(x, itw, q, q4, tid);
+    inv_passes<LOGN, LOGE, P - 1>(x, lds, itw, q, q4, tid);
   }
 }
 
 // Forward transform.  In: FirstMap order, values < 2q.  Out: LastMap order,
-// values below (2 + 2 LOGN) q (reduce with reduce_lazy).
+// values below (2 + 4 LOGN) q (reduce with reduce_lazy).
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void ntt_fwd(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* tw, uint64_t q,
                                         int tid) {
-  fwd_passes<LOGN, LOGE, 0>(x, lds, tw, q, 2 * q, tid);
+  fwd_passes<LOGN, LOGE, 0>(x, lds, tw, q, 4 * q, tid);
 }
 
-// Inverse transform without the n^-1 factor.  In: LastMap order, values < 2q.
-// Out: FirstMap order, [0, 2q).
+// Inverse transform without the n^-1 factor.  In: LastMap order, values < 4q.
+// Out: FirstMap order, [0, 4q).
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void ntt_inv(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* itw, uint64_t q,
                                         int tid) {
-  inv_passes<LOGN, LOGE, NttShape<LOGN, LOGE>::NPASS - 1>(x, lds, itw, q, 2 * q, tid);
+  inv_passes<LOGN, LOGE, NttShape<LOGN, LOGE>::NPASS - 1>(x, lds, itw, q, 4 * q, tid);
 }
 
 // Forward transform with natural-order I/O: in and out in FirstMap order
@@ -174,17 +177,17 @@ __device__ __forceinline__ void ntt_inv(uint64_t (&x)[1 << LOGE], uint64_t* lds,
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void ntt_fwd_nat(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* tw, uint64_t q,
                                             int tid) {
-  fwd_passes<LOGN, LOGE, 0>(x, lds, tw, q, 2 * q, tid);
+  fwd_passes<LOGN, LOGE, 0>(x, lds, tw, q, 4 * q, tid);
   exchange<LOGN, LOGE, NttShape<LOGN, LOGE>::LAST_S0, 0>(x, lds, tid);
 }
 
 // Inverse transform (no n^-1) with natural-order I/O: in and out in FirstMap
-// order, in < 2q, out in [0, 2q).
+// order, in < 4q, out in [0, 4q).
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void ntt_inv_nat(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* itw, uint64_t q,
                                             int tid) {
   exchange<LOGN, LOGE, 0, NttShape<LOGN, LOGE>::LAST_S0>(x, lds, tid);
-  inv_passes<LOGN, LOGE, NttShape<LOGN, LOGE>::NPASS - 1>(x, lds, itw, q, 2 * q, tid);
+  inv_passes<LOGN, LOGE, NttShape<LOGN, LOGE>::NPASS - 1>(x, lds, itw, q, 4 * q, tid);
 }
 
 // Source index of NTT entry i under X -> X^gal: entry i holds a(psi^(2 brv(i)+1)),
