@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-launch events")
     ap.add_argument("--serve-rates", default="5000,20000,50000", help="Poisson arrival rates (QPS), '' = skip")
+    ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner")
+    ap.add_argument("--graph-steps", type=int, default=2, help="timed steps of the graph-captured path (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     args = ap.parse_args()
 
@@ -196,7 +198,7 @@ def main():
     import torch
 
     from paper_2406_06761_amd import synth
-    from paper_2406_06761_amd.wally import PATH_BATCHED, PATH_PLAIN, Context, query_array
+    from paper_2406_06761_amd.wally import PATH_BATCHED, PATH_GRAPH, PATH_PLAIN, Context, query_array
 
     torch.cuda.set_device(0)
     t_setup = time.perf_counter()
@@ -245,6 +247,17 @@ def main():
     log(f"{nq} queries ({w.n_real} real), {scores} scores per step, pool {pool} packets, "
         f"setup {time.perf_counter() - t_setup:.1f} s")
 
+    tuned = None
+    if not args.no_tune and args.workload == "paper":
+        t0 = time.perf_counter()
+        sub = q[: min(8192, nq)]
+        res = ctx.tune(sub, batches=(512, 1024), sets=(2, 3), tiles=(8, 16))
+        best = min(res, key=lambda r: r[3])
+        tuned = {"sample_queries": len(sub), "candidates": [list(r) for r in res],
+                 "chosen": {"max_batch": best[0], "wave_sets": best[1], "tile_items": best[2]}}
+        log(f"tuner: {len(res)} configs in {time.perf_counter() - t0:.1f} s, chose B={best[0]} "
+            f"sets={best[1]} tile={best[2]} ({best[3]:.1f} ms on {len(sub)} queries)")
+
     for i in range(args.warmup):
         t0 = time.perf_counter()
         ctx.score_batch(q, path=PATH_BATCHED)
@@ -288,6 +301,20 @@ def main():
         for k, (nl, it, ms) in kstats.items():
             log(f"  {k:11s} launches {nl:7d} items {it:9d} total {ms:9.1f} ms avg {ms / max(nl, 1):.3f} ms")
 
+    graph = None
+    if args.graph_steps > 0:
+        t0 = time.perf_counter()
+        ctx.score_batch(q, path=PATH_GRAPH)  # capture + first replay
+        torch.cuda.synchronize()
+        log(f"graph capture + first replay: {time.perf_counter() - t0:.2f} s")
+        t0 = time.perf_counter()
+        for i in range(args.graph_steps):
+            ctx.score_batch(q, path=PATH_GRAPH)
+        torch.cuda.synchronize()
+        gdt = time.perf_counter() - t0
+        graph = scores * args.graph_steps / gdt
+        log(f"graph path: {gdt / args.graph_steps * 1e3:.1f} ms/step, {graph:.4g} scores/s")
+
     plain = None
     if args.plain_steps > 0:
         torch.cuda.synchronize()
@@ -328,12 +355,15 @@ def main():
                    "params": f"n={n}, L={L} x {54 if n == 8192 else 36}-bit limbs, t={info.t}",
                    "queries": nq, "real_queries": w.n_real, "scores_per_step": scores,
                    "real_scores_per_step": real_scores, "pool_packets": pool,
-                   "max_batch": args.max_batch or 1024, "wave_sets": args.wave_sets or 2},
+                   "max_batch": args.max_batch or 1024, "wave_sets": args.wave_sets or 2,
+                   "schedule": (tuned or {}).get("chosen")},
         "real_scores_per_s": real_scores * args.steps / dt,
         "queries_per_s": nq * args.steps / dt,
+        "graph_path_scores_per_s": graph,
         "plain_path_scores_per_s": plain,
         "speedup_vs_plain": (value / plain) if plain else None,
         "encode_s": encode_s,
+        "tuned": tuned,
         "serving": serving,
         "roofline": roofline,
         "kernels_ms": {k: v[2] for k, v in kstats.items()},

@@ -51,6 +51,7 @@ extern "C" {
 
 #define WALLY_PATH_BATCHED 0 /* queries of all clusters share launches        */
 #define WALLY_PATH_PLAIN 1   /* one launch sequence per cluster (baseline)     */
+#define WALLY_PATH_GRAPH 2   /* the batched launches captured in one hipGraph  */
 
 typedef struct wally_ctx wally_ctx;
 
@@ -118,12 +119,32 @@ int wally_cluster_info(const wally_ctx* ctx, uint32_t c, uint32_t* n_chunks, con
 /* Score nq queries (Server Computation algorithm, paper §5): for each, g-1
  * baby-step rotations, then per chunk the giant-step sums of plaintext
  * products combined by h-1 giant rotations.  q: host array of descriptors
- * with device pointers.  `path` selects WALLY_PATH_BATCHED or
- * WALLY_PATH_PLAIN; both give identical words.  Work is enqueued on
- * hip_stream (a hipStream_t; NULL = default stream) and the call returns once
- * it is enqueued; output is independent of batch composition.  Validation
- * errors are reported before anything is enqueued (EINVAL). */
+ * with device pointers.  `path`: WALLY_PATH_BATCHED (waves of queries of all
+ * clusters), WALLY_PATH_PLAIN (one launch sequence per cluster) or
+ * WALLY_PATH_GRAPH (the batched launches of the whole batch captured once in
+ * a hipGraph and replayed while the same query array and configuration are
+ * passed again); all give identical words.  Work is enqueued on hip_stream (a
+ * hipStream_t; NULL = default stream) and the call returns once it is
+ * enqueued; output is independent of batch composition.  Validation errors
+ * are reported before anything is enqueued (EINVAL); ESTATE while serving. */
 int wally_score_batch(wally_ctx* ctx, const wally_query* q, uint64_t nq, int path, void* hip_stream);
+
+/* One configuration timed by wally_tune. */
+typedef struct {
+  uint32_t max_batch;  /* queries per wave                                  */
+  uint32_t wave_sets;  /* waves in flight (one stream each)                 */
+  uint32_t tile_items; /* queries sharing one plaintext chunk per sum tile  */
+  double ms;           /* time of one batched call                          */
+} wally_tune_entry;
+
+/* Schedule autotuner: times wally_score_batch (batched path) on the caller's
+ * queries for every combination of the candidate wave sizes, wave-stream
+ * counts and plaintext-tile sizes (0-terminated lists; NULL or empty keeps
+ * the current value), keeps the fastest for this context and writes every
+ * timing to out[0..*n_out).  Synchronous; the outputs of the queries are
+ * written (several times). */
+int wally_tune(wally_ctx* ctx, const wally_query* q, uint64_t nq, const uint32_t* batches, const uint32_t* sets,
+               const uint32_t* tiles, wally_tune_entry* out, uint32_t max_out, uint32_t* n_out);
 
 /* Serving (continuous batching).  start: begin accepting work on hip_stream.
  * submit: non-blocking; EAGAIN when the in-flight budget is full (retry

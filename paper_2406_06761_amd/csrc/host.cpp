@@ -20,9 +20,6 @@
 using namespace wally;
 typedef unsigned __int128 u128;
 
-// giant items per plaintext-sharing tile of the sum kernel
-static constexpr uint32_t kTileItems = 16;
-
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -150,6 +147,14 @@ struct wally_ctx {
   // waves
   int B = 0;
   int n_sets = 2;
+  uint32_t tile_items = 16;  // giant items per plaintext-sharing tile of the sum kernel
+  // graph path: one captured graph of a whole batch, replayed while the batch
+  // (the query array) and the configuration stay the same
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  uint64_t graph_key = 0;
+  void* graph_desc = nullptr;  // device descriptors of the captured batch
+  bool capturing = false;
   std::vector<WaveWork> sets;
   hipEvent_t fork = nullptr;
   std::string err;
@@ -238,7 +243,7 @@ hipEvent_t pool_event(wally_ctx* c) {
 // Launch through `fn`, bracketed by timing events on `st` when timing is on.
 template <class F>
 hipError_t timed(wally_ctx* c, hipStream_t st, int kernel, uint64_t items, F fn) {
-  if (!c->timing) return fn();
+  if (!c->timing || c->capturing) return fn();
   hipEvent_t a = pool_event(c), b = pool_event(c);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, st);
@@ -258,7 +263,16 @@ hipError_t keyswitch(wally_ctx* c, const KsItem* items, int n, const KsArgs& a, 
   return e;
 }
 
+void drop_graph(wally_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  c->graph_exec = nullptr;
+  c->graph_key = 0;
+  dfree(c, c->graph_desc);
+  c->graph_desc = nullptr;
+}
+
 void free_sets(wally_ctx* c) {
+  drop_graph(c);
   for (auto& s : c->sets) {
     if (s.stream) (void)hipStreamSynchronize(s.stream);
     dfree(c, s.ctp);
@@ -334,18 +348,25 @@ KsArgs base_args(const wally_ctx* c, const WaveWork& s) {
 
 // Enqueue the whole scoring of one wave (queries qs[0..w)) on set s.
 // All queries must already be validated.
-int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w) {
+// Descriptors of one wave: copy and baby items per query, giant items per
+// (query, chunk) ordered by plaintext chunk, tiles of giant items sharing a
+// chunk, split in sub-waves of at most B giant items.
+struct WavePlan {
+  int w = 0;
+  size_t ng = 0, nt = 0;
+  std::vector<std::pair<size_t, size_t>> sub_tiles;  // per sub-wave: [first tile, end tile)
+};
+
+void plan_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w, CopyItem* copy, KsItem* baby,
+               KsItem* giant, MacTile* tiles, WavePlan& p) {
   const uint64_t ctw = c->ctw(), ptw = c->ptw();
-  // host descriptors may be rewritten only after the previous copy landed
-  HIP_OK(c, hipEventSynchronize(s.staged));
-  // giant items (query, chunk), ordered by plaintext chunk so tiles share it
   std::vector<std::pair<uint64_t, uint32_t>> order;  // (global chunk index, item)
   std::vector<std::pair<int, uint32_t>> gq;           // (query slot, chunk)
   for (int k = 0; k < w; ++k) {
     const wally_query& q = *qs[k];
     uint64_t* ctp = s.ctp + (uint64_t)k * c->g * ctw;
-    s.copy_host[k] = CopyItem{q.ct, ctp};
-    s.baby_host[k] = KsItem{q.key_baby, ctp, nullptr, nullptr, nullptr, nullptr, nullptr};
+    copy[k] = CopyItem{q.ct, ctp};
+    baby[k] = KsItem{q.key_baby, ctp, nullptr, nullptr, nullptr, nullptr, nullptr};
     for (uint32_t ch = 0; ch < c->chunks[q.cluster]; ++ch) {
       order.push_back({c->chunk_base[q.cluster] + ch, (uint32_t)gq.size()});
       gq.push_back({k, ch});
@@ -355,13 +376,13 @@ int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w)
                    [](const std::pair<uint64_t, uint32_t>& a, const std::pair<uint64_t, uint32_t>& b) {
                      return a.first < b.first;
                    });
-  const size_t ng = order.size();
-  // sub-waves of up to B giant items; slot = position inside the sub-wave
-  size_t nt = 0;
-  std::vector<std::pair<size_t, size_t>> sub_tiles;  // per sub-wave: [first tile, end tile)
-  for (size_t g0 = 0; g0 < ng; g0 += c->B) {
-    const size_t g1 = std::min(ng, g0 + (size_t)c->B);
-    const size_t t0 = nt;
+  p.w = w;
+  p.ng = order.size();
+  p.nt = 0;
+  p.sub_tiles.clear();
+  for (size_t g0 = 0; g0 < p.ng; g0 += c->B) {
+    const size_t g1 = std::min(p.ng, g0 + (size_t)c->B);
+    const size_t t0 = p.nt;
     for (size_t k = g0; k < g1; ++k) {
       const auto& gi = gq[order[k].second];
       const wally_query& q = *qs[gi.first];
@@ -374,22 +395,23 @@ int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w)
       it.buf0 = s.R0 + slot * ctw;
       it.buf1 = s.R1 + slot * ctw;
       it.acc = c->h == 1 ? it.fin : s.ACC + slot * c->h * ctw;
-      s.giant_host[k] = it;
-      // tiles: runs of one plaintext chunk, at most kTileItems items, inside the sub-wave
-      const bool start = k == g0 || order[k].first != order[k - 1].first || s.tile_host[nt - 1].count >= kTileItems;
-      if (start) s.tile_host[nt++] = MacTile{(uint32_t)(k - g0), 0};
-      s.tile_host[nt - 1].count++;
+      giant[k] = it;
+      const bool start = k == g0 || order[k].first != order[k - 1].first || tiles[p.nt - 1].count >= c->tile_items;
+      if (start) tiles[p.nt++] = MacTile{(uint32_t)(k - g0), 0};
+      tiles[p.nt - 1].count++;
     }
-    sub_tiles.push_back({t0, nt});
+    p.sub_tiles.push_back({t0, p.nt});
   }
-  HIP_OK(c, hipMemcpyAsync(s.copy_dev, s.copy_host, w * sizeof(CopyItem), hipMemcpyHostToDevice, s.stream));
-  HIP_OK(c, hipMemcpyAsync(s.baby_dev, s.baby_host, w * sizeof(KsItem), hipMemcpyHostToDevice, s.stream));
-  HIP_OK(c, hipMemcpyAsync(s.giant_dev, s.giant_host, ng * sizeof(KsItem), hipMemcpyHostToDevice, s.stream));
-  HIP_OK(c, hipMemcpyAsync(s.tile_dev, s.tile_host, nt * sizeof(MacTile), hipMemcpyHostToDevice, s.stream));
-  HIP_OK(c, hipEventRecord(s.staged, s.stream));
+}
 
+// Enqueue the kernels of a planned wave on stream st, reading the
+// descriptors from device memory.
+int launch_wave(wally_ctx* c, WaveWork& s, const WavePlan& p, const CopyItem* copy, const KsItem* baby,
+                const KsItem* giant, const MacTile* tiles, hipStream_t st) {
+  const uint64_t ctw = c->ctw();
+  const int w = p.w;
   // baby steps: ct'_0 = ct, ct'_j = Rot(ct'_{j-1}, 1)
-  HIP_OK(c, timed(c, s.stream, WALLY_KERNEL_COPY, w, [&] { return launch_copy_ct(s.copy_dev, w, ctw, s.stream); }));
+  HIP_OK(c, timed(c, st, WALLY_KERNEL_COPY, w, [&] { return launch_copy_ct(copy, w, ctw, st); }));
   for (int j = 1; j < c->g; ++j) {
     KsArgs a = base_args(c, s);
     a.gal = c->gal_baby;
@@ -397,19 +419,18 @@ int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w)
     a.in_off = (uint64_t)(j - 1) * ctw;
     a.out_sel = 0;
     a.out_off = (uint64_t)j * ctw;
-    HIP_OK(c, keyswitch(c, s.baby_dev, w, a, s.stream));
+    HIP_OK(c, keyswitch(c, baby, w, a, st));
   }
   // giant steps per (query, chunk): acc_i for all i, then
   // R = acc_{h-1}; R = acc_i + Rot(R, g) for i = h-2 .. 0
-  for (size_t sw = 0; sw < sub_tiles.size(); ++sw) {
+  for (size_t sw = 0; sw < p.sub_tiles.size(); ++sw) {
     const size_t g0 = sw * (size_t)c->B;
-    const int cnt = (int)std::min<size_t>(c->B, ng - g0);
-    const KsItem* items = s.giant_dev + g0;
-    const MacTile* tiles = s.tile_dev + sub_tiles[sw].first;
-    const int ntile = (int)(sub_tiles[sw].second - sub_tiles[sw].first);
+    const int cnt = (int)std::min<size_t>(c->B, p.ng - g0);
+    const KsItem* items = giant + g0;
+    const MacTile* tl = tiles + p.sub_tiles[sw].first;
+    const int ntile = (int)(p.sub_tiles[sw].second - p.sub_tiles[sw].first);
     KsArgs a = base_args(c, s);
-    HIP_OK(c, timed(c, s.stream, WALLY_KERNEL_MAC, cnt,
-                    [&] { return launch_mac_tiles(items, tiles, ntile, a, c->h, c->M, s.stream); }));
+    HIP_OK(c, timed(c, st, WALLY_KERNEL_MAC, cnt, [&] { return launch_mac_tiles(items, tl, ntile, a, c->h, c->M, st); }));
     int cur = 3;  // acc
     uint64_t cur_off = (uint64_t)(c->h - 1) * ctw;
     int next = 0;
@@ -420,12 +441,28 @@ int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w)
       b.in_off = cur_off;
       b.out_sel = i == 0 ? 2 : next;
       b.giant = i;
-      HIP_OK(c, keyswitch(c, items, cnt, b, s.stream));
+      HIP_OK(c, keyswitch(c, items, cnt, b, st));
       cur = next;
       cur_off = 0;
       next = 1 - next;
     }
   }
+  return WALLY_OK;
+}
+
+// Eager path: plan into the set's pinned buffers, copy, launch on its stream.
+int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w) {
+  // host descriptors may be rewritten only after the previous copy landed
+  HIP_OK(c, hipEventSynchronize(s.staged));
+  WavePlan p;
+  plan_wave(c, s, qs, w, s.copy_host, s.baby_host, s.giant_host, s.tile_host, p);
+  HIP_OK(c, hipMemcpyAsync(s.copy_dev, s.copy_host, w * sizeof(CopyItem), hipMemcpyHostToDevice, s.stream));
+  HIP_OK(c, hipMemcpyAsync(s.baby_dev, s.baby_host, w * sizeof(KsItem), hipMemcpyHostToDevice, s.stream));
+  HIP_OK(c, hipMemcpyAsync(s.giant_dev, s.giant_host, p.ng * sizeof(KsItem), hipMemcpyHostToDevice, s.stream));
+  HIP_OK(c, hipMemcpyAsync(s.tile_dev, s.tile_host, p.nt * sizeof(MacTile), hipMemcpyHostToDevice, s.stream));
+  HIP_OK(c, hipEventRecord(s.staged, s.stream));
+  int rc = launch_wave(c, s, p, s.copy_dev, s.baby_dev, s.giant_dev, s.tile_dev, s.stream);
+  if (rc) return rc;
   HIP_OK(c, hipEventRecord(s.done, s.stream));
   return WALLY_OK;
 }
@@ -675,30 +712,129 @@ int wally_cluster_info(const wally_ctx* c, uint32_t cl, uint32_t* n_chunks, cons
   return WALLY_OK;
 }
 
-int wally_score_batch(wally_ctx* c, const wally_query* q, uint64_t nq, int path, void* hip_stream) {
-  int rc = check_live(c);
-  if (rc) return rc;
-  std::lock_guard<std::mutex> lk(c->mu);
-  if (c->K == 0) return set_err(c, WALLY_ESTATE, "no clusters encoded");
-  if (path != WALLY_PATH_BATCHED && path != WALLY_PATH_PLAIN) return set_err(c, WALLY_EINVAL, "unknown path %d", path);
-  if (nq == 0) return WALLY_OK;
-  if (!q) return set_err(c, WALLY_EINVAL, "null query array");
-  for (uint64_t i = 0; i < nq; ++i)
-    if ((rc = validate_query(c, q[i], i))) return rc;
-  if ((rc = ensure_sets(c))) return rc;
-  hipStream_t user = (hipStream_t)hip_stream;
-  // order queries by cluster so a wave touches few plaintext chunks
-  std::vector<const wally_query*> ord(nq);
+}  // extern "C"
+
+namespace {
+
+uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* p = (const unsigned char*)data;
+  for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+  return h;
+}
+
+// Queries ordered by cluster (so a wave touches few plaintext chunks) and cut
+// into waves: up to B queries, of one cluster only on the plain path.
+void make_waves(wally_ctx* c, const wally_query* q, uint64_t nq, int path, std::vector<const wally_query*>& ord,
+                std::vector<std::pair<uint64_t, uint64_t>>& waves) {
+  ord.resize(nq);
   for (uint64_t i = 0; i < nq; ++i) ord[i] = &q[i];
   std::stable_sort(ord.begin(), ord.end(), [](const wally_query* a, const wally_query* b) { return a->cluster < b->cluster; });
-  // waves
-  std::vector<std::pair<uint64_t, uint64_t>> waves;
+  waves.clear();
   for (uint64_t i = 0; i < nq;) {
     uint64_t j = i;
-    while (j < nq && j - i < (uint64_t)c->B && (path == WALLY_PATH_BATCHED || ord[j]->cluster == ord[i]->cluster)) ++j;
+    while (j < nq && j - i < (uint64_t)c->B && (path != WALLY_PATH_PLAIN || ord[j]->cluster == ord[i]->cluster)) ++j;
     waves.push_back({i, j});
     i = j;
   }
+}
+
+// Graph path: descriptors of every wave in one device block, the whole batch
+// (fork, waves on the set streams, join) captured into one graph.
+int build_graph(wally_ctx* c, const std::vector<const wally_query*>& ord,
+                const std::vector<std::pair<uint64_t, uint64_t>>& waves) {
+  drop_graph(c);
+  const size_t nw = waves.size();
+  std::vector<WavePlan> plans(nw);
+  // sizes: copy/baby per query, giant/tile per (query, chunk)
+  size_t nq = ord.size(), ng = 0;
+  for (const wally_query* q : ord) ng += c->chunks[q->cluster];
+  const size_t bytes = nq * sizeof(CopyItem) + nq * sizeof(KsItem) + ng * sizeof(KsItem) + ng * sizeof(MacTile) + 256;
+  std::vector<unsigned char> host(bytes);
+  CopyItem* copy_h = (CopyItem*)host.data();
+  KsItem* baby_h = (KsItem*)(copy_h + nq);
+  KsItem* giant_h = baby_h + nq;
+  MacTile* tile_h = (MacTile*)(giant_h + ng);
+  int rc = dalloc(c, bytes, &c->graph_desc);
+  if (rc) return rc;
+  unsigned char* dbase = (unsigned char*)c->graph_desc;
+  std::vector<size_t> qoff(nw), goff(nw), toff(nw);
+  size_t qo = 0, go = 0, to = 0;
+  for (size_t wv = 0; wv < nw; ++wv) {
+    WaveWork& s = c->sets[wv % c->sets.size()];
+    const int w = (int)(waves[wv].second - waves[wv].first);
+    qoff[wv] = qo;
+    goff[wv] = go;
+    toff[wv] = to;
+    plan_wave(c, s, ord.data() + waves[wv].first, w, copy_h + qo, baby_h + qo, giant_h + go, tile_h + to, plans[wv]);
+    qo += w;
+    go += plans[wv].ng;
+    to += plans[wv].nt;
+  }
+  HIP_OK(c, hipMemcpy(dbase, host.data(), bytes, hipMemcpyHostToDevice));
+  const CopyItem* copy_d = (const CopyItem*)dbase;
+  const KsItem* baby_d = (const KsItem*)(copy_d + nq);
+  const KsItem* giant_d = baby_d + nq;
+  const MacTile* tile_d = (const MacTile*)(giant_d + ng);
+  if (!c->cap_stream) HIP_OK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIP_OK(c, hipStreamSynchronize(c->cap_stream));
+  for (auto& s : c->sets) HIP_OK(c, hipStreamSynchronize(s.stream));
+  HIP_OK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
+  rc = WALLY_OK;
+  hipError_t e = hipEventRecord(c->fork, c->cap_stream);
+  for (size_t k = 0; e == hipSuccess && k < c->sets.size(); ++k) e = hipStreamWaitEvent(c->sets[k].stream, c->fork, 0);
+  for (size_t wv = 0; e == hipSuccess && !rc && wv < nw; ++wv) {
+    WaveWork& s = c->sets[wv % c->sets.size()];
+    rc = launch_wave(c, s, plans[wv], copy_d + qoff[wv], baby_d + qoff[wv], giant_d + goff[wv], tile_d + toff[wv],
+                     s.stream);
+  }
+  for (size_t k = 0; e == hipSuccess && !rc && k < c->sets.size(); ++k) {
+    e = hipEventRecord(c->sets[k].done, c->sets[k].stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->cap_stream, c->sets[k].done, 0);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
+  c->capturing = false;
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess || e2 != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return set_err(c, WALLY_EDEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  e = hipGraphInstantiate(&c->graph_exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return set_err(c, WALLY_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+  return WALLY_OK;
+}
+
+int score_locked(wally_ctx* c, const wally_query* q, uint64_t nq, int path, hipStream_t user) {
+  int rc;
+  for (uint64_t i = 0; i < nq; ++i)
+    if ((rc = validate_query(c, q[i], i))) return rc;
+  if ((rc = ensure_sets(c))) return rc;
+  if (path == WALLY_PATH_GRAPH) {
+    uint64_t key = fnv1a(q, nq * sizeof(wally_query));
+    key = fnv1a(&c->B, sizeof c->B, key);
+    key = fnv1a(&c->tile_items, sizeof c->tile_items, key);
+    key ^= (uint64_t)c->sets.size() << 56;
+    if (!c->graph_exec || c->graph_key != key) {
+      std::vector<const wally_query*> ord;
+      std::vector<std::pair<uint64_t, uint64_t>> waves;
+      make_waves(c, q, nq, WALLY_PATH_BATCHED, ord, waves);
+      if ((rc = build_graph(c, ord, waves))) return rc;
+      c->graph_key = key;
+    }
+    // earlier eager work on the set streams shares the workspaces
+    for (auto& s : c->sets) HIP_OK(c, hipStreamWaitEvent(user, s.done, 0));
+    HIP_OK(c, hipGraphLaunch(c->graph_exec, user));
+    // later eager work forks from the user stream, so it runs after the graph
+    return WALLY_OK;
+  }
+  std::vector<const wally_query*> ord;
+  std::vector<std::pair<uint64_t, uint64_t>> waves;
+  make_waves(c, q, nq, path, ord, waves);
   // fork: every set stream waits for the caller's stream
   HIP_OK(c, hipEventRecord(c->fork, user));
   for (auto& s : c->sets) HIP_OK(c, hipStreamWaitEvent(s.stream, c->fork, 0));
@@ -713,6 +849,82 @@ int wally_score_batch(wally_ctx* c, const wally_query* q, uint64_t nq, int path,
   }
   return WALLY_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int wally_score_batch(wally_ctx* c, const wally_query* q, uint64_t nq, int path, void* hip_stream) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->K == 0) return set_err(c, WALLY_ESTATE, "no clusters encoded");
+  if (c->serving) return set_err(c, WALLY_ESTATE, "a serving session owns the workspaces");
+  if (path != WALLY_PATH_BATCHED && path != WALLY_PATH_PLAIN && path != WALLY_PATH_GRAPH)
+    return set_err(c, WALLY_EINVAL, "unknown path %d", path);
+  if (nq == 0) return WALLY_OK;
+  if (!q) return set_err(c, WALLY_EINVAL, "null query array");
+  return score_locked(c, q, nq, path, (hipStream_t)hip_stream);
+}
+
+int wally_tune(wally_ctx* c, const wally_query* q, uint64_t nq, const uint32_t* batches, const uint32_t* sets,
+               const uint32_t* tiles, wally_tune_entry* out, uint32_t max_out, uint32_t* n_out) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->K == 0) return set_err(c, WALLY_ESTATE, "no clusters encoded");
+  if (c->serving) return set_err(c, WALLY_ESTATE, "cannot tune while serving");
+  if (!q || nq == 0) return set_err(c, WALLY_EINVAL, "empty query array");
+  if (n_out) *n_out = 0;
+  const uint32_t cur_b[2] = {(uint32_t)c->B, 0}, cur_s[2] = {(uint32_t)c->n_sets, 0}, cur_t[2] = {c->tile_items, 0};
+  if (!batches || !batches[0]) batches = cur_b;
+  if (!sets || !sets[0]) sets = cur_s;
+  if (!tiles || !tiles[0]) tiles = cur_t;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_OK(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  HIP_OK(c, hipEventCreate(&e0));
+  HIP_OK(c, hipEventCreate(&e1));
+  const bool timing = c->timing;
+  c->timing = false;
+  double best = 1e300;
+  uint32_t bb = c->B, bs = c->n_sets, bt = c->tile_items, k = 0;
+  for (const uint32_t* pb = batches; *pb && !rc; ++pb)
+    for (const uint32_t* ps = sets; *ps && !rc; ++ps)
+      for (const uint32_t* pt = tiles; *pt && !rc; ++pt) {
+        free_sets(c);
+        c->B = (int)*pb;
+        c->n_sets = (int)std::min<uint32_t>(*ps, 8);
+        c->tile_items = *pt;
+        // warm-up (allocates the workspaces), then one timed batch
+        if ((rc = score_locked(c, q, nq, WALLY_PATH_BATCHED, st))) break;
+        hipError_t e = hipEventRecord(e0, st);
+        if (e == hipSuccess) rc = score_locked(c, q, nq, WALLY_PATH_BATCHED, st);
+        if (!rc && e == hipSuccess) e = hipEventRecord(e1, st);
+        if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) rc = set_err(c, WALLY_EDEVICE, "tuning run failed: %s", hipGetErrorString(e));
+        if (rc) break;
+        if (out && k < max_out) out[k] = wally_tune_entry{*pb, (uint32_t)c->n_sets, *pt, (double)ms};
+        ++k;
+        if (ms < best) best = ms, bb = *pb, bs = (uint32_t)c->n_sets, bt = *pt;
+      }
+  if (n_out) *n_out = std::min(k, max_out);
+  free_sets(c);
+  c->B = (int)bb;
+  c->n_sets = (int)bs;
+  c->tile_items = bt;
+  c->timing = timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(st);
+  return rc;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 // ---------------------------------------------------------------------------
 // serving: continuous batching over the workspace sets.  A wave is launched
@@ -824,6 +1036,7 @@ void wally_destroy(wally_ctx* c) {
   free_sets(c);
   while (!c->allocs.empty()) dfree(c, c->allocs.back().first);
   if (c->fork) (void)hipEventDestroy(c->fork);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto& t : c->timers) c->ev_pool.push_back(t.a), c->ev_pool.push_back(t.b);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;

@@ -16,7 +16,7 @@ HERE = Path(__file__).resolve().parent
 LIB_PATH = HERE / "libwally.so"
 
 OK, EINVAL, ENOMEM, EAGAIN, EPENDING, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5, -6
-PATH_BATCHED, PATH_PLAIN = 0, 1
+PATH_BATCHED, PATH_PLAIN, PATH_GRAPH = 0, 1, 2
 LAYOUT_PER_CLUSTER = 0
 
 QUERY_DTYPE = np.dtype([("cluster", "<u4"), ("reserved", "<u4"), ("ct", "<u8"), ("key_baby", "<u8"),
@@ -55,12 +55,18 @@ assert ctypes.sizeof(Query) == QUERY_DTYPE.itemsize
 # every symbol declared in include/wally.h and include/wally_diag.h
 SYMBOLS = [
     "wally_params_init", "wally_params_query", "wally_encode_clusters", "wally_cluster_info", "wally_score_batch",
+    "wally_tune",
     "wally_serve_start", "wally_serve_submit", "wally_serve_poll", "wally_serve_stop", "wally_strerror",
     "wally_last_error", "wally_destroy", "wally_diag_ntt", "wally_diag_rotate", "wally_diag_kernel_timing",
     "wally_diag_kernel_stats",
 ]
 
 KERNELS = ["ks_digits", "ks_extend", "ks_inner", "ks_pinv", "ks_moddown", "mac", "copy_ct"]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_uint32), ("wave_sets", ctypes.c_uint32), ("tile_items", ctypes.c_uint32),
+                ("ms", ctypes.c_double)]
 
 
 class KernelStat(ctypes.Structure):
@@ -88,6 +94,7 @@ def load():
         "wally_encode_clusters": ([vp, vp, u64, vp, u32], i32),
         "wally_cluster_info": ([vp, u32, ctypes.POINTER(u32), ctypes.POINTER(vp)], i32),
         "wally_score_batch": ([vp, vp, u64, i32, vp], i32),
+        "wally_tune": ([vp, vp, u64, vp, vp, vp, ctypes.POINTER(TuneEntry), u32, ctypes.POINTER(u32)], i32),
         "wally_serve_start": ([vp, vp], i32),
         "wally_serve_submit": ([vp, ctypes.POINTER(Query), ctypes.POINTER(u64)], i32),
         "wally_serve_poll": ([vp, ctypes.POINTER(u64), u32, ctypes.POINTER(u32)], i32),
@@ -174,6 +181,23 @@ class Context:
         queries = np.ascontiguousarray(queries, dtype=QUERY_DTYPE)
         self._check(self.lib.wally_score_batch(self.h, queries.ctypes.data, len(queries), path,
                                                _stream_handle(stream)), "wally_score_batch")
+
+    def tune(self, queries: np.ndarray, batches=(), sets=(), tiles=()):
+        """Autotune the batched schedule on these queries; returns the timings
+        [(max_batch, wave_sets, tile_items, ms)] (the fastest is kept)."""
+        queries = np.ascontiguousarray(queries, dtype=QUERY_DTYPE)
+
+        def arr(v):
+            a = (ctypes.c_uint32 * (len(v) + 1))(*v, 0)
+            return ctypes.cast(a, ctypes.c_void_p), a
+
+        (pb, kb), (ps, ks), (pt, kt) = arr(batches), arr(sets), arr(tiles)
+        cap = max(1, len(batches)) * max(1, len(sets)) * max(1, len(tiles))
+        out = (TuneEntry * cap)()
+        n = ctypes.c_uint32()
+        self._check(self.lib.wally_tune(self.h, queries.ctypes.data, len(queries), pb, ps, pt, out, cap,
+                                        ctypes.byref(n)), "wally_tune")
+        return [(e.max_batch, e.wave_sets, e.tile_items, e.ms) for e in out[: n.value]]
 
     def serve_start(self, stream=None):
         self._check(self.lib.wally_serve_start(self.h, _stream_handle(stream)), "wally_serve_start")

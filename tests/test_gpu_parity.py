@@ -167,3 +167,67 @@ def test_tiny_end_to_end(tiny_workload, path, max_batch):
             assert (dec[: len(rows)] == (rows @ qv[i].astype(np.int64)) % o.p.t).all()
     finally:
         c.close()
+
+
+def _tiny_queries(o, w, packets):
+    from paper_2406_06761_amd.wally import query_array, to_device
+
+    nq = len(w.targets)
+    cts = to_device(np.stack([pk[0] for pk in packets]))
+    kbs = to_device(np.stack([pk[1] for pk in packets]))
+    kgs = to_device(np.stack([pk[2] for pk in packets]))
+    outs = torch.zeros((nq, 1, 2, o.L, o.n), dtype=torch.int64, device="cuda")
+    q = query_array(w.targets, [cts[i].data_ptr() for i in range(nq)], [kbs[i].data_ptr() for i in range(nq)],
+                    [kgs[i].data_ptr() for i in range(nq)], [outs[i].data_ptr() for i in range(nq)])
+    return q, outs, (cts, kbs, kgs)
+
+
+def test_graph_replays_match_eager(tiny_workload):
+    """The captured batch replayed several times, with eager work and
+    synchronisations in between, gives the eager words every time."""
+    from paper_2406_06761_amd.wally import PATH_BATCHED, PATH_GRAPH, to_host
+
+    o, w, emb, offs, qv, packets, ref = tiny_workload
+    c = _ctx("tiny", max_batch=5, wave_sets=2)
+    try:
+        c.encode_clusters(emb, offs)
+        q, outs, keep = _tiny_queries(o, w, packets)
+        c.score_batch(q, path=PATH_BATCHED)
+        torch.cuda.synchronize()
+        eager = to_host(outs).copy()
+        for i in range(len(w.targets)):
+            assert (eager[i] == ref[i]).all(), i
+        for rep in range(3):
+            outs.zero_()  # eager work between replays
+            torch.cuda.synchronize()
+            c.score_batch(q, path=PATH_GRAPH)
+            torch.cuda.synchronize()
+            assert (to_host(outs) == eager).all(), rep
+        # eager again after the graph, then the graph again
+        outs.zero_()
+        c.score_batch(q, path=PATH_BATCHED)
+        c.score_batch(q, path=PATH_GRAPH)
+        torch.cuda.synchronize()
+        assert (to_host(outs) == eager).all()
+    finally:
+        c.close()
+
+
+def test_tuner_picks_a_config_and_stays_exact(tiny_workload):
+    from paper_2406_06761_amd.wally import PATH_BATCHED, to_host
+
+    o, w, emb, offs, qv, packets, ref = tiny_workload
+    c = _ctx("tiny", max_batch=16)
+    try:
+        c.encode_clusters(emb, offs)
+        q, outs, keep = _tiny_queries(o, w, packets)
+        res = c.tune(q, batches=(4, 16), sets=(1, 2), tiles=(4, 16))
+        assert len(res) == 8 and all(r[3] > 0 for r in res)
+        outs.zero_()
+        c.score_batch(q, path=PATH_BATCHED)
+        torch.cuda.synchronize()
+        got = to_host(outs)
+        for i in range(len(w.targets)):
+            assert (got[i] == ref[i]).all(), i
+    finally:
+        c.close()
