@@ -355,7 +355,7 @@ def main():
                    "params": f"n={n}, L={L} x {54 if n == 8192 else 36}-bit limbs, t={info.t}",
                    "queries": nq, "real_queries": w.n_real, "scores_per_step": scores,
                    "real_scores_per_step": real_scores, "pool_packets": pool,
-                   "max_batch": args.max_batch or 1024, "wave_sets": args.wave_sets or 2,
+                   "max_batch": args.max_batch or 512, "wave_sets": args.wave_sets or 2,
                    "schedule": (tuned or {}).get("chosen")},
         "real_scores_per_s": real_scores * args.steps / dt,
         "queries_per_s": nq * args.steps / dt,

@@ -63,7 +63,7 @@ typedef struct {
   uint32_t dim;        /* embedding dimension d                             */
   uint32_t layout;     /* WALLY_LAYOUT_PER_CLUSTER                          */
   int32_t device;      /* HIP device ordinal                                */
-  uint32_t max_batch;  /* queries resident per wave (0 = library default)   */
+  uint32_t max_batch;  /* queries resident per wave (0 = 512)                */
   uint32_t wave_sets;  /* waves in flight on separate streams (0 = 2)       */
   uint32_t reserved;   /* must be 0                                         */
   uint64_t hbm_budget; /* bytes the context may allocate (0 = 90% of free)  */

@@ -147,7 +147,7 @@ struct wally_ctx {
   // waves
   int B = 0;
   int n_sets = 2;
-  uint32_t tile_items = 16;  // giant items per plaintext-sharing tile of the sum kernel
+  uint32_t tile_items = 8;  // giant items per plaintext-sharing tile of the sum kernel
   // graph path: one captured graph of a whole batch, replayed while the batch
   // (the query array) and the configuration stay the same
   hipStream_t cap_stream = nullptr;
@@ -555,7 +555,7 @@ int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
     return WALLY_EDEVICE;
   }
   c->budget = desc->hbm_budget ? desc->hbm_budget : (uint64_t)(free_b * 0.9);
-  c->B = desc->max_batch ? (int)desc->max_batch : 1024;
+  c->B = desc->max_batch ? (int)desc->max_batch : 512;
   c->n_sets = desc->wave_sets ? (int)desc->wave_sets : 2;
   if (c->n_sets > 8) c->n_sets = 8;
 

@@ -29,12 +29,43 @@
 
 namespace wally {
 
-__device__ __forceinline__ const uint64_t* sel_in(const KsItem& it, int sel, uint64_t off) {
-  return sel == 0 ? it.buf0 + off : (sel == 1 ? it.buf1 + off : (sel == 2 ? it.fin + off : it.acc + off));
+// The selector is uniform; the chosen field is read straight from the item in
+// global memory (a dynamic pick from a register copy of the item would be
+// lowered to a stack array in scratch memory).
+__device__ __forceinline__ const uint64_t* sel_in(const KsItem* it, int sel, uint64_t off) {
+  const uint64_t* r;
+  switch (sel) {
+    case 0: r = it->buf0; break;
+    case 1: r = it->buf1; break;
+    case 2: r = it->fin; break;
+    default: r = it->acc; break;
+  }
+  return r + off;
 }
-__device__ __forceinline__ uint64_t* sel_out(const KsItem& it, int sel, uint64_t off) {
-  return sel == 0 ? it.buf0 + off : (sel == 1 ? it.buf1 + off : it.fin + off);
+__device__ __forceinline__ uint64_t* sel_out(const KsItem* it, int sel, uint64_t off) {
+  uint64_t* r;
+  switch (sel) {
+    case 0: r = it->buf0; break;
+    case 1: r = it->buf1; break;
+    default: r = it->fin; break;
+  }
+  return r + off;
 }
+
+// XCD-aware placement. The work-groups of a launch go to the eight XCDs round
+// robin (block id mod 8) and each XCD has its own L2. Where a launch has groups
+// of `per` blocks that read the same input row, a group's members get ids that
+// are congruent mod 8 and consecutive on that XCD, id = 8 (per s + k) + x for
+// member k of group 8 s + x, so the row comes from HBM once and from L2 after.
+constexpr uint32_t kXcds = 8;
+struct GroupSlot {
+  uint32_t group, member;
+};
+__device__ __forceinline__ GroupSlot xcd_group(uint32_t id, uint32_t per) {
+  const uint32_t x = id % kXcds, r = id / kXcds;
+  return {(r / per) * kXcds + x, r % per};
+}
+inline uint32_t xcd_blocks(uint32_t groups, uint32_t per) { return (groups + kXcds - 1) / kXcds * kXcds * per; }
 
 // ---------------------------------------------------------------------------
 // key switching, step 1: digits
@@ -47,8 +78,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_digits(const K
   __shared__ uint64_t lds[S::LDS_WORDS];
   const int tid = threadIdx.x;
   const int b = blockIdx.x, i = blockIdx.y;
-  const KsItem it = items[b];
-  const uint64_t* c1 = sel_in(it, a.in_sel, a.in_off) + ((uint64_t)a.L + i) * S::N;
+  const uint64_t* c1 = sel_in(items + b, a.in_sel, a.in_off) + ((uint64_t)a.L + i) * S::N;
   const uint64_t q = M.q[i];
   uint64_t x[S::E];
   gather_galois<LOGN, LOGE, LastMap<LOGN, LOGE>>(x, c1, lds, a.gal, tid);  // sigma(c1)_i, INTT input order
@@ -61,21 +91,23 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_digits(const K
 // ---------------------------------------------------------------------------
 // key switching, step 2: extended digits D[m][i] = NTT_m(x_i mod m); for
 // i = m the extended digit is sigma(c1)_m itself (a permuted copy).
-// grid (items, (L+1) * L), blockIdx.y = m * L + i; block T
+// 1-D grid of xcd_blocks(items * L, L + 1): group (b, i) reads digit x_i of
+// item b, its L + 1 members are the target moduli m; block T
 template <int LOGN, int LOGE>
 __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const KsItem* __restrict__ items, KsArgs a,
-                                                                         DevModuli M) {
+                                                                         int n_items, DevModuli M) {
   using S = NttShape<LOGN, LOGE>;
   using FM = FirstMap<LOGN, LOGE>;
   __shared__ uint64_t lds[S::LDS_WORDS];
   const int tid = threadIdx.x;
-  const int b = blockIdx.x, m = blockIdx.y / a.L, i = blockIdx.y % a.L;
   const int L = a.L;
+  const GroupSlot gs = xcd_group(blockIdx.x, L + 1);
+  if (gs.group >= (uint32_t)(n_items * L)) return;  // padding block (whole block, before any barrier)
+  const int b = gs.group / L, i = gs.group % L, m = gs.member;
   uint64_t* D = a.D + (((uint64_t)b * (L + 1) + m) * L + i) * S::N;
   uint64_t d[S::E];
   if (i == m) {
-    const KsItem it = items[b];
-    gather_galois<LOGN, LOGE, FM>(d, sel_in(it, a.in_sel, a.in_off) + ((uint64_t)L + m) * S::N, lds, a.gal, tid);
+    gather_galois<LOGN, LOGE, FM>(d, sel_in(items + b, a.in_sel, a.in_off) + ((uint64_t)L + m) * S::N, lds, a.gal, tid);
 #pragma unroll
     for (int e = 0; e < S::E; ++e) D[FM::idx(tid, e)] = d[e];
     return;
@@ -91,25 +123,32 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const K
 
 // ---------------------------------------------------------------------------
 // key switching, step 3: key inner product u_t[m] = sum_i D[m][i] * key[i][t][m]
-// with one 128-bit lazy sum per output word (elementwise, memory bound).
-// grid (n / 256, L+1, items); block 256
+// with one 128-bit lazy sum per output word (elementwise, memory bound; two
+// words per thread through 16-byte loads).
+// grid (n / 512, L+1, items); block 256
 __global__ __launch_bounds__(256) void k_ks_inner(const KsItem* __restrict__ items, KsArgs a, DevModuli M) {
   const int m = blockIdx.y, b = blockIdx.z;
   const int L = a.L, MM = a.L + 1;
   const uint64_t n = 1ull << a.log_n;
-  const uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t p = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 2;
   const uint64_t* key = items[b].key;
   const uint64_t* D = a.D + ((uint64_t)b * MM + m) * L * n + p;
   const ModConst mc = M.mc[m];
-  u128w acc0{0, 0}, acc1{0, 0};
+  u128w a00{0, 0}, a01{0, 0}, a10{0, 0}, a11{0, 0};  // [t][word]
   for (int i = 0; i < L; ++i) {
-    const uint64_t d = D[(uint64_t)i * n];
-    mac128(acc0, d, key[(((uint64_t)i * 2 + 0) * MM + m) * n + p]);
-    mac128(acc1, d, key[(((uint64_t)i * 2 + 1) * MM + m) * n + p]);
+    const ulonglong2 d = *reinterpret_cast<const ulonglong2*>(D + (uint64_t)i * n);
+    const ulonglong2 k0 = *reinterpret_cast<const ulonglong2*>(key + (((uint64_t)i * 2 + 0) * MM + m) * n + p);
+    const ulonglong2 k1 = *reinterpret_cast<const ulonglong2*>(key + (((uint64_t)i * 2 + 1) * MM + m) * n + p);
+    mac128(a00, d.x, k0.x);
+    mac128(a01, d.y, k0.y);
+    mac128(a10, d.x, k1.x);
+    mac128(a11, d.y, k1.y);
   }
   uint64_t* U = a.U + ((uint64_t)b * 2 * MM + m) * n + p;  // U[b][t][m], m = L is the P part
-  U[0] = reduce128(acc0, mc.q, mc.r64, mc.r64p, mc.onep);
-  U[(uint64_t)MM * n] = reduce128(acc1, mc.q, mc.r64, mc.r64p, mc.onep);
+  *reinterpret_cast<ulonglong2*>(U) = ulonglong2{reduce128(a00, mc.q, mc.r64, mc.r64p, mc.onep),
+                                                 reduce128(a01, mc.q, mc.r64, mc.r64p, mc.onep)};
+  *reinterpret_cast<ulonglong2*>(U + (uint64_t)MM * n) = ulonglong2{reduce128(a10, mc.q, mc.r64, mc.r64p, mc.onep),
+                                                                    reduce128(a11, mc.q, mc.r64, mc.r64p, mc.onep)};
 }
 
 // ---------------------------------------------------------------------------
@@ -138,16 +177,19 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_pinv(KsArgs a,
 // key switching, step 5: division by P and the rest of CtRotate:
 //   out_t[j] = (u_t[j] - NTT_j([y_t]_centred mod q_j)) * P^-1
 //              (+ sigma(c0)_j for t = 0) (+ acc_i in a Horner step)
-// grid (items, L, 2); block T
+// 1-D grid of xcd_blocks(items * 2, L): group (b, t) reads Y_t of item b, its L
+// members are the target limbs j; block T
 template <int LOGN, int LOGE>
-__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_waves_per_eu(4))) void k_ks_moddown(const KsItem* __restrict__ items, KsArgs a,
-                                                                          DevModuli M) {
+__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_waves_per_eu(4))) void k_ks_moddown(
+    const KsItem* __restrict__ items, KsArgs a, int n_items, DevModuli M) {
   using S = NttShape<LOGN, LOGE>;
   using FM = FirstMap<LOGN, LOGE>;
   __shared__ uint64_t lds[S::LDS_WORDS];
   const int tid = threadIdx.x;
-  const int b = blockIdx.x, j = blockIdx.y, t = blockIdx.z;
   const int L = a.L, MM = a.L + 1;
+  const GroupSlot gs = xcd_group(blockIdx.x, L);
+  if (gs.group >= (uint32_t)(n_items * 2)) return;  // padding block (whole block, before any barrier)
+  const int b = gs.group >> 1, t = gs.group & 1, j = gs.member;
   const uint64_t q = M.q[j];
   const uint64_t P = M.q[L];
   const uint64_t halfP = (P - 1) / 2;
@@ -159,26 +201,20 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_wa
     z[e] = y > halfP ? y + (q - P) : y;  // centred lift, then mod q_j (P < q_j)
   }
   ntt_fwd_nat<LOGN, LOGE>(z, lds, M.fwd[j], q, tid);
-  const KsItem it = items[b];
   const uint64_t* U = a.U + (((uint64_t)b * 2 + t) * MM + j) * S::N;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) {
     const uint64_t v = submod(U[FM::idx(tid, e)], reduce_lazy(z[e], q, M.mc[j].onep), q);
     z[e] = csub(shoup(v, M.pinv[j], M.pinvp[j], q), q);
   }
-  if (t == 0) {
-    uint64_t c0s[S::E];
-    gather_galois<LOGN, LOGE, FM>(c0s, sel_in(it, a.in_sel, a.in_off) + (uint64_t)j * S::N, lds, a.gal, tid);
-#pragma unroll
-    for (int e = 0; e < S::E; ++e) z[e] = addmod(z[e], c0s[e], q);
-  }
+  if (t == 0) add_galois<LOGN, LOGE, FM>(z, sel_in(items + b, a.in_sel, a.in_off) + (uint64_t)j * S::N, lds, a.gal, q, tid);
   const uint64_t toff = ((uint64_t)t * L + j) * S::N;
   if (a.giant >= 0) {  // Horner step: + acc_i
-    const uint64_t* acc = it.acc + (uint64_t)a.giant * 2 * L * S::N + toff;
+    const uint64_t* acc = items[b].acc + (uint64_t)a.giant * 2 * L * S::N + toff;
 #pragma unroll
     for (int e = 0; e < S::E; ++e) z[e] = addmod(z[e], acc[FM::idx(tid, e)], q);
   }
-  uint64_t* out = sel_out(it, a.out_sel, a.out_off) + toff;
+  uint64_t* out = sel_out(items + b, a.out_sel, a.out_off) + toff;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) out[FM::idx(tid, e)] = z[e];
 }
@@ -357,13 +393,13 @@ hipError_t launch_ks_digits(const KsItem* items, int n_items, const KsArgs& a, c
 
 hipError_t launch_ks_extend(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  WALLY_DISPATCH_LOGN(k_ks_extend, WALLY_KS_LOGE, dim3(n_items, (a.L + 1) * a.L), items, a, M);
+  WALLY_DISPATCH_LOGN(k_ks_extend, WALLY_KS_LOGE, dim3(xcd_blocks(n_items * a.L, a.L + 1)), items, a, n_items, M);
   return hipGetLastError();
 }
 
 hipError_t launch_ks_inner(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ks_inner, dim3((1u << a.log_n) / 256, a.L + 1, n_items), dim3(256), 0, st, items, a, M);
+  hipLaunchKernelGGL(k_ks_inner, dim3((1u << a.log_n) / 512, a.L + 1, n_items), dim3(256), 0, st, items, a, M);
   return hipGetLastError();
 }
 
@@ -375,7 +411,7 @@ hipError_t launch_ks_pinv(int n_items, const KsArgs& a, const DevModuli& M, hipS
 
 hipError_t launch_ks_moddown(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  WALLY_DISPATCH_LOGN(k_ks_moddown, WALLY_KS_LOGE, dim3(n_items, a.L, 2), items, a, M);
+  WALLY_DISPATCH_LOGN(k_ks_moddown, WALLY_KS_LOGE, dim3(xcd_blocks(n_items * 2, a.L)), items, a, n_items, M);
   return hipGetLastError();
 }
 

@@ -219,4 +219,23 @@ __device__ __forceinline__ void gather_galois(uint64_t (&x)[1 << LOGE], const ui
   __syncthreads();
 }
 
+// x <- x + sigma_gal(src) (mod q) in the register mapping MAP, with the same
+// coalesced LDS staging as gather_galois; the permuted word is added as it is
+// read, so no second register row is live.
+template <int LOGN, int LOGE, class MAP>
+__device__ __forceinline__ void add_galois(uint64_t (&x)[1 << LOGE], const uint64_t* __restrict__ src,
+                                           uint64_t* lds, uint32_t gal, uint64_t q, int tid) {
+  using S = NttShape<LOGN, LOGE>;
+  using FM = FirstMap<LOGN, LOGE>;
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) {
+    const uint32_t i = FM::idx(tid, e);
+    lds[S::lds(i)] = src[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) x[e] = addmod(x[e], lds[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))], q);
+  __syncthreads();
+}
+
 }  // namespace wally
