@@ -48,6 +48,14 @@ extern "C" {
 #define WALLY_ESTATE (-6)   /* call not valid in the current state           */
 
 #define WALLY_LAYOUT_PER_CLUSTER 0 /* each cluster owns ceil(N_c/n) chunks (paper §4.1) */
+/* Not in the paper; for indexes whose per-cluster layout exceeds HBM: a
+ * cluster of more than n entries owns ceil(N_c/n) chunks (listed first, in
+ * cluster order); the others share chunks, packed first-fit decreasing (size
+ * descending, ties by index, first shared chunk with room, at its fill
+ * level).  A query is scored against its cluster's chunks; its scores start
+ * at the cluster's slot base (wally_cluster_info) and the other slots of a
+ * shared chunk score other clusters' entries. */
+#define WALLY_LAYOUT_COPACK 1
 
 #define WALLY_PATH_BATCHED 0 /* queries of all clusters share launches        */
 #define WALLY_PATH_PLAIN 1   /* one launch sequence per cluster (baseline)     */
@@ -61,7 +69,7 @@ typedef struct {
   uint32_t limb_bits;  /* 30..54 bits per ciphertext prime                  */
   uint32_t t_bits;     /* plaintext modulus just above 2^t_bits (< limb_bits)*/
   uint32_t dim;        /* embedding dimension d                             */
-  uint32_t layout;     /* WALLY_LAYOUT_PER_CLUSTER                          */
+  uint32_t layout;     /* WALLY_LAYOUT_PER_CLUSTER or WALLY_LAYOUT_COPACK     */
   int32_t device;      /* HIP device ordinal                                */
   uint32_t max_batch;  /* queries resident per wave (0 = 512)                */
   uint32_t wave_sets;  /* waves in flight on separate streams (0 = 2)       */
@@ -112,9 +120,13 @@ int wally_params_query(const wally_ctx* ctx, wally_params_info* out);
 int wally_encode_clusters(wally_ctx* ctx, const int8_t* emb, uint64_t n_entries, const uint64_t* offsets,
                           uint32_t k);
 
-/* Chunks of cluster c and the device address of its plaintexts
- * [chunks][d_pad][L][n] (read-only for the caller). */
-int wally_cluster_info(const wally_ctx* ctx, uint32_t c, uint32_t* n_chunks, const uint64_t** plaintexts);
+/* Chunks of cluster c, the slot of its first entry in its first chunk (0 in
+ * the per-cluster layout) and the device address of its plaintexts
+ * [chunks][d_pad][L][n] (read-only for the caller).  Entry e of the cluster
+ * is scored in slot (slot_base + e) mod n of chunk (slot_base + e) / n of the
+ * response.  Any output pointer may be NULL.  EINVAL for c >= K. */
+int wally_cluster_info(const wally_ctx* ctx, uint32_t c, uint32_t* n_chunks, uint32_t* slot_base,
+                       const uint64_t** plaintexts);
 
 /* Score nq queries (Server Computation algorithm, paper §5): for each, g-1
  * baby-step rotations, then per chunk the giant-step sums of plaintext

@@ -140,9 +140,12 @@ struct wally_ctx {
   uint32_t* slot_of = nullptr;
   // index
   uint32_t K = 0;
-  std::vector<uint32_t> chunks;
-  std::vector<uint64_t> chunk_base;
+  uint32_t layout = WALLY_LAYOUT_PER_CLUSTER;
+  std::vector<uint32_t> chunks;      // chunks scored per cluster
+  std::vector<uint64_t> chunk_base;  // first chunk of each cluster
+  std::vector<uint32_t> slot_base;   // slot of each cluster's first entry in its first chunk
   uint32_t max_chunks = 0;
+  uint64_t n_chunks_total = 0;
   uint64_t* pt = nullptr;
   // waves
   int B = 0;
@@ -178,6 +181,65 @@ struct wally_ctx {
 };
 
 namespace {
+
+// Where each cluster's entries go.  Per cluster (paper §4.1 packing, Server
+// Initialization of §5): cluster c owns ceil(N_c / n) chunks, filled from slot
+// 0.  Co-packed: clusters of more than n entries keep chunks of their own (in
+// cluster order, first); the others go first-fit decreasing (size descending,
+// ties by index) into shared chunks at the chunk's fill level, so a query
+// needs one chunk and reads its scores from slot_base on.
+struct ChunkSeg {
+  uint32_t cluster;
+  uint64_t offset, count;  // entries [offset, offset + count) of the cluster
+};
+struct ChunkLayout {
+  std::vector<std::vector<ChunkSeg>> segs;  // per chunk, in slot order
+  std::vector<uint64_t> first;
+  std::vector<uint32_t> chunks, base;
+};
+
+void plan_layout(uint32_t layout, const uint64_t* offsets, uint32_t k, uint32_t n, ChunkLayout& out) {
+  out.segs.clear();
+  out.first.assign(k, 0);
+  out.chunks.assign(k, 0);
+  out.base.assign(k, 0);
+  auto own_chunks = [&](uint32_t c) {
+    const uint64_t sz = offsets[c + 1] - offsets[c];
+    out.first[c] = out.segs.size();
+    out.chunks[c] = (uint32_t)((sz + n - 1) / n);
+    for (uint64_t off = 0; off < sz; off += n) out.segs.push_back({ChunkSeg{c, off, std::min<uint64_t>(n, sz - off)}});
+  };
+  if (layout == WALLY_LAYOUT_PER_CLUSTER) {
+    for (uint32_t c = 0; c < k; ++c) own_chunks(c);
+    return;
+  }
+  std::vector<uint32_t> small;
+  for (uint32_t c = 0; c < k; ++c) {
+    if (offsets[c + 1] - offsets[c] > n)
+      own_chunks(c);
+    else
+      small.push_back(c);
+  }
+  std::stable_sort(small.begin(), small.end(), [&](uint32_t a, uint32_t b) {
+    return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
+  });
+  const size_t shared0 = out.segs.size();
+  std::vector<uint32_t> fill;  // used slots of each shared chunk
+  for (uint32_t c : small) {
+    const uint32_t sz = (uint32_t)(offsets[c + 1] - offsets[c]);
+    size_t b = 0;
+    while (b < fill.size() && fill[b] + sz > n) ++b;
+    if (b == fill.size()) {
+      fill.push_back(0);
+      out.segs.emplace_back();
+    }
+    out.first[c] = shared0 + b;
+    out.chunks[c] = 1;
+    out.base[c] = fill[b];
+    out.segs[shared0 + b].push_back(ChunkSeg{c, 0, sz});
+    fill[b] += sz;
+  }
+}
 
 int set_err(wally_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
@@ -507,9 +569,10 @@ int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
   if (desc->limb_bits < 30 || desc->limb_bits > 54) return WALLY_EINVAL;  // 27-bit halves in the sums
   if (desc->t_bits < 2 || desc->t_bits + 2 > desc->limb_bits) return WALLY_EINVAL;
   if (desc->dim < 1) return WALLY_EINVAL;
-  if (desc->layout != WALLY_LAYOUT_PER_CLUSTER) return WALLY_EINVAL;
+  if (desc->layout != WALLY_LAYOUT_PER_CLUSTER && desc->layout != WALLY_LAYOUT_COPACK) return WALLY_EINVAL;
   wally_ctx* c = new (std::nothrow) wally_ctx();
   if (!c) return WALLY_ENOMEM;
+  c->layout = desc->layout;
   c->device = desc->device;
   c->log_n = desc->log_n;
   c->n = 1 << c->log_n;
@@ -655,18 +718,11 @@ int wally_encode_clusters(wally_ctx* c, const int8_t* emb, uint64_t n_entries, c
   if (c->serving) return set_err(c, WALLY_ESTATE, "cannot re-encode while serving");
   if (!emb || !offsets || k == 0 || n_entries == 0) return set_err(c, WALLY_EINVAL, "empty or null index input");
   if (offsets[0] != 0 || offsets[k] != n_entries) return set_err(c, WALLY_EINVAL, "offsets must span [0, n_entries)");
-  std::vector<uint32_t> chunks(k);
-  std::vector<uint64_t> base(k);
-  uint64_t total = 0;
-  uint32_t maxc = 0;
-  for (uint32_t i = 0; i < k; ++i) {
+  for (uint32_t i = 0; i < k; ++i)
     if (offsets[i + 1] <= offsets[i]) return set_err(c, WALLY_EINVAL, "cluster %u is empty or offsets decrease", i);
-    const uint64_t sz = offsets[i + 1] - offsets[i];
-    chunks[i] = (uint32_t)((sz + c->n - 1) / c->n);
-    base[i] = total;
-    total += chunks[i];
-    maxc = std::max(maxc, chunks[i]);
-  }
+  ChunkLayout lay;
+  plan_layout(c->layout, offsets, k, c->n, lay);
+  const uint64_t total = lay.segs.size();
   // drop the previous index and workspaces, then allocate the new one
   free_sets(c);
   dfree(c, c->pt);
@@ -674,6 +730,20 @@ int wally_encode_clusters(wally_ctx* c, const int8_t* emb, uint64_t n_entries, c
   c->K = 0;
   const uint64_t ptw = c->ptw();
   if ((rc = dalloc(c, total * ptw * 8, (void**)&c->pt))) return rc;
+  // rows in chunk order: a chunk's entries are consecutive rows from slot 0
+  // (a copy only where clusters share chunks)
+  std::vector<int8_t> packed;
+  const int8_t* src = emb;
+  if (c->layout == WALLY_LAYOUT_COPACK) {
+    packed.resize(n_entries * c->d);
+    uint64_t r = 0;
+    for (const auto& segs : lay.segs)
+      for (const auto& sg : segs) {
+        std::memcpy(packed.data() + r * c->d, emb + (offsets[sg.cluster] + sg.offset) * c->d, sg.count * c->d);
+        r += sg.count;
+      }
+    src = packed.data();
+  }
   int8_t* demb = nullptr;
   EncodeJob* djobs = nullptr;
   if ((rc = dalloc(c, n_entries * c->d, (void**)&demb))) return rc;
@@ -682,13 +752,14 @@ int wally_encode_clusters(wally_ctx* c, const int8_t* emb, uint64_t n_entries, c
     return rc;
   }
   std::vector<EncodeJob> jobs(total);
-  for (uint32_t i = 0; i < k; ++i)
-    for (uint32_t ch = 0; ch < chunks[i]; ++ch) {
-      const uint64_t first = offsets[i] + (uint64_t)ch * c->n;
-      jobs[base[i] + ch] = EncodeJob{demb + first * c->d, std::min<uint64_t>(c->n, offsets[i + 1] - first),
-                                     c->pt + (base[i] + ch) * ptw};
-    }
-  hipError_t e = hipMemcpy(demb, emb, n_entries * c->d, hipMemcpyHostToDevice);
+  uint64_t row = 0;
+  for (uint64_t ch = 0; ch < total; ++ch) {
+    uint64_t cnt = 0;
+    for (const auto& sg : lay.segs[ch]) cnt += sg.count;
+    jobs[ch] = EncodeJob{demb + row * c->d, cnt, c->pt + ch * ptw};
+    row += cnt;
+  }
+  hipError_t e = hipMemcpy(demb, src, n_entries * c->d, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(djobs, jobs.data(), total * sizeof(EncodeJob), hipMemcpyHostToDevice);
   EncodeArgs a{c->log_n, c->L, (uint32_t)c->d, (uint32_t)c->d_pad, (uint32_t)c->g, c->slot_of};
   const uint64_t step = 4096;
@@ -699,15 +770,19 @@ int wally_encode_clusters(wally_ctx* c, const int8_t* emb, uint64_t n_entries, c
   dfree(c, djobs);
   if (e != hipSuccess) return set_err(c, WALLY_EDEVICE, "encode failed: %s", hipGetErrorString(e));
   c->K = k;
-  c->chunks = chunks;
-  c->chunk_base = base;
-  c->max_chunks = maxc;
+  c->chunks = std::move(lay.chunks);
+  c->chunk_base = std::move(lay.first);
+  c->slot_base = std::move(lay.base);
+  c->max_chunks = *std::max_element(c->chunks.begin(), c->chunks.end());
+  c->n_chunks_total = total;
   return WALLY_OK;
 }
 
-int wally_cluster_info(const wally_ctx* c, uint32_t cl, uint32_t* n_chunks, const uint64_t** plaintexts) {
+int wally_cluster_info(const wally_ctx* c, uint32_t cl, uint32_t* n_chunks, uint32_t* slot_base,
+                       const uint64_t** plaintexts) {
   if (!c || cl >= c->K) return WALLY_EINVAL;
   if (n_chunks) *n_chunks = c->chunks[cl];
+  if (slot_base) *slot_base = c->slot_base[cl];
   if (plaintexts) *plaintexts = c->pt + c->chunk_base[cl] * c->ptw();
   return WALLY_OK;
 }
@@ -722,13 +797,17 @@ uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) 
   return h;
 }
 
-// Queries ordered by cluster (so a wave touches few plaintext chunks) and cut
+// Queries ordered by chunk (so a wave touches few plaintext chunks) and cut
 // into waves: up to B queries, of one cluster only on the plain path.
 void make_waves(wally_ctx* c, const wally_query* q, uint64_t nq, int path, std::vector<const wally_query*>& ord,
                 std::vector<std::pair<uint64_t, uint64_t>>& waves) {
   ord.resize(nq);
   for (uint64_t i = 0; i < nq; ++i) ord[i] = &q[i];
-  std::stable_sort(ord.begin(), ord.end(), [](const wally_query* a, const wally_query* b) { return a->cluster < b->cluster; });
+  // by first chunk, then cluster: clusters that share a chunk land in the same waves and tiles
+  const std::vector<uint64_t>& fc = c->chunk_base;
+  std::stable_sort(ord.begin(), ord.end(), [&fc](const wally_query* a, const wally_query* b) {
+    return fc[a->cluster] != fc[b->cluster] ? fc[a->cluster] < fc[b->cluster] : a->cluster < b->cluster;
+  });
   waves.clear();
   for (uint64_t i = 0; i < nq;) {
     uint64_t j = i;

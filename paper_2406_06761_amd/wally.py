@@ -17,7 +17,7 @@ LIB_PATH = HERE / "libwally.so"
 
 OK, EINVAL, ENOMEM, EAGAIN, EPENDING, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 PATH_BATCHED, PATH_PLAIN, PATH_GRAPH = 0, 1, 2
-LAYOUT_PER_CLUSTER = 0
+LAYOUT_PER_CLUSTER, LAYOUT_COPACK = 0, 1
 
 QUERY_DTYPE = np.dtype([("cluster", "<u4"), ("reserved", "<u4"), ("ct", "<u8"), ("key_baby", "<u8"),
                         ("key_giant", "<u8"), ("out", "<u8")])
@@ -92,7 +92,7 @@ def load():
         "wally_params_init": ([ctypes.POINTER(ParamsDesc), ctypes.POINTER(vp)], i32),
         "wally_params_query": ([vp, ctypes.POINTER(ParamsInfo)], i32),
         "wally_encode_clusters": ([vp, vp, u64, vp, u32], i32),
-        "wally_cluster_info": ([vp, u32, ctypes.POINTER(u32), ctypes.POINTER(vp)], i32),
+        "wally_cluster_info": ([vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(vp)], i32),
         "wally_score_batch": ([vp, vp, u64, i32, vp], i32),
         "wally_tune": ([vp, vp, u64, vp, vp, vp, ctypes.POINTER(TuneEntry), u32, ctypes.POINTER(u32)], i32),
         "wally_serve_start": ([vp, vp], i32),
@@ -130,10 +130,10 @@ def _ptr(t):
 class Context:
     """One parameter set on one device (wally_params_init ... wally_destroy)."""
 
-    def __init__(self, log_n, num_limbs, limb_bits, t_bits, dim, device=0, max_batch=0, hbm_budget=0, wave_sets=0):
+    def __init__(self, log_n, num_limbs, limb_bits, t_bits, dim, device=0, max_batch=0, hbm_budget=0, wave_sets=0,
+                 layout=LAYOUT_PER_CLUSTER):
         self.lib = load()
-        d = ParamsDesc(log_n, num_limbs, limb_bits, t_bits, dim, LAYOUT_PER_CLUSTER, device, max_batch, wave_sets, 0,
-                       hbm_budget)
+        d = ParamsDesc(log_n, num_limbs, limb_bits, t_bits, dim, layout, device, max_batch, wave_sets, 0, hbm_budget)
         h = ctypes.c_void_p()
         rc = self.lib.wally_params_init(ctypes.byref(d), ctypes.byref(h))
         if rc:
@@ -171,10 +171,13 @@ class Context:
                                                    len(offsets) - 1), "wally_encode_clusters")
 
     def cluster_info(self, c):
+        """(chunks, device address of the cluster's plaintexts, slot base)."""
         n = ctypes.c_uint32()
+        b = ctypes.c_uint32()
         p = ctypes.c_void_p()
-        self._check(self.lib.wally_cluster_info(self.h, c, ctypes.byref(n), ctypes.byref(p)), "wally_cluster_info")
-        return n.value, p.value
+        self._check(self.lib.wally_cluster_info(self.h, c, ctypes.byref(n), ctypes.byref(b), ctypes.byref(p)),
+                    "wally_cluster_info")
+        return n.value, p.value, b.value
 
     def score_batch(self, queries: np.ndarray, path=PATH_BATCHED, stream=None):
         """queries: numpy array of QUERY_DTYPE (device pointers)."""

@@ -7,6 +7,7 @@ decrypted scores with int64 dot products mod t.
 import numpy as np
 import pytest
 
+from oracle import layout
 from oracle.bfv import Oracle
 from oracle.params import Params, preset
 from paper_2406_06761_amd import synth
@@ -22,7 +23,7 @@ def _ctx(name, **kw):
     return Context.preset(name, **kw)
 
 
-@pytest.fixture(scope="module", params=["tiny", "paper"])
+@pytest.fixture(scope="module", params=["tiny", "paper", "large"])
 def pair(request):
     name = request.param
     c = _ctx(name, max_batch=8)
@@ -104,12 +105,48 @@ def test_encode_parity(pair):
     offs = synth.offsets(sizes)
     c.encode_clusters(emb, offs)
     for k in range(len(sizes)):
-        chunks, ptr = c.cluster_info(k)
+        chunks, ptr, base = c.cluster_info(k)
+        assert base == 0
         want = o.encode_cluster(emb[int(offs[k]) : int(offs[k + 1])])
         assert chunks == want.shape[0]
         words = want.size
         got = _read_device(ptr, words).reshape(want.shape)
         assert (got == want).all(), k
+
+
+def test_small_end_to_end(pair):
+    """Two clusters (one of two chunks) and three real queries at the preset's
+    own parameters: response words equal the oracle's, decryption equals the
+    integer dot products."""
+    from paper_2406_06761_amd.wally import query_array, to_device, to_host
+
+    name, c, o = pair
+    p = o.p
+    sizes = np.array([300, p.n + 5], dtype=np.int64)
+    emb = synth.embeddings(int(sizes.sum()), p.dim, seed=51, norm="l2")
+    offs = synth.offsets(sizes)
+    c.encode_clusters(emb, offs)
+    targets = np.array([0, 1, 0], dtype=np.uint32)
+    qv = synth.query_vectors(3, p.dim, "l2", seed=52)
+    rng = np.random.default_rng(53)
+    packets = [o.make_query(qv[i], rng) for i in range(3)]
+    nch = [int((sizes[t] + p.n - 1) // p.n) for t in targets]
+    outs = [torch.zeros((k, 2, p.L, p.n), dtype=torch.int64, device="cuda") for k in nch]
+    dev = [(to_device(ct), to_device(kb), to_device(kg)) for ct, kb, kg, _ in packets]
+    q = query_array(targets, [d[0].data_ptr() for d in dev], [d[1].data_ptr() for d in dev],
+                    [d[2].data_ptr() for d in dev], [x.data_ptr() for x in outs])
+    c.score_batch(q)
+    torch.cuda.synchronize()
+    pts = [o.encode_cluster(emb[int(offs[k]) : int(offs[k + 1])]) for k in range(2)]
+    refs = o.score_many([(ct, kb, kg, pts[int(targets[i])]) for i, (ct, kb, kg, _) in enumerate(packets)], threads=3)
+    for i, t in enumerate(targets):
+        got = to_host(outs[i])
+        s = packets[i][3]
+        dec = np.concatenate([o.decrypt(s, got[j]) for j in range(nch[i])]).astype(np.int64)
+        rows = emb[int(offs[t]) : int(offs[t + 1])].astype(np.int64)
+        dec_ok = (dec[: len(rows)] == (rows @ qv[i].astype(np.int64)) % p.t).all()
+        assert (got == refs[i]).all(), (name, i, "decrypts correctly" if dec_ok else "decryption wrong too")
+        assert dec_ok, (name, i)
 
 
 def _read_device(ptr, words):
@@ -231,3 +268,70 @@ def test_tuner_picks_a_config_and_stays_exact(tiny_workload):
             assert (got[i] == ref[i]).all(), i
     finally:
         c.close()
+
+
+# ---------------------------------------------------------------------------
+# co-packed layout (clusters of at most n entries share chunks)
+
+COPACK_SIZES = [100, 4096 + 37, 5, 2 * 4096, 3000, 900, 1200, 4096, 60]
+
+
+@pytest.fixture(scope="module")
+def copack_setup():
+    from paper_2406_06761_amd.wally import LAYOUT_COPACK
+
+    p = preset("tiny")
+    o = Oracle(p)
+    sizes = np.array(COPACK_SIZES, dtype=np.int64)
+    emb = synth.embeddings(int(sizes.sum()), p.dim, seed=41, norm="inf")
+    offs = synth.offsets(sizes)
+    lay = layout.copack(sizes, p.n)
+    c = _ctx("tiny", max_batch=6, layout=LAYOUT_COPACK)
+    c.encode_clusters(emb, offs)
+    yield p, o, sizes, emb, offs, lay, c
+    c.close()
+
+
+def test_copack_layout_and_plaintexts(copack_setup):
+    p, o, sizes, emb, offs, lay, c = copack_setup
+    chunk0 = min(c.cluster_info(k)[1] for k in range(len(sizes)))
+    ptw_bytes = p.d_pad * p.L * p.n * 8
+    for k in range(len(sizes)):
+        chunks, ptr, base = c.cluster_info(k)
+        assert (chunks, base) == (lay.chunks[k], lay.base[k]), k
+        assert (ptr - chunk0) % ptw_bytes == 0 and (ptr - chunk0) // ptw_bytes == lay.first[k], k
+    assert lay.n_chunks < layout.per_cluster(sizes, p.n).n_chunks
+    for ch in range(lay.n_chunks):
+        want = o.encode_cluster(layout.chunk_rows(lay, ch, emb, offs))
+        assert want.shape[0] == 1
+        got = _read_device(chunk0 + ch * ptw_bytes, want.size).reshape(want.shape)
+        assert (got == want).all(), ch
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_copack_end_to_end(copack_setup, path):
+    from paper_2406_06761_amd.wally import query_array, to_device, to_host
+
+    p, o, sizes, emb, offs, lay, c = copack_setup
+    rng = np.random.default_rng(43)
+    targets = np.array([4, 5, 0, 8, 1, 2, 6, 3, 4, 7, 0], dtype=np.uint32)  # shared chunks, own chunks, repeats
+    qv = synth.query_vectors(len(targets), p.dim, "inf", seed=44)
+    packets = [o.make_query(qv[i], rng) for i in range(len(targets))]
+    nch = [lay.chunks[int(t)] for t in targets]
+    outs = [torch.zeros((k, 2, p.L, p.n), dtype=torch.int64, device="cuda") for k in nch]
+    dev = [(to_device(ct), to_device(kb), to_device(kg)) for ct, kb, kg, _ in packets]
+    q = query_array(targets, [d[0].data_ptr() for d in dev], [d[1].data_ptr() for d in dev],
+                    [d[2].data_ptr() for d in dev], [x.data_ptr() for x in outs])
+    c.score_batch(q, path=path)
+    torch.cuda.synchronize()
+    for i, t in enumerate(targets):
+        t = int(t)
+        pt = np.concatenate([o.encode_cluster(layout.chunk_rows(lay, lay.first[t] + j, emb, offs))
+                             for j in range(lay.chunks[t])])
+        got = to_host(outs[i])
+        ct, kb, kg, s = packets[i]
+        assert (got == o.score(ct, kb, kg, pt)).all(), (i, t)
+        dec = np.concatenate([o.decrypt(s, got[j]) for j in range(nch[i])]).astype(np.int64)
+        rows = emb[int(offs[t]) : int(offs[t + 1])].astype(np.int64)
+        b = lay.base[t]
+        assert (dec[b : b + len(rows)] == (rows @ qv[i].astype(np.int64)) % p.t).all(), (i, t)
