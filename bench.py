@@ -174,8 +174,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
-    ap.add_argument("--real", type=int, default=50_000, help="real queries per batch (paper workload)")
+    ap.add_argument("--workload", default="paper", choices=["paper", "batch500k", "large", "tiny"],
+                    help="paper: 3.2M x 192, 50k queries; batch500k: same index, 500k queries; "
+                         "large: 8M x 384 co-packed, 1M queries; tiny: 4096 x 64")
+    ap.add_argument("--real", type=int, default=0, help="real queries per batch (0 = the workload's own)")
+    ap.add_argument("--out-ring", type=int, default=0,
+                    help="response chunk slots shared round robin (0 = a private response per query when it fits)")
     ap.add_argument("--max-batch", type=int, default=0)
     ap.add_argument("--wave-sets", type=int, default=0)
     ap.add_argument("--pool", type=int, default=2048, help="distinct query packets resident on the device")
@@ -183,11 +187,14 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-launch events")
-    ap.add_argument("--serve-rates", default="5000,20000,50000", help="Poisson arrival rates (QPS), '' = skip")
+    ap.add_argument("--serve-rates", default=None,
+                    help="Poisson arrival rates (QPS), '' = skip (default 5000,20000,50000 on the paper workload)")
     ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner")
     ap.add_argument("--graph-steps", type=int, default=2, help="timed steps of the graph-captured path (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     args = ap.parse_args()
+    if args.serve_rates is None:
+        args.serve_rates = "5000,20000,50000" if args.workload == "paper" else ""
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -198,20 +205,31 @@ def main():
     import torch
 
     from paper_2406_06761_amd import synth
-    from paper_2406_06761_amd.wally import PATH_BATCHED, PATH_GRAPH, PATH_PLAIN, Context, query_array
+    from paper_2406_06761_amd.wally import (LAYOUT_COPACK, LAYOUT_PER_CLUSTER, PATH_BATCHED, PATH_GRAPH, PATH_PLAIN,
+                                            Context, query_array)
 
     torch.cuda.set_device(0)
     t_setup = time.perf_counter()
-    if args.workload == "paper":
-        w = synth.paper_workload(n_real=args.real)
+    layout = LAYOUT_PER_CLUSTER
+    if args.workload in ("paper", "batch500k"):
+        w = synth.paper_workload(n_real=args.real or (50_000 if args.workload == "paper" else 500_000))
         preset_name = "paper"
-        log(f"generating {w.n_entries} x {w.dim} int8 entries")
-        emb = synth.embeddings_parallel(w.n_entries, w.dim, norm=w.norm, threads=16)
+        desc = (f"3.2M x 192 int8, 1800 lognormal(0.8) clusters, {w.n_real // 1000}k Zipf(1.1) queries "
+                f"+ NB(2,0.5) fakes")
+    elif args.workload == "large":
+        w = synth.paper_workload(n_real=args.real or 1_000_000, entries=8_000_000, k=4000, dim=384, sigma=1.0,
+                                 name="large")
+        preset_name = "large"
+        layout = LAYOUT_COPACK
+        desc = (f"8M x 384 int8, 4000 lognormal(1.0) clusters co-packed, {w.n_real // 1000}k Zipf(1.1) queries "
+                f"+ NB(2,0.5) fakes")
     else:
         w = synth.tiny_workload()
         preset_name = "tiny"
-        emb = synth.embeddings(w.n_entries, w.dim, norm=w.norm)
-    ctx = Context.preset(preset_name, max_batch=args.max_batch, wave_sets=args.wave_sets)
+        desc = "4096 x 64 int8, 4 clusters, 16 queries"
+    log(f"generating {w.n_entries} x {w.dim} int8 entries")
+    emb = synth.embeddings_parallel(w.n_entries, w.dim, norm=w.norm, threads=16)
+    ctx = Context.preset(preset_name, max_batch=args.max_batch, wave_sets=args.wave_sets, layout=layout)
     info = ctx.info
     n, L = info.n, info.L
     log(f"params n={n} L={L} d_pad={info.d_pad} g={info.g} h={info.h}")
@@ -219,8 +237,10 @@ def main():
     ctx.encode_clusters(emb, synth.offsets(w.sizes))
     torch.cuda.synchronize()
     encode_s = time.perf_counter() - t0
-    chunks = (w.sizes + n - 1) // n
-    log(f"encoded {len(w.sizes)} clusters, {int(chunks.sum())} chunks, "
+    chunks = np.array([ctx.cluster_info(c)[0] for c in range(len(w.sizes))], dtype=np.int64)
+    n_chunks = len({ctx.cluster_info(c)[1] for c in range(len(w.sizes))}) if layout == LAYOUT_COPACK \
+        else int(chunks.sum())
+    log(f"encoded {len(w.sizes)} clusters, {n_chunks} chunks, "
         f"{ctx.bytes_allocated / 2**30:.1f} GiB resident, {encode_s:.2f} s")
     del emb
 
@@ -238,7 +258,16 @@ def main():
     out_off = np.zeros(nq, dtype=np.int64)
     out_off[1:] = np.cumsum(q_chunks)[:-1]
     ctw = int(info.ct_words)
-    outs = torch.empty(int(q_chunks.sum()) * ctw, dtype=torch.int64, device="cuda")
+    ring = args.out_ring
+    if not ring and int(q_chunks.sum()) * ctw * 8 > 64 << 30:
+        ring = 16384  # responses beyond 64 GiB: share a ring of chunk slots (8 GiB at n = 8192)
+    if ring:
+        span = ring - int(chunks.max())
+        out_off = out_off % span  # a query's chunks stay consecutive inside the ring
+        outs = torch.empty(ring * ctw, dtype=torch.int64, device="cuda")
+        log(f"responses share a ring of {ring} chunk slots")
+    else:
+        outs = torch.empty(int(q_chunks.sum()) * ctw, dtype=torch.int64, device="cuda")
     pidx = np.arange(nq) % pool
     q = query_array(w.targets, cts.data_ptr() + pidx * cts[0].numel() * 8, kbs.data_ptr() + pidx * kbs[0].numel() * 8,
                     kgs.data_ptr() + pidx * kgs[0].numel() * 8, outs.data_ptr() + out_off * ctw * 8)
@@ -248,7 +277,7 @@ def main():
         f"setup {time.perf_counter() - t_setup:.1f} s")
 
     tuned = None
-    if not args.no_tune and args.workload == "paper":
+    if not args.no_tune and args.workload != "tiny":
         t0 = time.perf_counter()
         sub = q[: min(8192, nq)]
         res = ctx.tune(sub, batches=(512, 1024), sets=(2, 3), tiles=(8, 16))
@@ -302,7 +331,10 @@ def main():
             log(f"  {k:11s} launches {nl:7d} items {it:9d} total {ms:9.1f} ms avg {ms / max(nl, 1):.3f} ms")
 
     graph = None
-    if args.graph_steps > 0:
+    waves = -(-nq // (args.max_batch or 512))
+    if args.graph_steps > 0 and waves > 128:
+        log(f"graph path skipped: {waves} waves, the library captures at most 128 per graph")
+    elif args.graph_steps > 0:
         t0 = time.perf_counter()
         ctx.score_batch(q, path=PATH_GRAPH)  # capture + first replay
         torch.cuda.synchronize()
@@ -334,7 +366,7 @@ def main():
     cpu = None
     if not args.no_cpu and args.cpu_sample > 0:
         threads = min(16, os.cpu_count() or 1)
-        cpu = cpu_baseline(w, args.cpu_sample if args.workload == "paper" else min(16, nq), threads, preset_name)
+        cpu = cpu_baseline(w, args.cpu_sample if args.workload != "tiny" else min(16, nq), threads, preset_name)
         log(f"cpu oracle: {cpu['value']:.4g} scores/s on {threads} threads")
 
     line = {
@@ -350,8 +382,8 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "3.2M x 192 int8, 1800 lognormal(0.8) clusters, 50k Zipf(1.1) queries + NB(2,0.5) fakes"
-                   if args.workload == "paper" else "4096 x 64 int8, 4 clusters, 16 queries",
+        "config": {"workload": desc, "layout": "copack" if layout == LAYOUT_COPACK else "per_cluster",
+                   "response_ring_slots": ring or None,
                    "params": f"n={n}, L={L} x {54 if n == 8192 else 36}-bit limbs, t={info.t}",
                    "queries": nq, "real_queries": w.n_real, "scores_per_step": scores,
                    "real_scores_per_step": real_scores, "pool_packets": pool,

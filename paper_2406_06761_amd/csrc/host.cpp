@@ -888,6 +888,11 @@ int build_graph(wally_ctx* c, const std::vector<const wally_query*>& ord,
   return WALLY_OK;
 }
 
+// Largest batch the graph path captures, in waves (about 150 kernel nodes
+// each).  Captures of about 1,000 waves ended the process inside the score
+// call; the limit keeps the graph within the sizes that have run.
+constexpr int kMaxGraphWaves = 128;
+
 int score_locked(wally_ctx* c, const wally_query* q, uint64_t nq, int path, hipStream_t user) {
   int rc;
   for (uint64_t i = 0; i < nq; ++i)
@@ -902,6 +907,11 @@ int score_locked(wally_ctx* c, const wally_query* q, uint64_t nq, int path, hipS
       std::vector<const wally_query*> ord;
       std::vector<std::pair<uint64_t, uint64_t>> waves;
       make_waves(c, q, nq, WALLY_PATH_BATCHED, ord, waves);
+      if (waves.size() > kMaxGraphWaves)
+        return set_err(c, WALLY_EINVAL,
+                       "graph path: the batch needs %zu waves of %d queries, at most %d are captured in one graph "
+                       "(split the batch or use the batched path)",
+                       waves.size(), c->B, kMaxGraphWaves);
       if ((rc = build_graph(c, ord, waves))) return rc;
       c->graph_key = key;
     }

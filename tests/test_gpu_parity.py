@@ -250,6 +250,23 @@ def test_graph_replays_match_eager(tiny_workload):
         c.close()
 
 
+def test_graph_refuses_batches_over_the_wave_limit(tiny_workload):
+    """More than 128 waves in one graph is refused before anything is captured."""
+    from paper_2406_06761_amd.wally import EINVAL, PATH_GRAPH, WallyError, query_array
+
+    o, w, emb, offs, qv, packets, ref = tiny_workload
+    c = _ctx("tiny", max_batch=1, wave_sets=1)
+    try:
+        c.encode_clusters(emb, offs)
+        q, outs, keep = _tiny_queries(o, w, packets)
+        big = np.concatenate([q] * 9)[:129]  # 129 one-query waves
+        with pytest.raises(WallyError) as e:
+            c.score_batch(big, path=PATH_GRAPH)
+        assert e.value.code == EINVAL and "128" in str(e.value)
+    finally:
+        c.close()
+
+
 def test_tuner_picks_a_config_and_stays_exact(tiny_workload):
     from paper_2406_06761_amd.wally import PATH_BATCHED, to_host
 
