@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import json
+from pathlib import Path
 import math
 import os
 import sys
@@ -32,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 39.3e12 lane-instructions/s
-INSTR_PER_MODMUL = 20                       # VALU instructions of one 54-bit Shoup butterfly
+INSTR_PER_MODMUL = 20                       # VALU instructions of one compiled 54-bit Shoup butterfly
 HBM_PEAK = 8.0e12
 
 
@@ -57,6 +58,38 @@ def per_item_work(kernel, n, L, g, h):
     if kernel == "mac":
         return 2 * g * L * n * h
     return 0
+
+
+def inner_bytes(n, L):
+    """Compulsory HBM bytes per item of the key inner product: the key
+    L x 2 x (L+1) x n, the extended digits (L+1) x L x n, the output 2 x (L+1) x n."""
+    return 8 * n * (2 * L * (L + 1) + (L + 1) * L + 2 * (L + 1))
+
+
+TRAFFIC_FILE = Path(__file__).resolve().parent / "profiles" / "hbm_traffic_paper.json"
+KERNEL_SOURCES = ["kernels.hip", "ntt.h", "arith.h", "kernels.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update((Path(__file__).resolve().parent / "paper_2406_06761_amd" / "csrc" / f).read_bytes())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel, params_name):
+    """HBM bytes per item of `kernel` from the committed counter profile, or
+    None when there is none for these parameters or the kernel sources changed
+    since the counters were taken."""
+    try:
+        rec = json.loads(TRAFFIC_FILE.read_text())
+    except (OSError, ValueError):
+        return None
+    if rec.get("params") != params_name or rec.get("kernel_sources_sha256") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_item", {}).get(kernel)
 
 
 def cpu_baseline(workload, sample, threads, params_name):
@@ -329,6 +362,42 @@ def main():
                     "path_frac": step_work / (ms_per_step * 1e-3) / peak}
         for k, (nl, it, ms) in kstats.items():
             log(f"  {k:11s} launches {nl:7d} items {it:9d} total {ms:9.1f} ms avg {ms / max(nl, 1):.3f} ms")
+
+    # Isolated kernel rates: the key-switch kernels alone on one stream
+    # (1,024 items through the rotation entry point), so each launch has the
+    # GPU to itself; the timed region above runs two streams whose launches
+    # share the GPU.
+    isolated = None
+    if timing:
+        cnt = min(1024, pool)
+        out_i = torch.empty_like(cts[:cnt])
+        ctx.diag_rotate(cts[:cnt], kbs[:cnt], out_i, 0)
+        torch.cuda.synchronize()
+        ctx.kernel_timing(True)
+        ctx.kernel_stats()
+        for r in range(5):
+            ctx.diag_rotate(cts[:cnt], kbs[:cnt], out_i, r & 1)
+        ist = ctx.kernel_stats()
+        ctx.kernel_timing(False)
+        peak = PEAK_VALU_LANE_OPS / INSTR_PER_MODMUL
+        isolated = {}
+        for k, (nl, it, ms) in ist.items():
+            if not nl:
+                continue
+            e = {"ms_per_launch": ms / nl, "items_per_launch": it / nl}
+            if k == "ks_inner":  # streams the key: HBM bound
+                e.update(bound="hbm", achieved_gbs=inner_bytes(n, L) * it / (ms * 1e-3) / 1e9,
+                         frac=inner_bytes(n, L) * it / (ms * 1e-3) / HBM_PEAK)
+            else:
+                w_ = per_item_work(k, n, L, info.g, info.h)
+                e.update(bound="alu", achieved_gmodmul=w_ * it / (ms * 1e-3) / 1e9, frac=w_ * it / (ms * 1e-3) / peak)
+            isolated[k] = e
+            log(f"  isolated {k:11s} {e['ms_per_launch']:.3f} ms per {cnt} items, frac {e['frac']:.3f}")
+        if roofline is not None:
+            roofline["isolated"] = isolated
+            traffic = stored_traffic(roofline["kernel"], preset_name)
+            if traffic is not None:
+                roofline["traffic"] = traffic * roofline["items_per_launch"]
 
     graph = None
     waves = -(-nq // (args.max_batch or 512))

@@ -29,10 +29,21 @@
 
 namespace wally {
 
+// Pointers read from descriptors in memory are generic to the compiler, which
+// then emits flat loads and stores (also counted by the LDS wait counter, so
+// the transforms' LDS waits would wait for them).  They always address device
+// global memory, so every access goes through a pointer typed with the global
+// address space.
+#define WALLY_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ WALLY_GLOBAL T* gmem(T* p) {
+  return (WALLY_GLOBAL T*)p;
+}
+
 // The selector is uniform; the chosen field is read straight from the item in
 // global memory (a dynamic pick from a register copy of the item would be
 // lowered to a stack array in scratch memory).
-__device__ __forceinline__ const uint64_t* sel_in(const KsItem* it, int sel, uint64_t off) {
+__device__ __forceinline__ WALLY_GLOBAL const uint64_t* sel_in(const KsItem* it, int sel, uint64_t off) {
   const uint64_t* r;
   switch (sel) {
     case 0: r = it->buf0; break;
@@ -40,16 +51,16 @@ __device__ __forceinline__ const uint64_t* sel_in(const KsItem* it, int sel, uin
     case 2: r = it->fin; break;
     default: r = it->acc; break;
   }
-  return r + off;
+  return gmem(r) + off;
 }
-__device__ __forceinline__ uint64_t* sel_out(const KsItem* it, int sel, uint64_t off) {
+__device__ __forceinline__ WALLY_GLOBAL uint64_t* sel_out(const KsItem* it, int sel, uint64_t off) {
   uint64_t* r;
   switch (sel) {
     case 0: r = it->buf0; break;
     case 1: r = it->buf1; break;
     default: r = it->fin; break;
   }
-  return r + off;
+  return gmem(r) + off;
 }
 
 // XCD-aware placement. The work-groups of a launch go to the eight XCDs round
@@ -78,7 +89,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_digits(const K
   __shared__ uint64_t lds[S::LDS_WORDS];
   const int tid = threadIdx.x;
   const int b = blockIdx.x, i = blockIdx.y;
-  const uint64_t* c1 = sel_in(items + b, a.in_sel, a.in_off) + ((uint64_t)a.L + i) * S::N;
+  const auto c1 = sel_in(items + b, a.in_sel, a.in_off) + ((uint64_t)a.L + i) * S::N;
   const uint64_t q = M.q[i];
   uint64_t x[S::E];
   gather_galois<LOGN, LOGE, LastMap<LOGN, LOGE>>(x, c1, lds, a.gal, tid);  // sigma(c1)_i, INTT input order
@@ -131,7 +142,7 @@ __global__ __launch_bounds__(256) void k_ks_inner(const KsItem* __restrict__ ite
   const int L = a.L, MM = a.L + 1;
   const uint64_t n = 1ull << a.log_n;
   const uint64_t p = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 2;
-  const uint64_t* key = items[b].key;
+  WALLY_GLOBAL const uint64_t* key = gmem(items[b].key);
   const uint64_t* D = a.D + ((uint64_t)b * MM + m) * L * n + p;
   const ModConst mc = M.mc[m];
   u128w a00{0, 0}, a01{0, 0}, a10{0, 0}, a11{0, 0};  // [t][word]
@@ -210,11 +221,11 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_wa
   if (t == 0) add_galois<LOGN, LOGE, FM>(z, sel_in(items + b, a.in_sel, a.in_off) + (uint64_t)j * S::N, lds, a.gal, q, tid);
   const uint64_t toff = ((uint64_t)t * L + j) * S::N;
   if (a.giant >= 0) {  // Horner step: + acc_i
-    const uint64_t* acc = items[b].acc + (uint64_t)a.giant * 2 * L * S::N + toff;
+    WALLY_GLOBAL const uint64_t* acc = gmem(items[b].acc) + (uint64_t)a.giant * 2 * L * S::N + toff;
 #pragma unroll
     for (int e = 0; e < S::E; ++e) z[e] = addmod(z[e], acc[FM::idx(tid, e)], q);
   }
-  uint64_t* out = sel_out(items + b, a.out_sel, a.out_off) + toff;
+  WALLY_GLOBAL uint64_t* out = sel_out(items + b, a.out_sel, a.out_off) + toff;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) out[FM::idx(tid, e)] = z[e];
 }
@@ -252,15 +263,16 @@ __global__ __launch_bounds__(256) void k_mac_tiles(const KsItem* __restrict__ it
   const ModConst mc = M.mc[j];
   const uint64_t c27 = M.c27[j], c27p = M.c27p[j];
   const uint64_t ctw = 2ull * L * n;
-  const uint64_t* pt = items[tl.first].pt + (uint64_t)j * n + x;  // PT[m][j][x] at m * L * n
+  WALLY_GLOBAL const uint64_t* pt = gmem(items[tl.first].pt) + (uint64_t)j * n + x;  // PT[m][j][x] at m * L * n
   const uint64_t M27 = (1ull << 27) - 1;
   for (uint32_t k = lane; k < tl.count; k += 4) {
-    const KsItem it = items[tl.first + k];
+    const KsItem& it = items[tl.first + k];
+    WALLY_GLOBAL const uint64_t* ctp = gmem(it.ctp);
     uint32_t c0l[G], c0h[G], c1l[G], c1h[G];
 #pragma unroll
     for (int jj = 0; jj < G; ++jj) {
-      const uint64_t v0 = it.ctp[jj * ctw + (uint64_t)j * n + x];
-      const uint64_t v1 = it.ctp[jj * ctw + ((uint64_t)L + j) * n + x];
+      const uint64_t v0 = ctp[jj * ctw + (uint64_t)j * n + x];
+      const uint64_t v1 = ctp[jj * ctw + ((uint64_t)L + j) * n + x];
       c0l[jj] = (uint32_t)(v0 & M27);
       c0h[jj] = (uint32_t)(v0 >> 27);
       c1l[jj] = (uint32_t)(v1 & M27);
@@ -279,7 +291,7 @@ __global__ __launch_bounds__(256) void k_mac_tiles(const KsItem* __restrict__ it
         b1 += (uint64_t)wl * c1h[jj] + (uint64_t)wh * c1l[jj];
         b2 += (uint64_t)wh * c1h[jj];
       }
-      uint64_t* acc = it.acc + (uint64_t)i * ctw + (uint64_t)j * n + x;
+      WALLY_GLOBAL uint64_t* acc = gmem(it.acc) + (uint64_t)i * ctw + (uint64_t)j * n + x;
       acc[0] = fold27(a0, a1, a2, mc, c27, c27p);
       acc[(uint64_t)L * n] = fold27(b0, b1, b2, mc, c27, c27p);
     }
@@ -290,8 +302,8 @@ __global__ __launch_bounds__(256) void k_mac_tiles(const KsItem* __restrict__ it
 // grid (items); block 256
 __global__ __launch_bounds__(256) void k_copy_ct(const CopyItem* __restrict__ items, uint64_t words) {
   const CopyItem it = items[blockIdx.x];
-  const ulonglong2* src = reinterpret_cast<const ulonglong2*>(it.src);
-  ulonglong2* dst = reinterpret_cast<ulonglong2*>(it.dst);
+  WALLY_GLOBAL const ulonglong2* src = (WALLY_GLOBAL const ulonglong2*)gmem(it.src);
+  WALLY_GLOBAL ulonglong2* dst = (WALLY_GLOBAL ulonglong2*)gmem(it.dst);
   for (uint64_t k = threadIdx.x; k < words / 2; k += blockDim.x) dst[k] = src[k];
 }
 
@@ -327,7 +339,7 @@ __global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_encode(const EncodeJ
     const uint64_t entry = s2;
     const uint32_t coord = ((s2 % dp) + m) % dp;
     int v = 0;
-    if (entry < jb.n_entries && coord < d) v = jb.emb[entry * d + coord];
+    if (entry < jb.n_entries && coord < d) v = gmem(jb.emb)[entry * d + coord];
     x[e] = v < 0 ? (uint64_t)((int64_t)t + v) : (uint64_t)v;
   }
   ntt_inv<LOGN, 4>(x, lds, M.inv[it], t, tid);
@@ -343,7 +355,7 @@ __global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_encode(const EncodeJ
 #pragma unroll
     for (int e = 0; e < 16; ++e) x[e] = cc[e] < 0 ? (uint64_t)((int64_t)q + cc[e]) : (uint64_t)cc[e];
     ntt_fwd_nat<LOGN, 4>(x, lds, M.fwd[l], q, tid);
-    uint64_t* out = jb.out + ((uint64_t)m * a.L + l) * S::N;
+    WALLY_GLOBAL uint64_t* out = gmem(jb.out) + ((uint64_t)m * a.L + l) * S::N;
 #pragma unroll
     for (int e = 0; e < 16; ++e) out[FirstMap<LOGN, 4>::idx(tid, e)] = reduce_lazy(x[e], q, M.mc[l].onep);
   }

@@ -203,9 +203,9 @@ __device__ __forceinline__ uint32_t galois_src(uint32_t i, uint32_t gal) {
 // x <- sigma_gal(src) in the register mapping MAP: the row is read with
 // coalesced loads into LDS and permuted there (a direct gather from global
 // memory would touch a different cache line in every lane).
-template <int LOGN, int LOGE, class MAP>
-__device__ __forceinline__ void gather_galois(uint64_t (&x)[1 << LOGE], const uint64_t* __restrict__ src,
-                                              uint64_t* lds, uint32_t gal, int tid) {
+template <int LOGN, int LOGE, class MAP, class SRC>
+__device__ __forceinline__ void gather_galois(uint64_t (&x)[1 << LOGE], SRC src, uint64_t* lds, uint32_t gal,
+                                              int tid) {
   using S = NttShape<LOGN, LOGE>;
   using FM = FirstMap<LOGN, LOGE>;
 #pragma unroll
@@ -222,9 +222,9 @@ __device__ __forceinline__ void gather_galois(uint64_t (&x)[1 << LOGE], const ui
 // x <- x + sigma_gal(src) (mod q) in the register mapping MAP, with the same
 // coalesced LDS staging as gather_galois; the permuted word is added as it is
 // read, so no second register row is live.
-template <int LOGN, int LOGE, class MAP>
-__device__ __forceinline__ void add_galois(uint64_t (&x)[1 << LOGE], const uint64_t* __restrict__ src,
-                                           uint64_t* lds, uint32_t gal, uint64_t q, int tid) {
+template <int LOGN, int LOGE, class MAP, class SRC>
+__device__ __forceinline__ void add_galois(uint64_t (&x)[1 << LOGE], SRC src, uint64_t* lds, uint32_t gal,
+                                           uint64_t q, int tid) {
   using S = NttShape<LOGN, LOGE>;
   using FM = FirstMap<LOGN, LOGE>;
 #pragma unroll
