@@ -105,11 +105,15 @@ def cpu_baseline(workload, sample, threads, params_name):
     idx = np.sort(rng.choice(len(workload.targets), size=sample, replace=False))
     offs = synth.offsets(workload.sizes)
     clusters = sorted(set(int(workload.targets[i]) for i in idx))
-    log(f"cpu baseline: encoding {len(clusters)} clusters with the oracle (untimed)")
-    pts = {}
-    for c in clusters:
+    log(f"cpu baseline: encoding {len(clusters)} clusters with the oracle (untimed, {threads} threads)")
+    from concurrent.futures import ThreadPoolExecutor
+
+    def enc(c):
         emb = synth.embeddings(int(workload.sizes[c]), workload.dim, norm=workload.norm, row_start=int(offs[c]))
-        pts[c] = o.encode_cluster(emb)
+        return c, o.encode_cluster(emb)
+
+    with ThreadPoolExecutor(threads) as ex:
+        pts = dict(ex.map(enc, clusters))
     jobs = []
     for i in idx:
         ct = o.uniform(rng, p.q, count=2)
@@ -217,7 +221,7 @@ def main():
     ap.add_argument("--wave-sets", type=int, default=0)
     ap.add_argument("--pool", type=int, default=2048, help="distinct query packets resident on the device")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-cluster path (0 = skip)")
-    ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--cpu-sample", type=int, default=480, help="queries the CPU oracle scores (about 10 s on 16 threads)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-launch events")
     ap.add_argument("--serve-rates", default=None,
@@ -401,8 +405,10 @@ def main():
 
     graph = None
     waves = -(-nq // (args.max_batch or 512))
-    if args.graph_steps > 0 and waves > 128:
-        log(f"graph path skipped: {waves} waves, the library captures at most 128 per graph")
+    if tuned:
+        waves = -(-nq // tuned["chosen"]["max_batch"])
+    if args.graph_steps > 0 and waves > 64:
+        log(f"graph path skipped: {waves} waves, the library captures at most 64 per graph")
     elif args.graph_steps > 0:
         t0 = time.perf_counter()
         ctx.score_batch(q, path=PATH_GRAPH)  # capture + first replay

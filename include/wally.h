@@ -135,7 +135,7 @@ int wally_cluster_info(const wally_ctx* ctx, uint32_t c, uint32_t* n_chunks, uin
  * clusters), WALLY_PATH_PLAIN (one launch sequence per cluster) or
  * WALLY_PATH_GRAPH (the batched launches of the whole batch captured once in
  * a hipGraph and replayed while the same query array and configuration are
- * passed again; at most 128 waves of max_batch queries, EINVAL beyond); all
+ * passed again; at most 64 waves of max_batch queries, EINVAL beyond); all
  * give identical words.  Work is enqueued on hip_stream (a
  * hipStream_t; NULL = default stream) and the call returns once it is
  * enqueued; output is independent of batch composition.  Validation errors

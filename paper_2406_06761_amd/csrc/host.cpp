@@ -891,7 +891,7 @@ int build_graph(wally_ctx* c, const std::vector<const wally_query*>& ord,
 // Largest batch the graph path captures, in waves (about 150 kernel nodes
 // each).  Captures of about 1,000 waves ended the process inside the score
 // call; the limit keeps the graph within the sizes that have run.
-constexpr int kMaxGraphWaves = 128;
+constexpr int kMaxGraphWaves = 64;
 
 int score_locked(wally_ctx* c, const wally_query* q, uint64_t nq, int path, hipStream_t user) {
   int rc;

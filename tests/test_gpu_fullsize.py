@@ -160,7 +160,7 @@ def test_paper_scale_sampled_parity():
 
 @pytest.mark.skip(reason="one graph capture of the whole 500k batch (~1,000 waves, ~150k kernel nodes) ended the "
                          "process with a segmentation fault inside the score call; no cause found in this code, so "
-                         "the graph path now refuses batches over 128 waves (EINVAL) and this case stays off")
+                         "the graph path now refuses batches over 64 waves (EINVAL) and this case stays off")
 def test_batch_500k_graph_sampled_parity():
     _batch_500k(graph=True)
 

@@ -251,7 +251,7 @@ def test_graph_replays_match_eager(tiny_workload):
 
 
 def test_graph_refuses_batches_over_the_wave_limit(tiny_workload):
-    """More than 128 waves in one graph is refused before anything is captured."""
+    """More than 64 waves in one graph is refused before anything is captured."""
     from paper_2406_06761_amd.wally import EINVAL, PATH_GRAPH, WallyError, query_array
 
     o, w, emb, offs, qv, packets, ref = tiny_workload
@@ -259,10 +259,10 @@ def test_graph_refuses_batches_over_the_wave_limit(tiny_workload):
     try:
         c.encode_clusters(emb, offs)
         q, outs, keep = _tiny_queries(o, w, packets)
-        big = np.concatenate([q] * 9)[:129]  # 129 one-query waves
+        big = np.concatenate([q] * 5)[:65]  # 65 one-query waves
         with pytest.raises(WallyError) as e:
             c.score_batch(big, path=PATH_GRAPH)
-        assert e.value.code == EINVAL and "128" in str(e.value)
+        assert e.value.code == EINVAL and "64" in str(e.value)
     finally:
         c.close()
 
