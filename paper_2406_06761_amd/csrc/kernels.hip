@@ -39,6 +39,9 @@ template <class T>
 __device__ __forceinline__ WALLY_GLOBAL T* gmem(T* p) {
   return (WALLY_GLOBAL T*)p;
 }
+// two words in one 16-byte access (a builtin vector type, usable in any
+// address space)
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
 // The selector is uniform; the chosen field is read straight from the item in
 // global memory (a dynamic pick from a register copy of the item would be
@@ -148,8 +151,8 @@ __global__ __launch_bounds__(256) void k_ks_inner(const KsItem* __restrict__ ite
   u128w a00{0, 0}, a01{0, 0}, a10{0, 0}, a11{0, 0};  // [t][word]
   for (int i = 0; i < L; ++i) {
     const ulonglong2 d = *reinterpret_cast<const ulonglong2*>(D + (uint64_t)i * n);
-    const ulonglong2 k0 = *reinterpret_cast<const ulonglong2*>(key + (((uint64_t)i * 2 + 0) * MM + m) * n + p);
-    const ulonglong2 k1 = *reinterpret_cast<const ulonglong2*>(key + (((uint64_t)i * 2 + 1) * MM + m) * n + p);
+    const u64x2 k0 = *(WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + 0) * MM + m) * n + p);
+    const u64x2 k1 = *(WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + 1) * MM + m) * n + p);
     mac128(a00, d.x, k0.x);
     mac128(a01, d.y, k0.y);
     mac128(a10, d.x, k1.x);
@@ -302,8 +305,8 @@ __global__ __launch_bounds__(256) void k_mac_tiles(const KsItem* __restrict__ it
 // grid (items); block 256
 __global__ __launch_bounds__(256) void k_copy_ct(const CopyItem* __restrict__ items, uint64_t words) {
   const CopyItem it = items[blockIdx.x];
-  WALLY_GLOBAL const ulonglong2* src = (WALLY_GLOBAL const ulonglong2*)gmem(it.src);
-  WALLY_GLOBAL ulonglong2* dst = (WALLY_GLOBAL ulonglong2*)gmem(it.dst);
+  WALLY_GLOBAL const u64x2* src = (WALLY_GLOBAL const u64x2*)gmem(it.src);
+  WALLY_GLOBAL u64x2* dst = (WALLY_GLOBAL u64x2*)gmem(it.dst);
   for (uint64_t k = threadIdx.x; k < words / 2; k += blockDim.x) dst[k] = src[k];
 }
 

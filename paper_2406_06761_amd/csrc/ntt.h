@@ -77,14 +77,25 @@ __device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, 
   Y = shoup4(v, W.x, W.y, q);
 }
 
+// Group index of combination c of thread tid in pass S0.  When the pass's low
+// bits cover every thread index (the first forward pass, the last inverse
+// pass) it does not depend on tid: written as a constant, the twiddles of the
+// pass become uniform loads.
+template <int LOGN, int LOGE, int S0>
+__device__ __forceinline__ uint32_t pass_high(int tid, int c) {
+  using M = PassMap<LOGN, LOGE, S0>;
+  constexpr int LOGT = LOGN - LOGE;
+  if constexpr (M::LOWB >= LOGT) return (uint32_t)c >> (M::LOWB - LOGT);
+  else return ((uint32_t)tid + M::T * (uint32_t)c) >> M::LOWB;
+}
+
 template <int LOGN, int LOGE, int S0>
 __device__ __forceinline__ void ct_pass(uint64_t (&x)[1 << LOGE], const ulonglong2* __restrict__ tw, uint64_t q,
                                         uint64_t q4, int tid) {
   using M = PassMap<LOGN, LOGE, S0>;
 #pragma unroll
   for (int c = 0; c < M::COMBOS; ++c) {
-    const uint32_t combo = tid + M::T * c;
-    const uint32_t high = combo >> M::LOWB;
+    const uint32_t high = pass_high<LOGN, LOGE, S0>(tid, c);
 #pragma unroll
     for (int ls = 0; ls < M::RW; ++ls) {
       const int half = 1 << (M::RW - 1 - ls);
@@ -105,8 +116,7 @@ __device__ __forceinline__ void gs_pass(uint64_t (&x)[1 << LOGE], const ulonglon
   using M = PassMap<LOGN, LOGE, S0>;
 #pragma unroll
   for (int c = 0; c < M::COMBOS; ++c) {
-    const uint32_t combo = tid + M::T * c;
-    const uint32_t high = combo >> M::LOWB;
+    const uint32_t high = pass_high<LOGN, LOGE, S0>(tid, c);
 #pragma unroll
     for (int ls = M::RW - 1; ls >= 0; --ls) {
       const int half = 1 << (M::RW - 1 - ls);

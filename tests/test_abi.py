@@ -55,3 +55,16 @@ def test_error_strings_and_null_handling():
     assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL
     d = wally.ParamsDesc(12, 3, 36, 20, 4096, 0, 0, 0, 0, 0, 0)  # d_pad does not divide n/2
     assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL
+
+
+def test_library_is_newer_than_its_sources():
+    """A failed rebuild leaves the previous library in place; catch it here
+    rather than measuring or testing stale code."""
+    from paper_2406_06761_amd.wally import LIB_PATH
+
+    if not LIB_PATH.exists():
+        pytest.skip("library not built")
+    root = Path(__file__).resolve().parents[1]
+    sources = list((root / "paper_2406_06761_amd" / "csrc").glob("*")) + list((root / "include").glob("*.h"))
+    newest = max(p.stat().st_mtime for p in sources)
+    assert LIB_PATH.stat().st_mtime >= newest, "libwally.so is older than its sources: rebuild failed or was skipped"
