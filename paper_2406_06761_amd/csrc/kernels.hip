@@ -253,7 +253,11 @@ __device__ __forceinline__ uint64_t fold27(uint64_t s0, uint64_t s1, uint64_t s2
   return csub(v - mulhi64(v, mc.onep) * q, q);            // v mod q
 }
 
-// grid (n / 64, L, tiles); block 256 = 64 coefficients x 4 item lanes
+// grid (n / 64, L, tiles); block 256 = 64 coefficients x 2 ciphertext parts x
+// 2 item lanes.  A thread keeps one part of one item's g rotated copies in
+// registers (2g 27-bit halves) and streams the tile's plaintexts; splitting the
+// parts over threads halves the registers per thread, so more waves hide the
+// load latency.
 template <int G>
 __global__ __launch_bounds__(256) void k_mac_tiles(const KsItem* __restrict__ items, const MacTile* __restrict__ tiles,
                                                    KsArgs a, int h, DevModuli M) {
@@ -262,41 +266,35 @@ __global__ __launch_bounds__(256) void k_mac_tiles(const KsItem* __restrict__ it
   const int L = a.L;
   const uint64_t n = 1ull << a.log_n;
   const uint64_t x = (uint64_t)blockIdx.x * 64 + (threadIdx.x & 63);
-  const int lane = threadIdx.x >> 6;
+  const int t = (threadIdx.x >> 6) & 1, lane = threadIdx.x >> 7;
   const ModConst mc = M.mc[j];
   const uint64_t c27 = M.c27[j], c27p = M.c27p[j];
   const uint64_t ctw = 2ull * L * n;
   WALLY_GLOBAL const uint64_t* pt = gmem(items[tl.first].pt) + (uint64_t)j * n + x;  // PT[m][j][x] at m * L * n
+  const uint64_t off = ((uint64_t)t * L + j) * n + x;                                  // part t, limb j
   const uint64_t M27 = (1ull << 27) - 1;
-  for (uint32_t k = lane; k < tl.count; k += 4) {
+  for (uint32_t k = lane; k < tl.count; k += 2) {
     const KsItem& it = items[tl.first + k];
-    WALLY_GLOBAL const uint64_t* ctp = gmem(it.ctp);
-    uint32_t c0l[G], c0h[G], c1l[G], c1h[G];
+    WALLY_GLOBAL const uint64_t* ctp = gmem(it.ctp) + off;
+    uint32_t cl[G], ch[G];
 #pragma unroll
     for (int jj = 0; jj < G; ++jj) {
-      const uint64_t v0 = ctp[jj * ctw + (uint64_t)j * n + x];
-      const uint64_t v1 = ctp[jj * ctw + ((uint64_t)L + j) * n + x];
-      c0l[jj] = (uint32_t)(v0 & M27);
-      c0h[jj] = (uint32_t)(v0 >> 27);
-      c1l[jj] = (uint32_t)(v1 & M27);
-      c1h[jj] = (uint32_t)(v1 >> 27);
+      const uint64_t v = ctp[jj * ctw];
+      cl[jj] = (uint32_t)(v & M27);
+      ch[jj] = (uint32_t)(v >> 27);
     }
+    WALLY_GLOBAL uint64_t* acc = gmem(it.acc) + off;
     for (int i = 0; i < h; ++i) {
-      uint64_t a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
+      uint64_t s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
       for (int jj = 0; jj < G; ++jj) {
         const uint64_t w = pt[(uint64_t)(G * i + jj) * L * n];
         const uint32_t wl = (uint32_t)(w & M27), wh = (uint32_t)(w >> 27);
-        a0 += (uint64_t)wl * c0l[jj];
-        a1 += (uint64_t)wl * c0h[jj] + (uint64_t)wh * c0l[jj];
-        a2 += (uint64_t)wh * c0h[jj];
-        b0 += (uint64_t)wl * c1l[jj];
-        b1 += (uint64_t)wl * c1h[jj] + (uint64_t)wh * c1l[jj];
-        b2 += (uint64_t)wh * c1h[jj];
+        s0 += (uint64_t)wl * cl[jj];
+        s1 += (uint64_t)wl * ch[jj] + (uint64_t)wh * cl[jj];
+        s2 += (uint64_t)wh * ch[jj];
       }
-      WALLY_GLOBAL uint64_t* acc = gmem(it.acc) + (uint64_t)i * ctw + (uint64_t)j * n + x;
-      acc[0] = fold27(a0, a1, a2, mc, c27, c27p);
-      acc[(uint64_t)L * n] = fold27(b0, b1, b2, mc, c27, c27p);
+      acc[(uint64_t)i * ctw] = fold27(s0, s1, s2, mc, c27, c27p);
     }
   }
 }
