@@ -274,9 +274,10 @@ def main():
     ctx.encode_clusters(emb, synth.offsets(w.sizes))
     torch.cuda.synchronize()
     encode_s = time.perf_counter() - t0
-    chunks = np.array([ctx.cluster_info(c)[0] for c in range(len(w.sizes))], dtype=np.int64)
-    n_chunks = len({ctx.cluster_info(c)[1] for c in range(len(w.sizes))}) if layout == LAYOUT_COPACK \
-        else int(chunks.sum())
+    cinfo = [ctx.cluster_info(c) for c in range(len(w.sizes))]
+    chunks = np.array([ci[0] for ci in cinfo], dtype=np.int64)
+    base_ptr = min(ci[1] for ci in cinfo)
+    n_chunks = max((ci[1] - base_ptr) // (int(info.pt_chunk_words) * 8) + ci[0] for ci in cinfo)
     log(f"encoded {len(w.sizes)} clusters, {n_chunks} chunks, "
         f"{ctx.bytes_allocated / 2**30:.1f} GiB resident, {encode_s:.2f} s")
     del emb
