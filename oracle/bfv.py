@@ -10,7 +10,8 @@ Paper references: BFV ciphertexts and the decryption identity, paper §2.1
 the operations PtCtMult / CtRotate, §2.1 ("SHE operations and costs"); the
 diagonal encoding and the baby-step giant-step evaluation, §4.1 and the
 Server Initialization / Server Computation algorithms of §5; RNS BFV and hybrid
-key switching, §7.1; ternary secrets and centred-binomial errors, §7.3.
+key switching, §7.1; ternary secrets and centred-binomial errors, §7.3;
+response compression (modulus switching to one limb, dropped low bits), §7.1.
 """
 from __future__ import annotations
 
@@ -98,6 +99,21 @@ def _u64(a):
 def _i64(a):
     a = np.ascontiguousarray(a, dtype=np.int64)
     return a, a.ctypes.data_as(i64p)
+
+
+def pack_bits(values, w: int) -> bytes:
+    """Values of w bits each, little-endian: value k is stream bits [k w, (k+1) w),
+    stream bit b is bit b mod 8 of byte b // 8."""
+    acc = 0
+    for k, v in enumerate(values):
+        acc |= int(v) << (k * w)
+    return acc.to_bytes((len(values) * w + 7) // 8, "little")
+
+
+def unpack_bits(blob: bytes, w: int, count: int):
+    acc = int.from_bytes(blob, "little")
+    mask = (1 << w) - 1
+    return [(acc >> (k * w)) & mask for k in range(count)]
 
 
 class Oracle:
@@ -233,6 +249,62 @@ class Oracle:
         v = np.where(v > Q // 2, v - Q, v)
         nu = max(abs(int(z)) for z in v)
         return math.log2(Q / (2 * t)) - math.log2(max(nu, 1))
+
+    # -- response compression (paper §7.1, "Reducing the response size") -------
+    def drop_bits(self, z: int = 8):
+        """(l0, l1): low bits dropped from c0 and c1 after switching to q_0.
+        The paper sets l0 = log2(q/t) - 2 and l1 <= floor(log2(q/t) - 2 -
+        log2(z sqrt(2n/9))) with z = 8; read here with q = q_0, the floor of
+        log2(q_0/t) for l0, and l1 at its bound (never below 0)."""
+        lg = math.log2(self.p.q[0] / self.p.t)
+        l0 = max(0, math.floor(lg) - 2)
+        l1 = max(0, math.floor(lg - 2 - math.log2(z * math.sqrt(2 * self.n / 9))))
+        return l0, l1
+
+    def compressed_widths(self):
+        """Bits per serialized coefficient of c0 and c1."""
+        b = self.p.q[0].bit_length()
+        return tuple(b - l for l in self.drop_bits())
+
+    def compress(self, ct):
+        """One response ciphertext [2][L][n] (NTT form mod Q) to the serialized
+        form: per part, switch the modulus from Q to q_0 with rounding,
+        c' = round(q_0 c / Q) = round(c / (q_1 ... q_{L-1})), taken on the
+        integer c in [0, Q) of each coefficient (coefficient form); then drop
+        the low l bits, c'' = floor((c' + 2^(l-1)) / 2^l) mod 2^w with
+        w = bits(q_0) - l; and pack the n values of w bits little-endian
+        (value k in stream bits [k w, (k+1) w)).  Returns bytes: part 0, part 1."""
+        Q, q0 = self.p.Q, self.p.q[0]
+        Qp = Q // q0
+        out = bytearray()
+        for part, (l, w) in enumerate(zip(self.drop_bits(), self.compressed_widths())):
+            coef = np.stack([self.intt(ct[part][i], i) for i in range(self.L)])
+            c = self._crt_lift(coef)  # integers in [0, Q)
+            cp = [((2 * int(v) + Qp) // (2 * Qp)) % q0 for v in c]
+            half = (1 << (l - 1)) if l else 0
+            out += pack_bits([((v + half) >> l) % (1 << w) for v in cp], w)
+        return bytes(out)
+
+    def decompress(self, blob):
+        """Serialized response -> (c0, c1) coefficient form mod q_0: v 2^l mod q_0."""
+        q0 = self.p.q[0]
+        parts, pos = [], 0
+        for l, w in zip(self.drop_bits(), self.compressed_widths()):
+            nbytes = self.n * w // 8
+            vals = unpack_bits(blob[pos : pos + nbytes], w, self.n)
+            pos += nbytes
+            parts.append(np.array([(v << l) % q0 for v in vals], dtype=np.uint64))
+        return parts
+
+    def decrypt_compressed(self, s, blob):
+        """Slots of a serialized response: m = round(t [c0 + c1 s]_{q_0} / q_0) mod t."""
+        q0, t = self.p.q[0], self.p.t
+        c0, c1 = self.decompress(blob)
+        s0 = np.array([int(v) % q0 for v in np.asarray(s, dtype=np.int64)], dtype=np.uint64)
+        prod = self.intt((self.ntt(c1, 0).astype(object) * self.ntt(s0, 0).astype(object) % q0).astype(np.uint64), 0)
+        x = [(int(a) + int(b)) % q0 for a, b in zip(c0, prod)]
+        m = [((v * t + q0 // 2) // q0) % t for v in x]
+        return self.decode_slots(np.array(m, dtype=np.uint64))
 
     # -- server ---------------------------------------------------------------
     def rotate(self, ct, key, gal: int):
