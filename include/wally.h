@@ -89,6 +89,9 @@ typedef struct {
   uint64_t key_words; /* words per Galois key = L * 2 * (L+1) * n           */
   uint64_t pt_chunk_words; /* words per encoded chunk = d_pad L n           */
   uint64_t bytes_allocated; /* device bytes held by the context             */
+  uint32_t drop_bits[2];         /* low bits dropped from c0, c1 (compression) */
+  uint32_t compressed_widths[2]; /* bits per serialized coefficient of c0, c1  */
+  uint64_t compressed_chunk_bytes; /* bytes of one compressed response ciphertext */
 } wally_params_info;
 
 /* One query: every pointer is a device pointer.  `out` receives
@@ -119,6 +122,20 @@ int wally_params_query(const wally_ctx* ctx, wally_params_info* out);
  * Replaces any previous index.  Synchronous.  EINVAL, ENOMEM, EDEVICE. */
 int wally_encode_clusters(wally_ctx* ctx, const int8_t* emb, uint64_t n_entries, const uint64_t* offsets,
                           uint32_t k);
+
+/* Response compression (paper §7.1, "Reducing the response size"): each of
+ * `chunks` response ciphertexts in `in` (device, [chunks][2][L][n], NTT form
+ * mod Q, as written by wally_score_batch) is switched from Q to the first
+ * limb q_0 with rounding, c' = round(c q_0 / Q) per coefficient of each part
+ * (exact, in coefficient form), then drop_bits[p] low bits are dropped with
+ * rounding, v = floor((c' + 2^(l-1)) / 2^l) mod 2^w with w =
+ * compressed_widths[p], and the n values of each part are packed little-endian
+ * (value k in stream bits [k w, (k+1) w), stream bit b = bit b%8 of byte b/8).
+ * `out` (device) receives [chunks][compressed_chunk_bytes]: part 0, then part
+ * 1.  A client recovers c' ~ v 2^l mod q_0 and decrypts at modulus q_0.  Work
+ * is enqueued on hip_stream; the context's scratch is shared, so calls must
+ * not overlap on different streams.  EINVAL for null or misaligned pointers. */
+int wally_compress_responses(wally_ctx* ctx, const uint64_t* in, uint64_t chunks, uint8_t* out, void* hip_stream);
 
 /* Chunks of cluster c, the slot of its first entry in its first chunk (0 in
  * the per-cluster layout) and the device address of its plaintexts

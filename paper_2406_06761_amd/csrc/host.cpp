@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -87,6 +88,69 @@ uint64_t min_root(uint64_t q, uint64_t two_n) {
 
 uint64_t shoup_of(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
 
+// responses compressed per pass (the coefficient-form scratch is this many
+// ciphertexts: 512 MiB at n = 8192, L = 4)
+constexpr uint64_t kCompressBatch = 1024;
+
+// little-endian multi-word integers for the compression constants
+void mw_mul_small(std::vector<uint64_t>& x, uint64_t m) {
+  u128 carry = 0;
+  for (uint64_t& w : x) {
+    const u128 v = (u128)w * m + carry;
+    w = (uint64_t)v;
+    carry = v >> 64;
+  }
+  if (carry) x.push_back((uint64_t)carry);
+}
+uint64_t mw_mod_small(const std::vector<uint64_t>& x, uint64_t q) {
+  u128 r = 0;
+  for (size_t k = x.size(); k-- > 0;) r = ((r << 64) | x[k]) % q;
+  return (uint64_t)r;
+}
+
+// Constants of response compression (paper §7.1, "Reducing the response
+// size"): switch from Q to q_0, then drop l0 / l1 low bits of the two parts,
+// l0 = floor(log2(q_0/t)) - 2 and l1 = floor(log2(q_0/t) - 2 - log2(z sqrt(2n/9)))
+// with z = 8 (the bounds of the cited calculation), neither below 0.
+bool compress_constants(const uint64_t* mods, int L, int log_n, uint64_t t, CompressArgs& a) {
+  a = CompressArgs{};
+  a.log_n = log_n;
+  a.L = L;
+  const uint64_t q0 = mods[0];
+  std::vector<uint64_t> qp{1};
+  for (int i = 1; i < L; ++i) mw_mul_small(qp, mods[i]);
+  if (qp.size() > (size_t)kMaxWords) return false;
+  a.words = (int)qp.size();
+  for (int w = 0; w < a.words; ++w) a.qp[w] = qp[w];
+  for (int i = 1; i < L; ++i) {
+    std::vector<uint64_t> m{1};
+    for (int j = 1; j < L; ++j)
+      if (j != i) mw_mul_small(m, mods[j]);
+    for (size_t w = 0; w < m.size() && w < (size_t)kMaxWords; ++w) a.m[i][w] = m[w];
+    const uint64_t qi = mods[i];
+    a.minv[i] = powmod(mw_mod_small(m, qi), qi - 2, qi);
+    a.minvp[i] = shoup_of(a.minv[i], qi);
+    a.mq0[i] = mw_mod_small(m, q0);
+    a.mq0p[i] = shoup_of(a.mq0[i], q0);
+  }
+  a.qpq0 = mw_mod_small(qp, q0);
+  a.qpinv = powmod(a.qpq0, q0 - 2, q0);
+  a.qpinvp = shoup_of(a.qpinv, q0);
+  const double n = (double)(1u << log_n);
+  const double lg = std::log2((double)q0 / (double)t);
+  const long l0 = (long)std::floor(lg) - 2;
+  const long l1 = (long)std::floor(lg - 2 - std::log2(8.0 * std::sqrt(2.0 * n / 9.0)));
+  uint32_t bits = 0;
+  while (bits < 64 && (q0 >> bits)) ++bits;
+  a.drop[0] = (uint32_t)std::max(0L, l0);
+  a.drop[1] = (uint32_t)std::max(0L, l1);
+  for (int p = 0; p < 2; ++p) {
+    a.width[p] = bits - a.drop[p];
+    a.part_bytes[p] = (uint64_t)(1u << log_n) * a.width[p] / 8;
+  }
+  return true;
+}
+
 struct WaveWork {
   // one workspace set: buffers for one wave of queries in flight
   uint64_t* ctp = nullptr;  // [B][g][2][L][n]
@@ -147,6 +211,10 @@ struct wally_ctx {
   uint32_t max_chunks = 0;
   uint64_t n_chunks_total = 0;
   uint64_t* pt = nullptr;
+  // response compression: constants and a coefficient-form scratch
+  CompressArgs comp{};
+  uint64_t* comp_scratch = nullptr;
+  uint64_t comp_scratch_chunks = 0;
   // waves
   int B = 0;
   int n_sets = 2;
@@ -657,6 +725,10 @@ int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
     c->M.pinv[j] = powmod(P % q, q - 2, q);
     c->M.pinvp[j] = shoup_of(c->M.pinv[j], q);
   }
+  if (!compress_constants(c->mods, c->L, c->log_n, c->mods[c->L + 1], c->comp)) {
+    wally_destroy(c);
+    return WALLY_EINVAL;
+  }
   std::vector<uint32_t> slot_of(c->n);
   {
     const uint32_t half = c->n / 2;
@@ -708,6 +780,11 @@ int wally_params_query(const wally_ctx* c, wally_params_info* o) {
   o->key_words = c->keyw();
   o->pt_chunk_words = c->ptw();
   o->bytes_allocated = c->allocated;
+  o->drop_bits[0] = c->comp.drop[0];
+  o->drop_bits[1] = c->comp.drop[1];
+  o->compressed_widths[0] = c->comp.width[0];
+  o->compressed_widths[1] = c->comp.width[1];
+  o->compressed_chunk_bytes = c->comp.part_bytes[0] + c->comp.part_bytes[1];
   return WALLY_OK;
 }
 
@@ -775,6 +852,31 @@ int wally_encode_clusters(wally_ctx* c, const int8_t* emb, uint64_t n_entries, c
   c->slot_base = std::move(lay.base);
   c->max_chunks = *std::max_element(c->chunks.begin(), c->chunks.end());
   c->n_chunks_total = total;
+  return WALLY_OK;
+}
+
+int wally_compress_responses(wally_ctx* c, const uint64_t* in, uint64_t chunks, uint8_t* out, void* hip_stream) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (chunks == 0) return WALLY_OK;
+  if (!in || !out) return set_err(c, WALLY_EINVAL, "null response or output pointer");
+  if ((uintptr_t)in & 7) return set_err(c, WALLY_EINVAL, "responses must be 8-byte aligned");
+  const uint64_t batch = std::min<uint64_t>(chunks, kCompressBatch);
+  if (c->comp_scratch_chunks < batch) {
+    dfree(c, c->comp_scratch);
+    c->comp_scratch = nullptr;
+    c->comp_scratch_chunks = 0;
+    if ((rc = dalloc(c, batch * c->ctw() * 8, (void**)&c->comp_scratch))) return rc;
+    c->comp_scratch_chunks = batch;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  const uint64_t cbytes = c->comp.part_bytes[0] + c->comp.part_bytes[1];
+  for (uint64_t b0 = 0; b0 < chunks; b0 += batch) {
+    const int nb = (int)std::min(batch, chunks - b0);
+    HIP_OK(c, launch_resp_intt(in + b0 * c->ctw(), c->comp_scratch, nb, c->log_n, c->L, c->M, st));
+    HIP_OK(c, launch_resp_pack(c->comp_scratch, out + b0 * cbytes, nb, c->comp, c->M, st));
+  }
   return WALLY_OK;
 }
 

@@ -74,6 +74,25 @@ struct EncodeArgs {
 };
 
 // the key-switching kernels, in launch order
+// Response compression (paper §7.1, "Reducing the response size").  With
+// Q' = q_1 ... q_{L-1} (the limbs switched away), a coefficient c in [0, Q)
+// with residues r_i becomes c' = round(c / Q') mod q_0
+//   = (r_0 - (sum_i y_i [Q'/q_i]_{q0} - k [Q']_{q0})) [Q'^-1]_{q0}   (mod q_0),
+// y_i = [r_i (Q'/q_i)^-1]_{q_i}, k = round(sum_i y_i / q_i), k found exactly
+// from the multi-word remainder of sum_i y_i (Q'/q_i) by Q'.
+constexpr int kMaxWords = 6;  // 64-bit words of Q' (up to 7 limbs of 54 bits)
+struct CompressArgs {
+  int log_n, L, words;                 // words of Q' (>= 1)
+  uint32_t drop[2], width[2];          // dropped low bits and serialized width per part
+  uint64_t part_bytes[2];              // n * width / 8
+  uint64_t qp[kMaxWords];              // Q'
+  uint64_t m[kMaxMod][kMaxWords];      // Q'/q_i, i = 1 .. L-1
+  uint64_t minv[kMaxMod], minvp[kMaxMod];  // (Q'/q_i)^-1 mod q_i and Shoup factor
+  uint64_t mq0[kMaxMod], mq0p[kMaxMod];    // Q'/q_i mod q_0 and Shoup factor
+  uint64_t qpq0;                       // Q' mod q_0
+  uint64_t qpinv, qpinvp;              // Q'^-1 mod q_0 and Shoup factor
+};
+
 hipError_t launch_ks_digits(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
 hipError_t launch_ks_extend(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
 hipError_t launch_ks_inner(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
@@ -82,6 +101,12 @@ hipError_t launch_ks_moddown(const KsItem* items, int n_items, const KsArgs& a, 
 // acc_i = sum_{j<g} PT[g i + j] * ct'_j for every giant index i of every item
 hipError_t launch_mac_tiles(const KsItem* items, const MacTile* tiles, int n_tiles, const KsArgs& a, int h,
                             const DevModuli& M, hipStream_t st);
+// rows [chunks][2][L][n], NTT form -> coefficient form in [0, q_i) (in to out)
+hipError_t launch_resp_intt(const uint64_t* in, uint64_t* out, int chunks, int log_n, int L, const DevModuli& M,
+                            hipStream_t st);
+// coefficient rows [chunks][2][L][n] -> serialized responses [chunks][part_bytes[0] + part_bytes[1]]
+hipError_t launch_resp_pack(const uint64_t* coef, uint8_t* out, int chunks, const CompressArgs& a, const DevModuli& M,
+                            hipStream_t st);
 hipError_t launch_copy_ct(const CopyItem* items, int n_items, uint64_t words, hipStream_t st);
 hipError_t launch_encode(const EncodeJob* jobs, int n_jobs, const EncodeArgs& a, const DevModuli& M, hipStream_t st);
 hipError_t launch_ntt_rows(uint64_t* data, int rows, int log_n, int mi, int inverse, const DevModuli& M,

@@ -388,6 +388,123 @@ __global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_ntt_rows(uint64_t* d
 }
 
 // ---------------------------------------------------------------------------
+// response compression (paper §7.1, "Reducing the response size")
+
+// one row per workgroup: row r of [chunks][2][L][n] is limb r mod L
+template <int LOGN>
+__global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_resp_intt(const uint64_t* __restrict__ in,
+                                                                      uint64_t* __restrict__ out, int L, DevModuli M) {
+  using S = NttShape<LOGN, 4>;
+  using FM = FirstMap<LOGN, 4>;
+  __shared__ uint64_t lds[S::LDS_WORDS];
+  const int tid = threadIdx.x;
+  const int mi = (int)(blockIdx.x % (uint32_t)L);
+  const uint64_t q = M.q[mi];
+  const uint64_t* src = in + (uint64_t)blockIdx.x * S::N;
+  uint64_t* dst = out + (uint64_t)blockIdx.x * S::N;
+  uint64_t x[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) x[e] = src[FM::idx(tid, e)];
+  ntt_inv_nat<LOGN, 4>(x, lds, M.inv[mi], q, tid);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) dst[FM::idx(tid, e)] = csub(shoup(x[e], M.ninv[mi], M.ninvp[mi], q), q);
+}
+
+// a += y * m (multi-word, `words` words of m, a has words + 1)
+__device__ __forceinline__ void mw_mac(uint64_t* acc, uint64_t y, const uint64_t* m, int words) {
+  uint64_t carry = 0;
+  for (int w = 0; w < words; ++w) {
+    const uint64_t lo = y * m[w], hi = __umul64hi(y, m[w]);
+    uint64_t s = acc[w] + lo;
+    uint64_t c = s < lo;
+    s += carry;
+    c += s < carry;
+    acc[w] = s;
+    carry = hi + c;
+  }
+  acc[words] += carry;
+}
+
+// thread per (chunk, part, group of 8 coefficients); the group's 8 values of
+// width w are written as w consecutive bytes (little-endian bit stream)
+__global__ __launch_bounds__(256) void k_resp_pack(const uint64_t* __restrict__ coef, uint8_t* __restrict__ out,
+                                                   int chunks, CompressArgs a, DevModuli M) {
+  const uint64_t n = 1ull << a.log_n;
+  const uint64_t groups = n / 8;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (uint64_t)chunks * 2 * groups) return;
+  const uint64_t g = gid % groups;
+  const int part = (int)((gid / groups) & 1);
+  const uint64_t chunk = gid / (2 * groups);
+  const int L = a.L, W = a.words;
+  const uint64_t q0 = M.q[0];
+  const ModConst mc0 = M.mc[0];
+  const uint64_t* rows = coef + ((chunk * 2 + part) * L) * n + g * 8;
+  const uint32_t l = a.drop[part], w = a.width[part];
+  const uint64_t half = l ? (1ull << (l - 1)) : 0, mask = (w == 64) ? ~0ull : ((1ull << w) - 1);
+  uint8_t* o = out + chunk * (a.part_bytes[0] + a.part_bytes[1]) + (part ? a.part_bytes[0] : 0) + g * w;
+  uint64_t bits = 0;
+  uint32_t nb = 0;
+  for (int k = 0; k < 8; ++k) {
+    uint64_t S[kMaxWords + 1] = {0, 0, 0, 0, 0, 0, 0};
+    u128w rq{0, 0};  // sum_i y_i [Q'/q_i]_{q0}
+    for (int i = 1; i < L; ++i) {
+      const uint64_t qi = M.q[i];
+      const uint64_t y = csub(shoup(rows[(uint64_t)i * n + k], a.minv[i], a.minvp[i], qi), qi);
+      mw_mac(S, y, a.m[i], W);
+      mac128(rq, y, a.mq0[i]);
+    }
+    // k = round(S / Q'): subtract Q' while S >= Q', then one more if 2 S > Q'
+    uint32_t kc = 0;
+    for (;;) {
+      bool ge = true;  // S >= Q'
+      for (int wd = W; wd >= 0; --wd) {
+        const uint64_t qw = wd < W ? a.qp[wd] : 0;
+        if (S[wd] != qw) {
+          ge = S[wd] > qw;
+          break;
+        }
+      }
+      if (!ge) break;
+      uint64_t br = 0;
+      for (int wd = 0; wd <= W; ++wd) {
+        const uint64_t qw = wd < W ? a.qp[wd] : 0;
+        const uint64_t d = S[wd] - qw - br;
+        br = (S[wd] < qw) || (S[wd] - qw < br);
+        S[wd] = d;
+      }
+      ++kc;
+    }
+    {  // 2 S > Q'  (S < Q' here, so 2 S fits in W + 1 words)
+      bool gt = false;
+      for (int wd = W; wd >= 0; --wd) {
+        const uint64_t two = (S[wd] << 1) | (wd ? S[wd - 1] >> 63 : 0);
+        const uint64_t qw = wd < W ? a.qp[wd] : 0;
+        if (two != qw) {
+          gt = two > qw;
+          break;
+        }
+      }
+      kc += gt;
+    }
+    const uint64_t rmod = reduce128(rq, q0, mc0.r64, mc0.r64p, mc0.onep);
+    uint64_t kq = 0;  // k [Q']_{q0}, k <= L - 1
+    for (uint32_t r = 0; r < kc; ++r) kq = addmod(kq, a.qpq0, q0);
+    const uint64_t rc = submod(rmod, kq, q0);                  // [centred remainder]_{q0}
+    const uint64_t d = submod(rows[k], rc, q0);                 // r_0 - r_c
+    const uint64_t cp = csub(shoup(d, a.qpinv, a.qpinvp, q0), q0);  // c' in [0, q0)
+    const uint64_t v = ((cp + half) >> l) & mask;
+    bits |= v << nb;
+    nb += w;
+    while (nb >= 8) {
+      *o++ = (uint8_t)bits;
+      bits >>= 8;
+      nb -= 8;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 
 // KERNEL<LOGN, LOGE> with T = n / 2^LOGE threads
@@ -470,6 +587,26 @@ hipError_t launch_ntt_rows(uint64_t* data, int rows, int log_n, int mi, int inve
     case 13: hipLaunchKernelGGL(k_ntt_rows<13>, dim3(rows), dim3(NttShape<13, 4>::T), 0, st, data, mi, inverse, M); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_resp_intt(const uint64_t* in, uint64_t* out, int chunks, int log_n, int L, const DevModuli& M,
+                            hipStream_t st) {
+  if (chunks <= 0) return hipSuccess;
+  const dim3 grid((uint32_t)chunks * 2 * (uint32_t)L);
+  switch (log_n) {
+    case 12: hipLaunchKernelGGL(k_resp_intt<12>, grid, dim3(NttShape<12, 4>::T), 0, st, in, out, L, M); break;
+    case 13: hipLaunchKernelGGL(k_resp_intt<13>, grid, dim3(NttShape<13, 4>::T), 0, st, in, out, L, M); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_resp_pack(const uint64_t* coef, uint8_t* out, int chunks, const CompressArgs& a, const DevModuli& M,
+                            hipStream_t st) {
+  if (chunks <= 0) return hipSuccess;
+  const uint64_t threads = (uint64_t)chunks * 2 * ((1ull << a.log_n) / 8);
+  hipLaunchKernelGGL(k_resp_pack, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, st, coef, out, chunks, a, M);
   return hipGetLastError();
 }
 

@@ -42,7 +42,8 @@ class ParamsInfo(ctypes.Structure):
                 ("t", ctypes.c_uint64), ("psi", ctypes.c_uint64 * 9), ("psi_t", ctypes.c_uint64),
                 ("gal_baby", ctypes.c_uint64), ("gal_giant", ctypes.c_uint64), ("ct_words", ctypes.c_uint64),
                 ("key_words", ctypes.c_uint64), ("pt_chunk_words", ctypes.c_uint64),
-                ("bytes_allocated", ctypes.c_uint64)]
+                ("bytes_allocated", ctypes.c_uint64), ("drop_bits", ctypes.c_uint32 * 2),
+                ("compressed_widths", ctypes.c_uint32 * 2), ("compressed_chunk_bytes", ctypes.c_uint64)]
 
 
 class Query(ctypes.Structure):
@@ -55,7 +56,7 @@ assert ctypes.sizeof(Query) == QUERY_DTYPE.itemsize
 # every symbol declared in include/wally.h and include/wally_diag.h
 SYMBOLS = [
     "wally_params_init", "wally_params_query", "wally_encode_clusters", "wally_cluster_info", "wally_score_batch",
-    "wally_tune",
+    "wally_tune", "wally_compress_responses",
     "wally_serve_start", "wally_serve_submit", "wally_serve_poll", "wally_serve_stop", "wally_strerror",
     "wally_last_error", "wally_destroy", "wally_diag_ntt", "wally_diag_rotate", "wally_diag_kernel_timing",
     "wally_diag_kernel_stats",
@@ -94,6 +95,7 @@ def load():
         "wally_encode_clusters": ([vp, vp, u64, vp, u32], i32),
         "wally_cluster_info": ([vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(vp)], i32),
         "wally_score_batch": ([vp, vp, u64, i32, vp], i32),
+        "wally_compress_responses": ([vp, vp, u64, vp, vp], i32),
         "wally_tune": ([vp, vp, u64, vp, vp, vp, ctypes.POINTER(TuneEntry), u32, ctypes.POINTER(u32)], i32),
         "wally_serve_start": ([vp, vp], i32),
         "wally_serve_submit": ([vp, ctypes.POINTER(Query), ctypes.POINTER(u64)], i32),
@@ -178,6 +180,15 @@ class Context:
         self._check(self.lib.wally_cluster_info(self.h, c, ctypes.byref(n), ctypes.byref(b), ctypes.byref(p)),
                     "wally_cluster_info")
         return n.value, p.value, b.value
+
+    def compress_responses(self, responses, out, stream=None):
+        """responses: device tensor of [chunks][2][L][n] words; out: device
+        uint8 tensor of chunks * info.compressed_chunk_bytes bytes."""
+        chunks = responses.numel() // self.info.ct_words
+        if out.numel() * out.element_size() < chunks * self.info.compressed_chunk_bytes:
+            raise ValueError("output buffer too small")
+        self._check(self.lib.wally_compress_responses(self.h, _ptr(responses), chunks, _ptr(out),
+                                                      _stream_handle(stream)), "wally_compress_responses")
 
     def score_batch(self, queries: np.ndarray, path=PATH_BATCHED, stream=None):
         """queries: numpy array of QUERY_DTYPE (device pointers)."""
