@@ -229,6 +229,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner")
     ap.add_argument("--graph-steps", type=int, default=2, help="timed steps of the graph-captured path (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--no-compress", action="store_true", help="skip the response-compression leg")
     args = ap.parse_args()
     if args.serve_rates is None:
         args.serve_rates = "5000,20000,50000" if args.workload == "paper" else ""
@@ -368,6 +369,28 @@ def main():
         for k, (nl, it, ms) in kstats.items():
             log(f"  {k:11s} launches {nl:7d} items {it:9d} total {ms:9.1f} ms avg {ms / max(nl, 1):.3f} ms")
 
+    # Response compression (switch to one limb, dropped low bits, packed) of
+    # the batch's responses, timed on its own after the scoring steps.
+    compress = None
+    if not args.no_compress:
+        chunks_out = int(outs.numel()) // ctw
+        cb = int(info.compressed_chunk_bytes)
+        comp = torch.empty(chunks_out * cb, dtype=torch.uint8, device="cuda")
+        ctx.compress_responses(outs, comp)  # warm-up (scratch allocation)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.compress_responses(outs, comp)
+        torch.cuda.synchronize()
+        cdt = time.perf_counter() - t0
+        in_b, out_b = chunks_out * ctw * 8, chunks_out * cb
+        compress = {"chunks": chunks_out, "ms": cdt * 1e3, "bytes_in": in_b, "bytes_out": out_b,
+                    "ratio": in_b / out_b, "chunks_per_s": chunks_out / cdt,
+                    "hbm_gbs": (in_b + out_b) / cdt / 1e9, "hbm_frac": (in_b + out_b) / cdt / HBM_PEAK,
+                    "drop_bits": list(info.drop_bits), "widths": list(info.compressed_widths)}
+        log(f"compress: {chunks_out} responses in {cdt * 1e3:.1f} ms, {in_b / out_b:.2f}x smaller, "
+            f"{(in_b + out_b) / cdt / 1e9:.0f} GB/s of response bytes")
+        del comp
+
     # Isolated kernel rates: the key-switch kernels alone on one stream
     # (1,024 items through the rotation entry point), so each launch has the
     # GPU to itself; the timed region above runs two streams whose launches
@@ -472,6 +495,7 @@ def main():
         "speedup_vs_plain": (value / plain) if plain else None,
         "encode_s": encode_s,
         "tuned": tuned,
+        "response_compression": compress,
         "serving": serving,
         "roofline": roofline,
         "kernels_ms": {k: v[2] for k, v in kstats.items()},

@@ -11,7 +11,9 @@ the decryption equals the int64 dot products (within the no-wrap bound of
 paper §7.3 the centred lift mod t is the integer dot product).
 
 * paper: 3.2M x 192 entries, 1,800 lognormal(0.8) clusters, 50,000 Zipf(1.1)
-  real queries + NB(2, 0.5) fakes, per-cluster layout, batched path;
+  real queries + NB(2, 0.5) fakes, per-cluster layout, batched path; all
+  responses also compressed (paper §7.1), sampled ones checked byte for byte
+  and by decryption;
 * batch of 500k: the same index and 500,000 real queries + fakes in one
   batched call; the ~258 GB of responses do not fit beside the index,
   so unchecked queries share a ring of response slots (checked ones own
@@ -38,7 +40,7 @@ def _query_vec(w, i):
     return synth.embeddings(1, w.dim, seed=synth.SEED_QUERIES, norm=w.norm, row_start=i)[0]
 
 
-def _sampled_parity(ctx, p, w, emb, lay, batch, picks, path, ring=0, pool=2048):
+def _sampled_parity(ctx, p, w, emb, lay, batch, picks, path, ring=0, pool=2048, compress=False):
     """Score logical queries `batch` of workload `w` (picks get real packets),
     then check picks and a few pool-packet queries against the oracle."""
     from paper_2406_06761_amd.wally import query_array, to_device, to_host
@@ -105,12 +107,31 @@ def _sampled_parity(ctx, p, w, emb, lay, batch, picks, path, ring=0, pool=2048):
                      to_host(kgs[pi]).reshape(L, 2, L + 1, n), cluster_pt(c)))
         metas.append((k, c, None, None))
     refs = o.score_many(jobs, threads=8)
+    comp = None
+    if compress:  # the whole batch's responses, serialized on the GPU (paper §7.1)
+        cb = ctx.info.compressed_chunk_bytes
+        total = int(outs.numel()) // ctw
+        comp_dev = torch.empty(total * cb, dtype=torch.uint8, device="cuda")
+        ctx.compress_responses(outs, comp_dev)
+        torch.cuda.synchronize()
+        comp = comp_dev.cpu().numpy().tobytes()
+        print(f"{w.name}: compressed {total} responses, {total * cb / 2**30:.2f} GiB", flush=True)
     half_t = (p.t - 1) // 2
     for (k, c, vec, s), ref in zip(metas, refs):
         got = to_host(outs[out_off[k] * ctw : (out_off[k] + q_chunks[k]) * ctw]).reshape(q_chunks[k], 2, L, n)
         assert (got == ref).all(), (int(batch[k]), c)
+        blobs = None
+        if comp is not None:
+            blobs = [comp[(out_off[k] + j) * cb : (out_off[k] + j + 1) * cb] for j in range(q_chunks[k])]
+            for j in range(q_chunks[k]):
+                assert blobs[j] == o.compress(ref[j]), (int(batch[k]), c, j)
         if vec is None:
             continue
+        if blobs is not None:
+            decc = np.concatenate([o.decrypt_compressed(s, b) for b in blobs]).astype(np.int64)
+            centredc = np.where(decc > half_t, decc - p.t, decc)
+            rows_ = emb[int(offs[c]) : int(offs[c + 1])].astype(np.int64)
+            assert (centredc[lay.base[c] : lay.base[c] + len(rows_)] == rows_ @ vec.astype(np.int64)).all()
         rows = emb[int(offs[c]) : int(offs[c + 1])].astype(np.int64)
         dec = np.concatenate([o.decrypt(s, got[j]) for j in range(q_chunks[k])]).astype(np.int64)
         centred = np.where(dec > half_t, dec - p.t, dec)
@@ -152,7 +173,7 @@ def test_paper_scale_sampled_parity():
         _check_layout(ctx, lay, p, 7)
         real, counts, chosen = _hot_cold_multi(w, lay)
         picks = {int(i) for c in chosen for i in np.nonzero(real == c)[0][:2]} | {w.n_real}  # + the first fake
-        checked = _sampled_parity(ctx, p, w, emb, lay, range(len(w.targets)), picks, PATH_BATCHED)
+        checked = _sampled_parity(ctx, p, w, emb, lay, range(len(w.targets)), picks, PATH_BATCHED, compress=True)
         assert checked >= 6
     finally:
         ctx.close()
