@@ -353,19 +353,24 @@ def main():
         kstats = ctx.kernel_stats()
         ctx.kernel_timing(False)
         work = {k: per_item_work(k, n, L, info.g, info.h) for k in kstats}
-        dom = max((k for k in kstats if work[k] > 0), key=lambda k: kstats[k][2])
+        dom = max((k for k in kstats if work[k] > 0 and kstats[k][0]), key=lambda k: kstats[k][2])
         launches, items, total_ms = kstats[dom]
         avg_ms = total_ms / max(launches, 1)
         items_per_launch = items / max(launches, 1)
-        achieved = work[dom] * items_per_launch / (avg_ms * 1e-3)
         peak = PEAK_VALU_LANE_OPS / INSTR_PER_MODMUL
         step_work = sum(kstats[k][1] * work[k] for k in kstats) / args.steps
-        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e9, "peak": peak / 1e9,
-                    "unit": "Gmodmul/s", "frac": achieved / peak, "traffic": None,
-                    "avg_launch_ms": avg_ms, "items_per_launch": items_per_launch,
-                    "work_per_item": work[dom],
-                    "path_gmodmul_per_s": step_work / (ms_per_step * 1e-3) / 1e9,
-                    "path_frac": step_work / (ms_per_step * 1e-3) / peak}
+        if dom == "ks_inner":  # streams the key: HBM bound
+            achieved = inner_bytes(n, L) * items_per_launch / (avg_ms * 1e-3)
+            roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
+                        "bytes_per_item": inner_bytes(n, L)}
+        else:
+            achieved = work[dom] * items_per_launch / (avg_ms * 1e-3)
+            roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e9, "peak": peak / 1e9,
+                        "unit": "Gmodmul/s", "frac": achieved / peak, "traffic": None, "work_per_item": work[dom]}
+        roofline.update({"avg_launch_ms": avg_ms, "items_per_launch": items_per_launch,
+                         "path_gmodmul_per_s": step_work / (ms_per_step * 1e-3) / 1e9,
+                         "path_frac": step_work / (ms_per_step * 1e-3) / peak})
         for k, (nl, it, ms) in kstats.items():
             log(f"  {k:11s} launches {nl:7d} items {it:9d} total {ms:9.1f} ms avg {ms / max(nl, 1):.3f} ms")
 
