@@ -34,6 +34,7 @@ _MAX = 8
 u64p = ctypes.POINTER(ctypes.c_uint64)
 i64p = ctypes.POINTER(ctypes.c_int64)
 i8p = ctypes.POINTER(ctypes.c_int8)
+i16p = ctypes.POINTER(ctypes.c_int16)
 
 
 def build(force: bool = True) -> Path:
@@ -79,6 +80,7 @@ def _load():
             "or_rotate": [P, u64p, u64p, ctypes.c_uint64, u64p],
             "or_ptct_mul": [P, u64p, u64p, u64p],
             "or_encode_cluster": [P, i8p, ctypes.c_uint64, u64p],
+            "or_encode_cluster16": [P, i16p, ctypes.c_uint64, u64p],
             "or_score": [P, u64p, u64p, u64p, u64p, ctypes.c_uint64, u64p],
         }
         for name, args in sig.items():
@@ -99,6 +101,19 @@ def _u64(a):
 def _i64(a):
     a = np.ascontiguousarray(a, dtype=np.int64)
     return a, a.ctypes.data_as(i64p)
+
+
+def crt_combine(m0, m1, t0: int, t1: int):
+    """Plaintext CRT (paper §7.3): the integers in (-t0 t1 / 2, t0 t1 / 2]
+    congruent to m0 mod t0 and m1 mod t1."""
+    T = t0 * t1
+    u = pow(t1, -1, t0) * t1 % T  # 1 mod t0, 0 mod t1
+    w = pow(t0, -1, t1) * t0 % T  # 0 mod t0, 1 mod t1
+    out = np.empty(len(m0), dtype=np.int64)
+    for k, (a, b) in enumerate(zip(m0, m1)):
+        x = (int(a) * u + int(b) * w) % T
+        out[k] = x - T if x > T // 2 else x
+    return out
 
 
 def pack_bits(values, w: int) -> bytes:
@@ -325,12 +340,16 @@ class Oracle:
         return int(self.lib.or_cluster_chunks(self._ps, n_entries))
 
     def encode_cluster(self, emb):
-        """int8 [N_c][d] -> plaintexts [chunks][d_pad][L][n]."""
-        emb = np.ascontiguousarray(emb, dtype=np.int8)
+        """int8 or int16 [N_c][d] -> plaintexts [chunks][d_pad][L][n]."""
+        wide = np.asarray(emb).dtype == np.int16
+        emb = np.ascontiguousarray(emb, dtype=np.int16 if wide else np.int8)
         assert emb.ndim == 2 and emb.shape[1] == self.p.dim
         chunks = self.cluster_chunks(emb.shape[0])
         out = np.empty((chunks, self.p.d_pad, self.L, self.n), dtype=np.uint64)
-        self.lib.or_encode_cluster(self._ps, emb.ctypes.data_as(i8p), emb.shape[0], out.ctypes.data_as(u64p))
+        if wide:
+            self.lib.or_encode_cluster16(self._ps, emb.ctypes.data_as(i16p), emb.shape[0], out.ctypes.data_as(u64p))
+        else:
+            self.lib.or_encode_cluster(self._ps, emb.ctypes.data_as(i8p), emb.shape[0], out.ctypes.data_as(u64p))
         return out
 
     def score(self, ct, key_baby, key_giant, pt):
@@ -359,6 +378,19 @@ class Oracle:
         v = np.zeros(self.p.d_pad, dtype=np.int64)
         v[: len(qvec)] = np.asarray(qvec, dtype=np.int64)
         return np.tile(v, self.n // self.p.d_pad) % self.p.t
+
+    def make_crt_query(self, other, qvec, rng):
+        """Plaintext CRT (paper §7.3): one secret key and one pair of rotation
+        keys (they do not depend on t), the query encrypted under this oracle's
+        t and under `other`'s (same ciphertext moduli).  Returns (ct, ct_other,
+        key_baby, key_giant, s)."""
+        assert other.p.q == self.p.q and other.p.P == self.p.P and other.n == self.n
+        s = self.secret_key(rng)
+        ct = self.encrypt(s, self.query_slots(qvec), rng)
+        ct2 = other.encrypt(s, other.query_slots(qvec), rng)
+        kb = self.galois_key(s, self.p.gal_baby, rng)
+        kg = self.galois_key(s, self.p.gal_giant, rng)
+        return ct, ct2, kb, kg, s
 
     def make_query(self, qvec, rng):
         """A fresh key pair and the query packet (ct, key_baby, key_giant, s)."""

@@ -398,7 +398,23 @@ uint64_t or_cluster_chunks(const or_params* p, uint64_t n_entries) {
  * g*i + j rotated right by g*i within each row (the baby-step giant-step
  * pre-rotation), slot-encoded mod t, lifted and put in NTT form per limb.
  * emb: int8 [n_entries][d] row-major; out: [chunks][d_pad][L][n]. */
+static int64_t entry_value(const void* emb, int elem_bytes, uint64_t i) {
+  return elem_bytes == 1 ? (int64_t)((const int8_t*)emb)[i] : (int64_t)((const int16_t*)emb)[i];
+}
+
+static void encode_cluster_any(const or_params* p, const void* emb, int elem_bytes, uint64_t n_entries, uint64_t* out);
+
 void or_encode_cluster(const or_params* p, const int8_t* emb, uint64_t n_entries, uint64_t* out) {
+  encode_cluster_any(p, emb, 1, n_entries, out);
+}
+
+/* The same with int16 entries (higher-precision embeddings for the plaintext
+ * CRT variant, paper 7.3). */
+void or_encode_cluster16(const or_params* p, const int16_t* emb, uint64_t n_entries, uint64_t* out) {
+  encode_cluster_any(p, emb, 2, n_entries, out);
+}
+
+static void encode_cluster_any(const or_params* p, const void* emb, int elem_bytes, uint64_t n_entries, uint64_t* out) {
   const uint32_t n = 1u << p->log_n, half = n / 2;
   const uint32_t dp = (uint32_t)p->d_pad, d = (uint32_t)p->d;
   const uint64_t chunks = or_cluster_chunks(p, n_entries);
@@ -413,7 +429,7 @@ void or_encode_cluster(const or_params* p, const int8_t* emb, uint64_t n_entries
           const uint64_t entry = k * n + s;
           const uint32_t coord = ((s % dp) + m) % dp;
           int64_t v = 0;
-          if (entry < n_entries && coord < d) v = emb[entry * d + coord];
+          if (entry < n_entries && coord < d) v = entry_value(emb, elem_bytes, entry * d + coord);
           diag[s] = smod(v, p->t);
         }
         const uint32_t r = (uint32_t)(p->g * i) % half;

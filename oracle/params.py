@@ -66,7 +66,9 @@ def ntt_primes(log_n: int, bits: int, count: int) -> list[int]:
 def plain_modulus(log_n: int, t_bits: int) -> int:
     """Smallest prime above 2**t_bits congruent to 1 mod 2n."""
     two_n = 2 << log_n
-    t = (2**t_bits // two_n + 1) * two_n + 1
+    t = (2**t_bits // two_n) * two_n + 1  # first t = 1 mod 2n above 2**t_bits
+    if t <= 2**t_bits:
+        t += two_n
     while not is_prime(t):
         t += two_n
     return t
@@ -149,6 +151,12 @@ PRESETS = {
     "tiny": dict(log_n=12, L=3, limb_bits=36, t_bits=20, dim=64),
     "paper": dict(log_n=13, L=4, limb_bits=54, t_bits=22, dim=192),
     "large": dict(log_n=13, L=4, limb_bits=54, t_bits=23, dim=384),
+    # plaintext CRT (paper §7.3): the same ciphertext moduli with two plaintext
+    # moduli just above 2^16 and 2^17
+    "tiny_t16": dict(log_n=12, L=3, limb_bits=36, t_bits=16, dim=64),
+    "tiny_t17": dict(log_n=12, L=3, limb_bits=36, t_bits=17, dim=64),
+    "paper_t16": dict(log_n=13, L=4, limb_bits=54, t_bits=16, dim=192),
+    "paper_t17": dict(log_n=13, L=4, limb_bits=54, t_bits=17, dim=192),
 }
 
 

@@ -669,7 +669,8 @@ int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
       if (is_prime(cand)) c->mods[found++] = cand;
       cand -= two_n;
     }
-    uint64_t t = ((1ull << desc->t_bits) / two_n + 1) * two_n + 1;
+    uint64_t t = ((1ull << desc->t_bits) / two_n) * two_n + 1;  // first t = 1 mod 2n above 2^t_bits
+    if (t <= (1ull << desc->t_bits)) t += two_n;
     while (!is_prime(t)) t += two_n;
     c->mods[c->L + 1] = t;
   }

@@ -69,3 +69,12 @@ def test_bsgs_split_and_galois_elements():
 def test_delta_is_floor_q_over_t():
     p = preset("paper")
     assert p.delta * p.t <= p.Q < (p.delta + 1) * p.t
+
+
+def test_plain_modulus_takes_the_fermat_prime():
+    # 2^16 + 1 = 65537 is prime and 65536 is a multiple of 2n for n <= 2^15,
+    # so it is the smallest prime above 2^16 that is 1 mod 2n
+    from oracle.params import plain_modulus
+
+    assert plain_modulus(12, 16) == 65537 and plain_modulus(13, 16) == 65537
+    assert plain_modulus(13, 22) == 4423681 and plain_modulus(12, 20) == 1073153
