@@ -123,6 +123,15 @@ int wally_params_query(const wally_ctx* ctx, wally_params_info* out);
 int wally_encode_clusters(wally_ctx* ctx, const int8_t* emb, uint64_t n_entries, const uint64_t* offsets,
                           uint32_t k);
 
+/* The same with int16 entries: the higher-precision embeddings of the
+ * plaintext-CRT variant (paper §7.3), where a context per plaintext modulus
+ * (t_bits 16 and 17) scores the query encrypted under each, with the same
+ * rotation keys, and the client recombines the two results by the CRT.
+ * Entries must be small enough that the dot products stay below t/2 of the
+ * combined modulus for the result to be the integer dot product. */
+int wally_encode_clusters_i16(wally_ctx* ctx, const int16_t* emb, uint64_t n_entries, const uint64_t* offsets,
+                              uint32_t k);
+
 /* Response compression (paper §7.1, "Reducing the response size"): each of
  * `chunks` response ciphertexts in `in` (device, [chunks][2][L][n], NTT form
  * mod Q, as written by wally_score_batch) is switched from Q to the first

@@ -789,7 +789,28 @@ int wally_params_query(const wally_ctx* c, wally_params_info* o) {
   return WALLY_OK;
 }
 
+}  // extern "C"
+
+namespace {
+int encode_clusters(wally_ctx* c, const void* emb, int elem, uint64_t n_entries, const uint64_t* offsets, uint32_t k);
+}  // namespace
+
+extern "C" {
+
 int wally_encode_clusters(wally_ctx* c, const int8_t* emb, uint64_t n_entries, const uint64_t* offsets, uint32_t k) {
+  return encode_clusters(c, emb, 1, n_entries, offsets, k);
+}
+
+int wally_encode_clusters_i16(wally_ctx* c, const int16_t* emb, uint64_t n_entries, const uint64_t* offsets,
+                              uint32_t k) {
+  return encode_clusters(c, emb, 2, n_entries, offsets, k);
+}
+
+}  // extern "C"
+
+namespace {
+
+int encode_clusters(wally_ctx* c, const void* emb, int elem, uint64_t n_entries, const uint64_t* offsets, uint32_t k) {
   int rc = check_live(c);
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(c->mu);
@@ -810,21 +831,23 @@ int wally_encode_clusters(wally_ctx* c, const int8_t* emb, uint64_t n_entries, c
   if ((rc = dalloc(c, total * ptw * 8, (void**)&c->pt))) return rc;
   // rows in chunk order: a chunk's entries are consecutive rows from slot 0
   // (a copy only where clusters share chunks)
-  std::vector<int8_t> packed;
-  const int8_t* src = emb;
+  const uint64_t row_bytes = (uint64_t)c->d * elem;
+  std::vector<uint8_t> packed;
+  const uint8_t* src = (const uint8_t*)emb;
   if (c->layout == WALLY_LAYOUT_COPACK) {
-    packed.resize(n_entries * c->d);
+    packed.resize(n_entries * row_bytes);
     uint64_t r = 0;
     for (const auto& segs : lay.segs)
       for (const auto& sg : segs) {
-        std::memcpy(packed.data() + r * c->d, emb + (offsets[sg.cluster] + sg.offset) * c->d, sg.count * c->d);
+        std::memcpy(packed.data() + r * row_bytes, src + (offsets[sg.cluster] + sg.offset) * row_bytes,
+                    sg.count * row_bytes);
         r += sg.count;
       }
     src = packed.data();
   }
-  int8_t* demb = nullptr;
+  uint8_t* demb = nullptr;
   EncodeJob* djobs = nullptr;
-  if ((rc = dalloc(c, n_entries * c->d, (void**)&demb))) return rc;
+  if ((rc = dalloc(c, n_entries * row_bytes, (void**)&demb))) return rc;
   if ((rc = dalloc(c, total * sizeof(EncodeJob), (void**)&djobs))) {
     dfree(c, demb);
     return rc;
@@ -834,12 +857,12 @@ int wally_encode_clusters(wally_ctx* c, const int8_t* emb, uint64_t n_entries, c
   for (uint64_t ch = 0; ch < total; ++ch) {
     uint64_t cnt = 0;
     for (const auto& sg : lay.segs[ch]) cnt += sg.count;
-    jobs[ch] = EncodeJob{demb + row * c->d, cnt, c->pt + ch * ptw};
+    jobs[ch] = EncodeJob{demb + row * row_bytes, cnt, c->pt + ch * ptw};
     row += cnt;
   }
-  hipError_t e = hipMemcpy(demb, src, n_entries * c->d, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(demb, src, n_entries * row_bytes, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(djobs, jobs.data(), total * sizeof(EncodeJob), hipMemcpyHostToDevice);
-  EncodeArgs a{c->log_n, c->L, (uint32_t)c->d, (uint32_t)c->d_pad, (uint32_t)c->g, c->slot_of};
+  EncodeArgs a{c->log_n, c->L, (uint32_t)c->d, (uint32_t)c->d_pad, (uint32_t)c->g, elem == 2 ? 1u : 0u, c->slot_of};
   const uint64_t step = 4096;
   for (uint64_t j0 = 0; e == hipSuccess && j0 < total; j0 += step)
     e = launch_encode(djobs + j0, (int)std::min(step, total - j0), a, c->M, nullptr);
@@ -855,6 +878,10 @@ int wally_encode_clusters(wally_ctx* c, const int8_t* emb, uint64_t n_entries, c
   c->n_chunks_total = total;
   return WALLY_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int wally_compress_responses(wally_ctx* c, const uint64_t* in, uint64_t chunks, uint8_t* out, void* hip_stream) {
   int rc = check_live(c);

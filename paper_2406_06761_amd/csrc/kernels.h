@@ -62,7 +62,7 @@ struct CopyItem {
 };
 
 struct EncodeJob {
-  const int8_t* emb;    // first entry of the chunk, row-major [.][d]
+  const void* emb;      // first entry of the chunk, row-major [.][d], int8 or int16 (EncodeArgs::wide)
   uint64_t n_entries;   // entries of the cluster in this chunk (<= n)
   uint64_t* out;        // [d_pad][L][n]
 };
@@ -70,6 +70,7 @@ struct EncodeJob {
 struct EncodeArgs {
   int log_n, L;
   uint32_t d, d_pad, g;
+  uint32_t wide;            // entries are int16 (else int8)
   const uint32_t* slot_of;  // NTT index -> slot
 };
 

@@ -340,7 +340,8 @@ __global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_encode(const EncodeJ
     const uint64_t entry = s2;
     const uint32_t coord = ((s2 % dp) + m) % dp;
     int v = 0;
-    if (entry < jb.n_entries && coord < d) v = gmem(jb.emb)[entry * d + coord];
+    if (entry < jb.n_entries && coord < d)
+      v = a.wide ? gmem((const int16_t*)jb.emb)[entry * d + coord] : gmem((const int8_t*)jb.emb)[entry * d + coord];
     x[e] = v < 0 ? (uint64_t)((int64_t)t + v) : (uint64_t)v;
   }
   ntt_inv<LOGN, 4>(x, lds, M.inv[it], t, tid);

@@ -22,14 +22,18 @@ SEED_DB, SEED_SIZES, SEED_QUERIES, SEED_TARGETS, SEED_FAKES, SEED_CRYPTO, SEED_A
 ROW_BLOCK = 1 << 16
 
 
-def embeddings(n_rows: int, dim: int, seed: int = SEED_DB, norm: str = "l2", row_start: int = 0) -> np.ndarray:
-    """int8 rows ``round(127 * g / ||g||)`` with ``g ~ N(0, I_dim)``.
+def embeddings(n_rows: int, dim: int, seed: int = SEED_DB, norm: str = "l2", row_start: int = 0,
+               scale: int = 127) -> np.ndarray:
+    """Rows ``round(scale * g / ||g||)`` with ``g ~ N(0, I_dim)``: int8 for the
+    default scale 127, int16 for larger scales (up to 32767, the 15-bit
+    precision of the plaintext-CRT variant).
 
     Row r comes from block ``r // ROW_BLOCK`` whose generator is seeded with
     ``(seed, block)``, so ``embeddings(k, d, row_start=s)`` equals rows
     ``[s, s + k)`` of a larger call.  ``norm`` is ``"l2"`` or ``"inf"``.
     """
-    out = np.empty((n_rows, dim), dtype=np.int8)
+    dtype = np.int8 if scale <= 127 else np.int16
+    out = np.empty((n_rows, dim), dtype=dtype)
     r = row_start
     end = row_start + n_rows
     while r < end:
@@ -40,26 +44,27 @@ def embeddings(n_rows: int, dim: int, seed: int = SEED_DB, norm: str = "l2", row
         # how many rows of it are taken
         g = np.random.default_rng([seed, b]).standard_normal((take_hi - lo, dim))[r - lo :]
         if norm == "l2":
-            scale = np.linalg.norm(g, axis=1, keepdims=True)
+            nrm = np.linalg.norm(g, axis=1, keepdims=True)
         elif norm == "inf":
-            scale = np.abs(g).max(axis=1, keepdims=True)
+            nrm = np.abs(g).max(axis=1, keepdims=True)
         else:
             raise ValueError(norm)
-        out[r - row_start : take_hi - row_start] = np.rint(127.0 * g / scale).astype(np.int8)
+        out[r - row_start : take_hi - row_start] = np.rint(float(scale) * g / nrm).astype(dtype)
         r = take_hi
     return out
 
 
-def embeddings_parallel(n_rows: int, dim: int, seed: int = SEED_DB, norm: str = "l2", threads: int = 8) -> np.ndarray:
+def embeddings_parallel(n_rows: int, dim: int, seed: int = SEED_DB, norm: str = "l2", threads: int = 8,
+                        scale: int = 127) -> np.ndarray:
     """Same rows as :func:`embeddings`, generated block-parallel on host threads."""
     from concurrent.futures import ThreadPoolExecutor
 
-    out = np.empty((n_rows, dim), dtype=np.int8)
+    out = np.empty((n_rows, dim), dtype=np.int8 if scale <= 127 else np.int16)
     starts = list(range(0, n_rows, ROW_BLOCK))
 
     def work(s):
         k = min(ROW_BLOCK, n_rows - s)
-        out[s : s + k] = embeddings(k, dim, seed, norm, row_start=s)
+        out[s : s + k] = embeddings(k, dim, seed, norm, row_start=s, scale=scale)
 
     with ThreadPoolExecutor(threads) as ex:
         list(ex.map(work, starts))
@@ -179,6 +184,6 @@ def paper_workload(n_real: int = 50_000, entries: int = 3_200_000, k: int = 1800
     return Workload(name, entries, dim, "l2", sizes, np.concatenate([real, fake_targets]), n_real)
 
 
-def query_vectors(n: int, dim: int, norm: str, seed: int = SEED_QUERIES) -> np.ndarray:
-    """int8 query embeddings from the same generator as the database rows."""
-    return embeddings(n, dim, seed=seed, norm=norm)
+def query_vectors(n: int, dim: int, norm: str, seed: int = SEED_QUERIES, scale: int = 127) -> np.ndarray:
+    """Query embeddings from the same generator as the database rows."""
+    return embeddings(n, dim, seed=seed, norm=norm, scale=scale)

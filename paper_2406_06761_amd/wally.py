@@ -56,7 +56,7 @@ assert ctypes.sizeof(Query) == QUERY_DTYPE.itemsize
 # every symbol declared in include/wally.h and include/wally_diag.h
 SYMBOLS = [
     "wally_params_init", "wally_params_query", "wally_encode_clusters", "wally_cluster_info", "wally_score_batch",
-    "wally_tune", "wally_compress_responses",
+    "wally_tune", "wally_compress_responses", "wally_encode_clusters_i16",
     "wally_serve_start", "wally_serve_submit", "wally_serve_poll", "wally_serve_stop", "wally_strerror",
     "wally_last_error", "wally_destroy", "wally_diag_ntt", "wally_diag_rotate", "wally_diag_kernel_timing",
     "wally_diag_kernel_stats",
@@ -93,6 +93,7 @@ def load():
         "wally_params_init": ([ctypes.POINTER(ParamsDesc), ctypes.POINTER(vp)], i32),
         "wally_params_query": ([vp, ctypes.POINTER(ParamsInfo)], i32),
         "wally_encode_clusters": ([vp, vp, u64, vp, u32], i32),
+        "wally_encode_clusters_i16": ([vp, vp, u64, vp, u32], i32),
         "wally_cluster_info": ([vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(vp)], i32),
         "wally_score_batch": ([vp, vp, u64, i32, vp], i32),
         "wally_compress_responses": ([vp, vp, u64, vp, vp], i32),
@@ -145,7 +146,9 @@ class Context:
 
     @classmethod
     def preset(cls, name, **kw):
-        table = {"tiny": (12, 3, 36, 20, 64), "paper": (13, 4, 54, 22, 192), "large": (13, 4, 54, 23, 384)}
+        table = {"tiny": (12, 3, 36, 20, 64), "paper": (13, 4, 54, 22, 192), "large": (13, 4, 54, 23, 384),
+                 "tiny_t16": (12, 3, 36, 16, 64), "tiny_t17": (12, 3, 36, 17, 64),
+                 "paper_t16": (13, 4, 54, 16, 192), "paper_t17": (13, 4, 54, 17, 192)}
         return cls(*table[name], **kw)
 
     def _check(self, rc, what):
@@ -167,10 +170,15 @@ class Context:
         return [i.q[j] for j in range(i.L)] + [i.P]
 
     def encode_clusters(self, emb: np.ndarray, offsets: np.ndarray):
-        emb = np.ascontiguousarray(emb, dtype=np.int8)
+        """int8 rows (wally_encode_clusters) or int16 rows (wally_encode_clusters_i16)."""
         offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
-        self._check(self.lib.wally_encode_clusters(self.h, emb.ctypes.data, emb.shape[0], offsets.ctypes.data,
-                                                   len(offsets) - 1), "wally_encode_clusters")
+        if np.asarray(emb).dtype == np.int16:
+            emb = np.ascontiguousarray(emb, dtype=np.int16)
+            fn, name = self.lib.wally_encode_clusters_i16, "wally_encode_clusters_i16"
+        else:
+            emb = np.ascontiguousarray(emb, dtype=np.int8)
+            fn, name = self.lib.wally_encode_clusters, "wally_encode_clusters"
+        self._check(fn(self.h, emb.ctypes.data, emb.shape[0], offsets.ctypes.data, len(offsets) - 1), name)
 
     def cluster_info(self, c):
         """(chunks, device address of the cluster's plaintexts, slot base)."""

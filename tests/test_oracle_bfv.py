@@ -217,12 +217,14 @@ def _diag_plaintext_slots(emb, n_entries, chunk, m, p):
     return np.concatenate([np.roll(diag[:half], r), np.roll(diag[half:], r)]) % p.t
 
 
-def test_encode_cluster_matches_definition(micro):
+@pytest.mark.parametrize("dtype", [np.int8, np.int16])
+def test_encode_cluster_matches_definition(micro, dtype):
     o = micro
     p = o.p
     rng = np.random.default_rng(15)
     n_entries = 21  # two chunks, ragged tail
-    emb = rng.integers(-127, 128, (n_entries, p.dim)).astype(np.int8)
+    lim = np.iinfo(dtype).max
+    emb = rng.integers(-lim, lim + 1, (n_entries, p.dim)).astype(dtype)
     pt = o.encode_cluster(emb)
     assert pt.shape == (2, p.d_pad, p.L, p.n)
     half_t = (p.t - 1) // 2
@@ -254,3 +256,48 @@ def test_no_wrap_bound():
         dots = e.astype(np.int64) @ q.astype(np.int64).T
         assert np.abs(dots).max() <= bound
         assert (np.linalg.norm(e.astype(np.float64), axis=1) <= 127 + math.sqrt(p.dim) / 2).all()
+
+
+def test_crt_combine_exhaustive():
+    """Plaintext CRT (paper §7.3): every residue pair of small moduli maps to
+    the unique integer in (-T/2, T/2] with those residues."""
+    from oracle.bfv import crt_combine
+
+    t0, t1 = 5, 7
+    T = t0 * t1
+    a = np.array([x for x in range(t0) for _ in range(t1)])
+    b = np.array([y for _ in range(t0) for y in range(t1)])
+    got = crt_combine(a, b, t0, t1)
+    for x, y, z in zip(a, b, got):
+        assert -T // 2 < z <= T // 2 and z % t0 == x and z % t1 == y
+
+
+def test_crt_no_wrap_bound():
+    """With both plaintext moduli the precision bound p < sqrt((T-1)/2) - sqrt(d)/2
+    of paper §7.3 (T = t0 t1) admits 15-bit entries: rows scaled to 32767."""
+    from paper_2406_06761_amd import synth
+
+    for base in ("tiny", "paper"):
+        T = preset(base + "_t16").t * preset(base + "_t17").t
+        d = preset(base).dim
+        assert 32767 < math.sqrt((T - 1) / 2) - math.sqrt(d) / 2
+        e = synth.embeddings(500, d, scale=32767)
+        q = synth.query_vectors(20, d, "l2", scale=32767)
+        assert np.abs(e.astype(np.int64) @ q.astype(np.int64).T).max() < T // 2
+
+
+def test_crt_pair_end_to_end_oracle():
+    """Two plaintext moduli, one key pair: the recombined decryptions of the
+    scored responses are the integer dot products of 15-bit rows."""
+    from oracle.bfv import crt_combine
+    from paper_2406_06761_amd import synth
+
+    o0, o1 = Oracle(preset("tiny_t16")), Oracle(preset("tiny_t17"))
+    rows = synth.embeddings(300, 64, seed=71, scale=32767)
+    qv = synth.query_vectors(1, 64, "l2", seed=72, scale=32767)[0]
+    ct0, ct1, kb, kg, s = o0.make_crt_query(o1, qv, np.random.default_rng(73))
+    m0 = o0.decrypt(s, o0.score(ct0, kb, kg, o0.encode_cluster(rows))[0])
+    m1 = o1.decrypt(s, o1.score(ct1, kb, kg, o1.encode_cluster(rows))[0])
+    dots = rows.astype(np.int64) @ qv.astype(np.int64)
+    assert (crt_combine(m0, m1, o0.p.t, o1.p.t)[:300] == dots).all()
+    assert np.abs(dots).max() > o1.p.t // 2  # beyond either modulus alone
