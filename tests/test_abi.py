@@ -13,7 +13,7 @@ def _declared():
     names = set()
     for h in (ROOT / "include").glob("*.h"):
         text = re.sub(r"/\*.*?\*/", "", h.read_text(), flags=re.S)
-        names.update(re.findall(r"\b(wally_[a-z_]+)\s*\(", text))
+        names.update(re.findall(r"\b(wally_[a-z0-9_]+)\s*\(", text))
     return names
 
 
