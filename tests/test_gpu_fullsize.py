@@ -229,3 +229,76 @@ def test_large_copack_sampled_parity():
         assert checked >= 6
     finally:
         ctx.close()
+
+
+def test_paper_scale_plaintext_crt():
+    """Plaintext CRT (paper §7.3) at paper scale: the 3.2M x 192 index with
+    15-bit (int16) entries under t just above 2^16 and 2^17, one context after
+    the other; the whole 53,710-query batch in each; sampled real queries
+    (hot, cold, multi-chunk) recombine to the integer dot products."""
+    from oracle.bfv import crt_combine
+    from paper_2406_06761_amd.wally import PATH_BATCHED, Context, query_array, to_device, to_host
+
+    p0, p1 = preset("paper_t16"), preset("paper_t17")
+    o0, o1 = Oracle(p0), Oracle(p1)
+    n, L = p0.n, p0.L
+    w = synth.paper_workload()
+    offs = synth.offsets(w.sizes)
+    emb = synth.embeddings_parallel(w.n_entries, w.dim, norm=w.norm, threads=16, scale=32767)
+    lay = layout.per_cluster(w.sizes, n)
+    real, counts, chosen = _hot_cold_multi(w, lay)
+    picks = sorted({int(np.nonzero(real == c)[0][0]) for c in chosen})
+    rng = np.random.default_rng(synth.SEED_CRYPTO + 21)
+    packets = {}
+    for i in picks:
+        vec = synth.embeddings(1, w.dim, seed=synth.SEED_QUERIES, norm=w.norm, row_start=i, scale=32767)[0]
+        packets[i] = (vec,) + o0.make_crt_query(o1, vec, rng)  # vec, ct0, ct1, kb, kg, s
+    nq = len(w.targets)
+    q_chunks = np.array([lay.chunks[int(t)] for t in w.targets], dtype=np.int64)
+    ctw = 2 * L * n
+    out_off = np.zeros(nq, dtype=np.int64)
+    out_off[1:] = np.cumsum(q_chunks)[:-1]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(synth.SEED_CRYPTO)
+    pool = 512
+    cts = synth.uniform_residues(gen, (pool, 2), p0.q, n, device="cuda")
+    kbs = synth.uniform_residues(gen, (pool, L, 2), p0.moduli, n, device="cuda")
+    kgs = synth.uniform_residues(gen, (pool, L, 2), p0.moduli, n, device="cuda")
+    pidx = np.arange(nq) % pool
+    decs = []
+    for which, (o, name) in enumerate(((o0, "paper_t16"), (o1, "paper_t17"))):
+        outs = torch.zeros(int(q_chunks.sum()) * ctw, dtype=torch.int64, device="cuda")
+        ct_ptr = cts.data_ptr() + pidx * cts[0].numel() * 8
+        kb_ptr = kbs.data_ptr() + pidx * kbs[0].numel() * 8
+        kg_ptr = kgs.data_ptr() + pidx * kgs[0].numel() * 8
+        keep = []
+        for i in picks:
+            vec, c0, c1, kb, kg, s = packets[i]
+            d = (to_device(c0 if which == 0 else c1), to_device(kb), to_device(kg))
+            keep.append(d)
+            ct_ptr[i], kb_ptr[i], kg_ptr[i] = d[0].data_ptr(), d[1].data_ptr(), d[2].data_ptr()
+        ctx = Context.preset(name)
+        try:
+            ctx.encode_clusters(emb, offs)
+            ctx.score_batch(query_array(w.targets, ct_ptr, kb_ptr, kg_ptr, outs.data_ptr() + out_off * ctw * 8),
+                            path=PATH_BATCHED)
+            torch.cuda.synchronize()
+        finally:
+            ctx.close()
+        print(f"{name}: scored {nq} queries", flush=True)
+        got_all = to_host(outs)
+        del outs
+        torch.cuda.empty_cache()
+        per = {}
+        for i in picks:
+            vec, c0, c1, kb, kg, s = packets[i]
+            c = int(w.targets[i])
+            got = got_all[out_off[i] * ctw : (out_off[i] + q_chunks[i]) * ctw].reshape(q_chunks[i], 2, L, n)
+            per[i] = np.concatenate([o.decrypt(s, got[k]) for k in range(q_chunks[i])])
+        decs.append(per)
+    for i in picks:
+        vec = packets[i][0]
+        c = int(w.targets[i])
+        rows = emb[int(offs[c]) : int(offs[c + 1])].astype(np.int64)
+        comb = crt_combine(decs[0][i], decs[1][i], p0.t, p1.t)
+        assert (comb[: len(rows)] == rows @ vec.astype(np.int64)).all(), (i, c)
