@@ -509,12 +509,21 @@ def main():
                 roofline["traffic"] = traffic * roofline["items_per_launch"]
 
     graph = None
-    waves = -(-nq // (args.max_batch or 512))
-    if tuned:
-        waves = -(-nq // tuned["chosen"]["max_batch"])
-    if args.graph_steps > 0 and waves > 64:
-        log(f"graph path skipped: {waves} waves, the library captures at most 64 per graph")
-    elif args.graph_steps > 0:
+    graph_b = None
+    b_now = tuned["chosen"]["max_batch"] if tuned else (args.max_batch or 512)
+    run_graph = args.graph_steps > 0
+    if run_graph and -(-nq // b_now) > 64:
+        # the library captures at most 64 waves per graph: larger waves for this leg
+        graph_b = 1 << max(0, (-(-nq // 64) - 1).bit_length())
+        if graph_b > 2048:  # workspaces of such waves would not fit beside the index
+            log(f"graph path skipped: {nq} queries need waves of {graph_b}")
+            run_graph, graph_b = False, None
+        else:
+            sets_now = tuned["chosen"]["wave_sets"] if tuned else (args.wave_sets or 2)
+            tile_now = tuned["chosen"]["tile_items"] if tuned else 8
+            ctx.tune(q[: min(2048, nq)], batches=(graph_b,), sets=(sets_now,), tiles=(tile_now,))
+            log(f"graph path: waves of {graph_b} queries ({-(-nq // graph_b)} waves)")
+    if run_graph:
         t0 = time.perf_counter()
         ctx.score_batch(q, path=PATH_GRAPH)  # capture + first replay
         torch.cuda.synchronize()
@@ -572,6 +581,7 @@ def main():
         "real_scores_per_s": real_scores * args.steps / dt,
         "queries_per_s": nq * args.steps / dt,
         "graph_path_scores_per_s": graph,
+        "graph_path_max_batch": graph_b,
         "plain_path_scores_per_s": plain,
         "speedup_vs_plain": (value / plain) if plain else None,
         "encode_s": encode_s,
