@@ -71,7 +71,9 @@ typedef struct {
   uint32_t dim;        /* embedding dimension d                             */
   uint32_t layout;     /* WALLY_LAYOUT_PER_CLUSTER or WALLY_LAYOUT_COPACK     */
   int32_t device;      /* HIP device ordinal                                */
-  uint32_t max_batch;  /* queries resident per wave (0 = 512)                */
+  uint32_t max_batch;  /* queries resident per wave (0 = 512, at most 32768;
+                          max_batch x chunks of the largest cluster at most
+                          32768, else scoring returns WALLY_EINVAL)          */
   uint32_t wave_sets;  /* waves in flight on separate streams (0 = 2)       */
   uint32_t reserved;   /* must be 0                                         */
   uint64_t hbm_budget; /* bytes the context may allocate (0 = 90% of free)  */
@@ -142,8 +144,9 @@ int wally_encode_clusters_i16(wally_ctx* ctx, const int16_t* emb, uint64_t n_ent
  * (value k in stream bits [k w, (k+1) w), stream bit b = bit b%8 of byte b/8).
  * `out` (device) receives [chunks][compressed_chunk_bytes]: part 0, then part
  * 1.  A client recovers c' ~ v 2^l mod q_0 and decrypts at modulus q_0.  Work
- * is enqueued on hip_stream; the context's scratch is shared, so calls must
- * not overlap on different streams.  EINVAL for null or misaligned pointers. */
+ * is enqueued on hip_stream; the context's scratch is shared, so a call runs
+ * after the previous call's work, whatever stream that was on.  EINVAL for
+ * null or misaligned pointers. */
 int wally_compress_responses(wally_ctx* ctx, const uint64_t* in, uint64_t chunks, uint8_t* out, void* hip_stream);
 
 /* Chunks of cluster c, the slot of its first entry in its first chunk (0 in

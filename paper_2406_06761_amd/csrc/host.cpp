@@ -215,6 +215,7 @@ struct wally_ctx {
   CompressArgs comp{};
   uint64_t* comp_scratch = nullptr;
   uint64_t comp_scratch_chunks = 0;
+  hipEvent_t comp_done = nullptr;  // recorded after each compression call
   // waves
   int B = 0;
   int n_sets = 2;
@@ -226,6 +227,8 @@ struct wally_ctx {
   uint64_t graph_key = 0;
   void* graph_desc = nullptr;  // device descriptors of the captured batch
   bool capturing = false;
+  hipEvent_t graph_done = nullptr;  // recorded after each graph launch; later eager work waits for it
+  bool graph_pending = false;
   std::vector<WaveWork> sets;
   hipEvent_t fork = nullptr;
   std::string err;
@@ -393,7 +396,13 @@ hipError_t keyswitch(wally_ctx* c, const KsItem* items, int n, const KsArgs& a, 
   return e;
 }
 
+constexpr int kMaxWaveQueries = 1 << 15;
+constexpr size_t kMaxWaveItems = (size_t)1 << 15;
+
 void drop_graph(wally_ctx* c) {
+  // a replay still in flight reads the descriptors and workspaces freed here
+  if (c->graph_pending) (void)hipEventSynchronize(c->graph_done);
+  c->graph_pending = false;
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   c->graph_exec = nullptr;
   c->graph_key = 0;
@@ -431,7 +440,11 @@ void free_sets(wally_ctx* c) {
 // Workspace sets for waves of up to B queries (allocated on first use and
 // whenever the index changes the largest chunk count).
 int ensure_sets(wally_ctx* c) {
+  // wave size: the item grids of the key-switch kernels stay below 2^32 threads
+  if (c->B < 1 || c->B > kMaxWaveQueries) return set_err(c, WALLY_EINVAL, "max_batch must be in 1..%d", kMaxWaveQueries);
   const size_t giant_cap = (size_t)c->B * std::max<uint32_t>(1, c->max_chunks);
+  if (giant_cap > kMaxWaveItems)
+    return set_err(c, WALLY_EINVAL, "max_batch x chunks of the largest cluster exceeds %zu items per wave", kMaxWaveItems);
   if (!c->sets.empty() && c->sets[0].giant_cap >= giant_cap) return WALLY_OK;
   free_sets(c);
   c->sets.resize(c->n_sets);
@@ -634,6 +647,7 @@ int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
   *out = nullptr;
   if (desc->log_n != 12 && desc->log_n != 13) return WALLY_EINVAL;
   if (desc->num_limbs < 1 || desc->num_limbs > kMaxLimbs) return WALLY_EINVAL;
+  if (desc->max_batch > (uint32_t)kMaxWaveQueries) return WALLY_EINVAL;
   if (desc->limb_bits < 30 || desc->limb_bits > 54) return WALLY_EINVAL;  // 27-bit halves in the sums
   if (desc->t_bits < 2 || desc->t_bits + 2 > desc->limb_bits) return WALLY_EINVAL;
   if (desc->dim < 1) return WALLY_EINVAL;
@@ -892,6 +906,7 @@ int wally_compress_responses(wally_ctx* c, const uint64_t* in, uint64_t chunks, 
   if ((uintptr_t)in & 7) return set_err(c, WALLY_EINVAL, "responses must be 8-byte aligned");
   const uint64_t batch = std::min<uint64_t>(chunks, kCompressBatch);
   if (c->comp_scratch_chunks < batch) {
+    if (c->comp_done) HIP_OK(c, hipEventSynchronize(c->comp_done));  // the last call may still read it
     dfree(c, c->comp_scratch);
     c->comp_scratch = nullptr;
     c->comp_scratch_chunks = 0;
@@ -899,12 +914,16 @@ int wally_compress_responses(wally_ctx* c, const uint64_t* in, uint64_t chunks, 
     c->comp_scratch_chunks = batch;
   }
   hipStream_t st = (hipStream_t)hip_stream;
+  // the scratch is shared: a call on another stream runs after the last one
+  if (c->comp_done) HIP_OK(c, hipStreamWaitEvent(st, c->comp_done, 0));
+  else HIP_OK(c, hipEventCreateWithFlags(&c->comp_done, hipEventDisableTiming));
   const uint64_t cbytes = c->comp.part_bytes[0] + c->comp.part_bytes[1];
   for (uint64_t b0 = 0; b0 < chunks; b0 += batch) {
     const int nb = (int)std::min(batch, chunks - b0);
     HIP_OK(c, launch_resp_intt(in + b0 * c->ctw(), c->comp_scratch, nb, c->log_n, c->L, c->M, st));
     HIP_OK(c, launch_resp_pack(c->comp_scratch, out + b0 * cbytes, nb, c->comp, c->M, st));
   }
+  HIP_OK(c, hipEventRecord(c->comp_done, st));
   return WALLY_OK;
 }
 
@@ -1048,15 +1067,23 @@ int score_locked(wally_ctx* c, const wally_query* q, uint64_t nq, int path, hipS
     // earlier eager work on the set streams shares the workspaces
     for (auto& s : c->sets) HIP_OK(c, hipStreamWaitEvent(user, s.done, 0));
     HIP_OK(c, hipGraphLaunch(c->graph_exec, user));
-    // later eager work forks from the user stream, so it runs after the graph
+    // later eager work may come on another stream: it waits for this event
+    if (!c->graph_done) HIP_OK(c, hipEventCreateWithFlags(&c->graph_done, hipEventDisableTiming));
+    HIP_OK(c, hipEventRecord(c->graph_done, user));
+    c->graph_pending = true;
     return WALLY_OK;
   }
   std::vector<const wally_query*> ord;
   std::vector<std::pair<uint64_t, uint64_t>> waves;
   make_waves(c, q, nq, path, ord, waves);
-  // fork: every set stream waits for the caller's stream
+  // fork: every set stream waits for the caller's stream (and a graph replay
+  // still using the workspaces, whatever stream it was launched on)
   HIP_OK(c, hipEventRecord(c->fork, user));
-  for (auto& s : c->sets) HIP_OK(c, hipStreamWaitEvent(s.stream, c->fork, 0));
+  for (auto& s : c->sets) {
+    HIP_OK(c, hipStreamWaitEvent(s.stream, c->fork, 0));
+    if (c->graph_pending) HIP_OK(c, hipStreamWaitEvent(s.stream, c->graph_done, 0));
+  }
+  c->graph_pending = false;
   for (size_t wv = 0; wv < waves.size(); ++wv) {
     WaveWork& s = c->sets[wv % c->sets.size()];
     if ((rc = enqueue_wave(c, s, ord.data() + waves[wv].first, (int)(waves[wv].second - waves[wv].first)))) return rc;
@@ -1189,7 +1216,11 @@ int wally_serve_start(wally_ctx* c, void* hip_stream) {
   if ((rc = ensure_sets(c))) return rc;
   c->serve_stream = (hipStream_t)hip_stream;
   HIP_OK(c, hipEventRecord(c->fork, c->serve_stream));
-  for (auto& s : c->sets) HIP_OK(c, hipStreamWaitEvent(s.stream, c->fork, 0));
+  for (auto& s : c->sets) {
+    HIP_OK(c, hipStreamWaitEvent(s.stream, c->fork, 0));
+    if (c->graph_pending) HIP_OK(c, hipStreamWaitEvent(s.stream, c->graph_done, 0));
+  }
+  c->graph_pending = false;
   c->pending.clear();
   c->finished.clear();
   // admission: in flight = one wave per set; waiting = the same again
@@ -1255,6 +1286,8 @@ void wally_destroy(wally_ctx* c) {
   free_sets(c);
   while (!c->allocs.empty()) dfree(c, c->allocs.back().first);
   if (c->fork) (void)hipEventDestroy(c->fork);
+  if (c->graph_done) (void)hipEventDestroy(c->graph_done);
+  if (c->comp_done) (void)hipEventDestroy(c->comp_done);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto& t : c->timers) c->ev_pool.push_back(t.a), c->ev_pool.push_back(t.b);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);

@@ -55,6 +55,8 @@ def test_error_strings_and_null_handling():
     assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL
     d = wally.ParamsDesc(12, 3, 36, 20, 4096, 0, 0, 0, 0, 0, 0)  # d_pad does not divide n/2
     assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL
+    d = wally.ParamsDesc(12, 3, 36, 20, 64, 0, 0, 32769, 0, 0, 0)  # wave beyond the grid limits
+    assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL
 
 
 def test_library_is_newer_than_its_sources():

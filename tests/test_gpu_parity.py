@@ -250,6 +250,37 @@ def test_graph_replays_match_eager(tiny_workload):
         c.close()
 
 
+def test_graph_then_eager_on_another_stream(tiny_workload):
+    """A replay on one stream followed at once, without a synchronisation, by
+    an eager batch on another stream: the eager waves share the replay's
+    workspaces, so they must wait for it; both outputs are exact."""
+    from paper_2406_06761_amd.wally import PATH_BATCHED, PATH_GRAPH, to_host
+
+    o, w, emb, offs, qv, packets, ref = tiny_workload
+    c = _ctx("tiny", max_batch=5, wave_sets=2)
+    try:
+        c.encode_clusters(emb, offs)
+        q, outs, keep = _tiny_queries(o, w, packets)
+        q2, outs2, keep2 = _tiny_queries(o, w, packets)
+        c.score_batch(q, path=PATH_GRAPH)  # capture (runs once)
+        torch.cuda.synchronize()
+        outs.zero_()
+        torch.cuda.synchronize()
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        for rep in range(2):
+            c.score_batch(q, path=PATH_GRAPH, stream=s1)
+            c.score_batch(q2, path=PATH_BATCHED, stream=s2)
+            torch.cuda.synchronize()
+            a, b = to_host(outs), to_host(outs2)
+            for i in range(len(w.targets)):
+                assert (a[i] == ref[i]).all() and (b[i] == ref[i]).all(), (rep, i)
+            outs.zero_()
+            outs2.zero_()
+            torch.cuda.synchronize()
+    finally:
+        c.close()
+
+
 def test_graph_refuses_batches_over_the_wave_limit(tiny_workload):
     """More than 64 waves in one graph is refused before anything is captured."""
     from paper_2406_06761_amd.wally import EINVAL, PATH_GRAPH, WallyError, query_array
