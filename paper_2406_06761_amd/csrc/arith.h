@@ -32,14 +32,30 @@ __device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t wp, u
 // a * w mod q in [0, 4q) for any a < 2^64, w < q, wp = floor(w 2^64 / q).
 // Shoup's quotient floor(a wp / 2^64) without the low x low partial product
 // and without the carry between the two middle ones:
-//   a wp = a1 w1 2^64 + (a0 w1 + a1 w0) 2^32 + a0 w0, and the dropped parts add
+//   a wp = a1 p1 2^64 + (a0 p1 + a1 p0) 2^32 + a0 p0 (p1, p0 the words of wp),
+//   and the dropped parts add
 //   less than 3 to the quotient, so qh is exact or up to 2 below it.
-__device__ __forceinline__ uint64_t shoup4(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+//
+// The remainder a w - qh q is formed mod 2^64 as a w + qh (2^64 - q): with
+// nq = 2^64 - q the two low x low products chain through one 64-bit addend
+// and the four cross products only touch the high word, so no 64-bit
+// subtraction is needed (8 instead of 10 VALU operations).
+__device__ __forceinline__ uint64_t shoup4(uint64_t a, uint64_t w, uint64_t wp, uint64_t nq) {
   const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
-  const uint32_t w0 = (uint32_t)wp, w1 = (uint32_t)(wp >> 32);
-  const uint64_t mid = (uint64_t)__umulhi(a0, w1) + __umulhi(a1, w0);
-  const uint64_t qh = (uint64_t)a1 * w1 + mid;
-  return a * w - qh * q;
+  const uint32_t p0 = (uint32_t)wp, p1 = (uint32_t)(wp >> 32);
+  uint64_t mid = (uint64_t)__umulhi(a0, p1) + __umulhi(a1, p0);
+  // Empty asm operands keep the compiler from re-associating these sums into
+  // forms that need zero-extended register pairs (one extra move each).
+  asm("" : "+v"(mid));
+  const uint64_t qh = (uint64_t)a1 * p1 + mid;
+  const uint32_t h0 = (uint32_t)qh, h1 = (uint32_t)(qh >> 32);
+  const uint32_t w0 = (uint32_t)w, w1 = (uint32_t)(w >> 32);
+  const uint32_t n0 = (uint32_t)nq, n1 = (uint32_t)(nq >> 32);
+  const uint64_t lo = (uint64_t)a0 * w0 + (uint64_t)h0 * n0;  // wraps mod 2^64
+  uint32_t lo_hi = (uint32_t)(lo >> 32);
+  asm("" : "+v"(lo_hi));
+  const uint32_t hi = lo_hi + a0 * w1 + a1 * w0 + h0 * n1 + h1 * n0;
+  return ((uint64_t)hi << 32) | (uint32_t)lo;
 }
 
 // x in [0, 2q) -> [0, q)

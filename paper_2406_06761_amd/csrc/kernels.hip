@@ -66,6 +66,33 @@ __device__ __forceinline__ WALLY_GLOBAL uint64_t* sel_out(const KsItem* it, int 
   return gmem(r) + off;
 }
 
+// Rows in LastMap order.  The last pass has LOWB = 0, so registers 2c and
+// 2c + 1 of a thread hold adjacent words and lanes hold consecutive pairs:
+// a row moves with one coalesced 16-byte access per pair, and a transform
+// whose output (forward) or input (inverse) is in this order needs no
+// exchange to or from the natural order.  Rows live in global memory (the
+// pointer may be generic or global-typed).
+template <int LOGN, int LOGE, class PTR>
+__device__ __forceinline__ void load_last(uint64_t (&x)[1 << LOGE], PTR src, int tid) {
+  using LM = LastMap<LOGN, LOGE>;
+  static_assert(LM::LOWB == 0 && LM::RW >= 1, "pairs of the last pass are adjacent words");
+#pragma unroll
+  for (int c = 0; c < (1 << LOGE) / 2; ++c) {
+    const u64x2 v = *(WALLY_GLOBAL const u64x2*)(src + LM::idx(tid, 2 * c));
+    x[2 * c] = v.x;
+    x[2 * c + 1] = v.y;
+  }
+}
+
+template <int LOGN, int LOGE, class PTR>
+__device__ __forceinline__ void store_last(PTR dst, const uint64_t (&x)[1 << LOGE], int tid) {
+  using LM = LastMap<LOGN, LOGE>;
+  static_assert(LM::LOWB == 0 && LM::RW >= 1, "pairs of the last pass are adjacent words");
+#pragma unroll
+  for (int c = 0; c < (1 << LOGE) / 2; ++c)
+    *(WALLY_GLOBAL u64x2*)(dst + LM::idx(tid, 2 * c)) = u64x2{x[2 * c], x[2 * c + 1]};
+}
+
 // XCD-aware placement. The work-groups of a launch go to the eight XCDs round
 // robin (block id mod 8) and each XCD has its own L2. Where a launch has groups
 // of `per` blocks that read the same input row, a group's members get ids that
@@ -130,15 +157,18 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const K
   const uint64_t* X = a.X + ((uint64_t)b * L + i) * S::N;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) d[e] = X[FM::idx(tid, e)];  // < q_i < 2 q_m: a valid lazy input
-  ntt_fwd_nat<LOGN, LOGE>(d, lds, M.fwd[m], q, tid);  // out < 54 q
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) D[FM::idx(tid, e)] = reduce_lazy(d[e], q, M.mc[m].onep);
+  ntt_fwd<LOGN, LOGE>(d, lds, M.fwd[m], q, tid);  // out < 54 q, LastMap order
+  // stored unreduced: the inner product's 128-bit sums take words below 54 q
+  // (up to eight products of them with key words stay below 2^117) and
+  // reduce once
+  store_last<LOGN, LOGE>(D, d, tid);
 }
 
 // ---------------------------------------------------------------------------
 // key switching, step 3: key inner product u_t[m] = sum_i D[m][i] * key[i][t][m]
 // with one 128-bit lazy sum per output word (elementwise, memory bound; two
-// words per thread through 16-byte loads).
+// words per thread through 16-byte loads).  D words are below 54 q (the
+// forward transform's lazy bound), key words below q.
 // grid (n / 512, L+1, items); block 256
 __global__ __launch_bounds__(256) void k_ks_inner(const KsItem* __restrict__ items, KsArgs a, DevModuli M) {
   const int m = blockIdx.y, b = blockIdx.z;
@@ -179,9 +209,8 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_pinv(KsArgs a,
   const uint64_t P = M.q[L];
   const uint64_t* U = a.U + (((uint64_t)b * 2 + t) * MM + L) * S::N;
   uint64_t y[S::E];
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) y[e] = U[FM::idx(tid, e)];
-  ntt_inv_nat<LOGN, LOGE>(y, lds, M.inv[L], P, tid);
+  load_last<LOGN, LOGE>(y, U, tid);
+  ntt_inv<LOGN, LOGE>(y, lds, M.inv[L], P, tid);  // out FirstMap order
   uint64_t* Y = a.Y + ((uint64_t)b * 2 + t) * S::N;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) Y[FM::idx(tid, e)] = csub(shoup(y[e], M.ninv[L], M.ninvp[L], P), P);
@@ -214,23 +243,30 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_wa
     const uint64_t y = Y[FM::idx(tid, e)];
     z[e] = y > halfP ? y + (q - P) : y;  // centred lift, then mod q_j (P < q_j)
   }
-  ntt_fwd_nat<LOGN, LOGE>(z, lds, M.fwd[j], q, tid);
+  ntt_fwd<LOGN, LOGE>(z, lds, M.fwd[j], q, tid);  // LastMap order from here on, z < (2 + 4 LOGN) q
+  using LM = LastMap<LOGN, LOGE>;
+  // u - z is taken as u + zb - z with zb the transform's output bound: below
+  // 2^60, which the Shoup product by P^-1 accepts unreduced
+  const uint64_t zb = (2 + 4 * LOGN) * q;
   const uint64_t* U = a.U + (((uint64_t)b * 2 + t) * MM + j) * S::N;
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) {
-    const uint64_t v = submod(U[FM::idx(tid, e)], reduce_lazy(z[e], q, M.mc[j].onep), q);
-    z[e] = csub(shoup(v, M.pinv[j], M.pinvp[j], q), q);
+  for (int c = 0; c < S::E / 2; ++c) {
+    const u64x2 u = *(WALLY_GLOBAL const u64x2*)(U + LM::idx(tid, 2 * c));
+    z[2 * c] = csub(shoup(u.x + zb - z[2 * c], M.pinv[j], M.pinvp[j], q), q);
+    z[2 * c + 1] = csub(shoup(u.y + zb - z[2 * c + 1], M.pinv[j], M.pinvp[j], q), q);
   }
-  if (t == 0) add_galois<LOGN, LOGE, FM>(z, sel_in(items + b, a.in_sel, a.in_off) + (uint64_t)j * S::N, lds, a.gal, q, tid);
+  if (t == 0) add_galois<LOGN, LOGE, LM>(z, sel_in(items + b, a.in_sel, a.in_off) + (uint64_t)j * S::N, lds, a.gal, q, tid);
   const uint64_t toff = ((uint64_t)t * L + j) * S::N;
   if (a.giant >= 0) {  // Horner step: + acc_i
     WALLY_GLOBAL const uint64_t* acc = gmem(items[b].acc) + (uint64_t)a.giant * 2 * L * S::N + toff;
 #pragma unroll
-    for (int e = 0; e < S::E; ++e) z[e] = addmod(z[e], acc[FM::idx(tid, e)], q);
+    for (int c = 0; c < S::E / 2; ++c) {
+      const u64x2 v = *(WALLY_GLOBAL const u64x2*)(acc + LM::idx(tid, 2 * c));
+      z[2 * c] = addmod(z[2 * c], v.x, q);
+      z[2 * c + 1] = addmod(z[2 * c + 1], v.y, q);
+    }
   }
-  WALLY_GLOBAL uint64_t* out = sel_out(items + b, a.out_sel, a.out_off) + toff;
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) out[FM::idx(tid, e)] = z[e];
+  store_last<LOGN, LOGE>(sel_out(items + b, a.out_sel, a.out_off) + toff, z, tid);
 }
 
 // ---------------------------------------------------------------------------

@@ -64,7 +64,7 @@ using LastMap = PassMap<LOGN, LOGE, NttShape<LOGN, LOGE>::LAST_S0>;
 // Cooley-Tukey butterfly without reduction: inputs below B, outputs below B + 4q
 // (q4 = 4q).
 __device__ __forceinline__ void ct_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, uint64_t q, uint64_t q4) {
-  const uint64_t t = shoup4(Y, W.x, W.y, q);
+  const uint64_t t = shoup4(Y, W.x, W.y, 0 - q);
   Y = X + q4 - t;
   X = X + t;
 }
@@ -74,7 +74,7 @@ __device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, 
   const uint64_t u = X + Y;
   const uint64_t v = X - Y + q4;
   X = u >= q4 ? u - q4 : u;
-  Y = shoup4(v, W.x, W.y, q);
+  Y = shoup4(v, W.x, W.y, 0 - q);
 }
 
 // Group index of combination c of thread tid in pass S0.  When the pass's low
