@@ -501,7 +501,8 @@ def main():
                 w_ = per_item_work(k, n, L, info.g, info.h)
                 e.update(bound="alu", achieved_gmodmul=w_ * it / (ms * 1e-3) / 1e9, frac=w_ * it / (ms * 1e-3) / peak)
             isolated[k] = e
-            log(f"  isolated {k:11s} {e['ms_per_launch']:.3f} ms per {cnt} items, frac {e['frac']:.3f}")
+            log(f"  isolated {k:11s} {e['ms_per_launch']:.3f} ms per launch of {e['items_per_launch']:.0f} items, "
+                f"frac {e['frac']:.3f}")
         if roofline is not None:
             roofline["isolated"] = isolated
             traffic = stored_traffic(roofline["kernel"], preset_name)

@@ -289,48 +289,62 @@ __device__ __forceinline__ uint64_t fold27(uint64_t s0, uint64_t s1, uint64_t s2
   return csub(v - mulhi64(v, mc.onep) * q, q);            // v mod q
 }
 
-// grid (n / 64, L, tiles); block 256 = 64 coefficients x 2 ciphertext parts x
-// 2 item lanes.  A thread keeps one part of one item's g rotated copies in
-// registers (2g 27-bit halves) and streams the tile's plaintexts; splitting the
-// parts over threads halves the registers per thread, so more waves hide the
-// load latency.
-template <int G>
+// grid (n / 64, L, tiles); block 256 = 64 coefficients x 4 thread rows.  TP
+// ciphertext parts per thread: with TP = 2 a thread keeps both parts of one
+// item's g rotated copies in registers (4g 27-bit halves) and each plaintext
+// word it loads feeds two products, so the loads (served by L1/L2: every item
+// of the tile streams the same plaintext) are halved; the 4 rows take 4 items
+// at a time.  With TP = 1 (g = 32, where both parts would not fit in
+// registers) the rows are 2 parts x 2 items.
+template <int G, int TP>
 __global__ __launch_bounds__(256) void k_mac_tiles(const KsItem* __restrict__ items, const MacTile* __restrict__ tiles,
                                                    KsArgs a, int h, DevModuli M) {
+  static_assert(TP == 1 || TP == 2, "one or both ciphertext parts per thread");
+  constexpr int LANES = TP == 2 ? 4 : 2;  // items in flight per block
   const MacTile tl = tiles[blockIdx.z];
   const int j = blockIdx.y;
   const int L = a.L;
   const uint64_t n = 1ull << a.log_n;
   const uint64_t x = (uint64_t)blockIdx.x * 64 + (threadIdx.x & 63);
-  const int t = (threadIdx.x >> 6) & 1, lane = threadIdx.x >> 7;
+  const int row = threadIdx.x >> 6;
+  const int t0 = TP == 2 ? 0 : (row & 1);
+  const int lane = TP == 2 ? row : (row >> 1);
   const ModConst mc = M.mc[j];
   const uint64_t c27 = M.c27[j], c27p = M.c27p[j];
   const uint64_t ctw = 2ull * L * n;
   WALLY_GLOBAL const uint64_t* pt = gmem(items[tl.first].pt) + (uint64_t)j * n + x;  // PT[m][j][x] at m * L * n
-  const uint64_t off = ((uint64_t)t * L + j) * n + x;                                  // part t, limb j
   const uint64_t M27 = (1ull << 27) - 1;
-  for (uint32_t k = lane; k < tl.count; k += 2) {
+  for (uint32_t k = lane; k < tl.count; k += LANES) {
     const KsItem& it = items[tl.first + k];
-    WALLY_GLOBAL const uint64_t* ctp = gmem(it.ctp) + off;
-    uint32_t cl[G], ch[G];
+    uint32_t cl[TP][G], ch[TP][G];
 #pragma unroll
-    for (int jj = 0; jj < G; ++jj) {
-      const uint64_t v = ctp[jj * ctw];
-      cl[jj] = (uint32_t)(v & M27);
-      ch[jj] = (uint32_t)(v >> 27);
+    for (int p = 0; p < TP; ++p) {
+      WALLY_GLOBAL const uint64_t* ctp = gmem(it.ctp) + ((uint64_t)(t0 + p) * L + j) * n + x;
+#pragma unroll
+      for (int jj = 0; jj < G; ++jj) {
+        const uint64_t v = ctp[jj * ctw];
+        cl[p][jj] = (uint32_t)(v & M27);
+        ch[p][jj] = (uint32_t)(v >> 27);
+      }
     }
-    WALLY_GLOBAL uint64_t* acc = gmem(it.acc) + off;
+    WALLY_GLOBAL uint64_t* acc = gmem(it.acc) + ((uint64_t)t0 * L + j) * n + x;
     for (int i = 0; i < h; ++i) {
-      uint64_t s0 = 0, s1 = 0, s2 = 0;
+      uint64_t s0[TP], s1[TP], s2[TP];
+#pragma unroll
+      for (int p = 0; p < TP; ++p) s0[p] = s1[p] = s2[p] = 0;
 #pragma unroll
       for (int jj = 0; jj < G; ++jj) {
         const uint64_t w = pt[(uint64_t)(G * i + jj) * L * n];
         const uint32_t wl = (uint32_t)(w & M27), wh = (uint32_t)(w >> 27);
-        s0 += (uint64_t)wl * cl[jj];
-        s1 += (uint64_t)wl * ch[jj] + (uint64_t)wh * cl[jj];
-        s2 += (uint64_t)wh * ch[jj];
+#pragma unroll
+        for (int p = 0; p < TP; ++p) {
+          s0[p] += (uint64_t)wl * cl[p][jj];
+          s1[p] += (uint64_t)wl * ch[p][jj] + (uint64_t)wh * cl[p][jj];
+          s2[p] += (uint64_t)wh * ch[p][jj];
+        }
       }
-      acc[(uint64_t)i * ctw] = fold27(s0, s1, s2, mc, c27, c27p);
+#pragma unroll
+      for (int p = 0; p < TP; ++p) acc[(uint64_t)i * ctw + (uint64_t)p * L * n] = fold27(s0[p], s1[p], s2[p], mc, c27, c27p);
     }
   }
 }
@@ -587,10 +601,10 @@ hipError_t launch_mac_tiles(const KsItem* items, const MacTile* tiles, int n_til
   if (n_tiles <= 0) return hipSuccess;
   const dim3 grid((1u << a.log_n) / 64, a.L, n_tiles);
   switch (a.g) {
-    case 4: hipLaunchKernelGGL(k_mac_tiles<4>, grid, dim3(256), 0, st, items, tiles, a, h, M); break;
-    case 8: hipLaunchKernelGGL(k_mac_tiles<8>, grid, dim3(256), 0, st, items, tiles, a, h, M); break;
-    case 16: hipLaunchKernelGGL(k_mac_tiles<16>, grid, dim3(256), 0, st, items, tiles, a, h, M); break;
-    case 32: hipLaunchKernelGGL(k_mac_tiles<32>, grid, dim3(256), 0, st, items, tiles, a, h, M); break;
+    case 4: hipLaunchKernelGGL((k_mac_tiles<4, 2>), grid, dim3(256), 0, st, items, tiles, a, h, M); break;
+    case 8: hipLaunchKernelGGL((k_mac_tiles<8, 2>), grid, dim3(256), 0, st, items, tiles, a, h, M); break;
+    case 16: hipLaunchKernelGGL((k_mac_tiles<16, 2>), grid, dim3(256), 0, st, items, tiles, a, h, M); break;
+    case 32: hipLaunchKernelGGL((k_mac_tiles<32, 1>), grid, dim3(256), 0, st, items, tiles, a, h, M); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
