@@ -58,8 +58,20 @@ __device__ __forceinline__ uint64_t shoup4(uint64_t a, uint64_t w, uint64_t wp, 
   return ((uint64_t)hi << 32) | (uint32_t)lo;
 }
 
-// x in [0, 2q) -> [0, q)
-__device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t q) { return x >= q ? x - q : x; }
+// x - m when x >= m, else x, for x < 2^63 + m.  The sign of x - m picks the
+// result through a bit select: no compare, so no VCC write and none of the
+// wait states a VCC read right after it needs (empty asm operands keep the
+// compiler from turning it back into compare and select).
+__device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t m) {
+  uint64_t nm = 0 - m;
+  asm("" : "+s"(nm));
+  const uint64_t w = x + nm;
+  uint32_t keep = (uint32_t)((int32_t)(uint32_t)(w >> 32) >> 31);  // all ones when x < m
+  asm("" : "+v"(keep));
+  const uint32_t lo = (keep & (uint32_t)x) | (~keep & (uint32_t)w);
+  const uint32_t hi = (keep & (uint32_t)(x >> 32)) | (~keep & (uint32_t)(w >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
 
 // x in [0, 4q) -> [0, q)
 __device__ __forceinline__ uint64_t reduce4(uint64_t x, uint64_t q, uint64_t q2) {

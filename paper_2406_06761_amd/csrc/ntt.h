@@ -48,13 +48,39 @@ struct PassMap {
   static constexpr int COMBOS = (1 << LOGE) >> RW;
   static constexpr int T = NttShape<LOGN, LOGE>::T;
   // index of register e of thread tid
-  __device__ static __forceinline__ uint32_t idx(int tid, int e) {
-    const uint32_t c = e >> RW, w = e & ((1 << RW) - 1);
-    const uint32_t combo = tid + T * c;
+  __host__ __device__ static constexpr uint32_t idx_c(int tid, int e) {
+    const uint32_t c = (uint32_t)e >> RW, w = (uint32_t)e & ((1u << RW) - 1);
+    const uint32_t combo = (uint32_t)tid + T * c;
     const uint32_t high = combo >> LOWB, low = combo & ((1u << LOWB) - 1);
     return (high << (LOGN - S0)) | (w << LOWB) | low;
   }
+  __device__ static __forceinline__ uint32_t idx(int tid, int e) { return idx_c(tid, e); }
 };
+
+// The index of a map is a thread part OR an element part on disjoint bits
+// (combo = tid + T c puts tid below c), and the padded LDS offset idx +
+// idx / 32 of such a sum splits the same way (no carry crosses bit 5).  So an
+// exchange needs one per-thread base and compile-time element offsets, which
+// become the immediate offsets of the LDS instructions.
+template <int LOGN, int LOGE, class MAP>
+__device__ __forceinline__ int lds_base(int tid) {
+  return NttShape<LOGN, LOGE>::lds(MAP::idx(tid, 0));
+}
+template <int LOGN, int LOGE, class MAP>
+__host__ __device__ constexpr int lds_off(int e) {
+  return (int)(MAP::idx_c(0, e) + (MAP::idx_c(0, e) >> 5));
+}
+template <int LOGN, int LOGE, class MAP>
+constexpr bool lds_split_holds() {
+  constexpr int T = NttShape<LOGN, LOGE>::T, E = 1 << LOGE;
+  for (int tid = 0; tid < T; ++tid)
+    for (int e = 0; e < E; ++e) {
+      const uint32_t i = MAP::idx_c(tid, e), i0 = MAP::idx_c(tid, 0), ie = MAP::idx_c(0, e);
+      if ((i0 & ie) != 0 || (i0 | ie) != i) return false;
+      if (i + (i >> 5) != i0 + (i0 >> 5) + ie + (ie >> 5)) return false;
+    }
+  return true;
+}
 
 template <int LOGN, int LOGE>
 using FirstMap = PassMap<LOGN, LOGE, 0>;
@@ -73,7 +99,7 @@ __device__ __forceinline__ void ct_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, 
 __device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, ulonglong2 W, uint64_t q, uint64_t q4) {
   const uint64_t u = X + Y;
   const uint64_t v = X - Y + q4;
-  X = u >= q4 ? u - q4 : u;
+  X = csub(u, q4);
   Y = shoup4(v, W.x, W.y, 0 - q);
 }
 
@@ -136,11 +162,16 @@ __device__ __forceinline__ void gs_pass(uint64_t (&x)[1 << LOGE], const ulonglon
 template <int LOGN, int LOGE, int SA, int SB>
 __device__ __forceinline__ void exchange(uint64_t (&x)[1 << LOGE], uint64_t* lds, int tid) {
   using S = NttShape<LOGN, LOGE>;
+  using MA = PassMap<LOGN, LOGE, SA>;
+  using MB = PassMap<LOGN, LOGE, SB>;
+  static_assert(lds_split_holds<LOGN, LOGE, MA>() && lds_split_holds<LOGN, LOGE, MB>(), "padded offsets split");
+  uint64_t* wa = lds + lds_base<LOGN, LOGE, MA>(tid);
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) lds[S::lds(PassMap<LOGN, LOGE, SA>::idx(tid, e))] = x[e];
+  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, MA>(e)] = x[e];
   __syncthreads();
+  const uint64_t* rb = lds + lds_base<LOGN, LOGE, MB>(tid);
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) x[e] = lds[S::lds(PassMap<LOGN, LOGE, SB>::idx(tid, e))];
+  for (int e = 0; e < S::E; ++e) x[e] = rb[lds_off<LOGN, LOGE, MB>(e)];
   __syncthreads();
 }
 
@@ -218,11 +249,9 @@ __device__ __forceinline__ void gather_galois(uint64_t (&x)[1 << LOGE], SRC src,
                                               int tid) {
   using S = NttShape<LOGN, LOGE>;
   using FM = FirstMap<LOGN, LOGE>;
+  uint64_t* wa = lds + lds_base<LOGN, LOGE, FM>(tid);
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) {
-    const uint32_t i = FM::idx(tid, e);
-    lds[S::lds(i)] = src[i];
-  }
+  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = src[FM::idx(tid, e)];
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < S::E; ++e) x[e] = lds[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))];
@@ -237,11 +266,9 @@ __device__ __forceinline__ void add_galois(uint64_t (&x)[1 << LOGE], SRC src, ui
                                            uint64_t q, int tid) {
   using S = NttShape<LOGN, LOGE>;
   using FM = FirstMap<LOGN, LOGE>;
+  uint64_t* wa = lds + lds_base<LOGN, LOGE, FM>(tid);
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) {
-    const uint32_t i = FM::idx(tid, e);
-    lds[S::lds(i)] = src[i];
-  }
+  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = src[FM::idx(tid, e)];
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < S::E; ++e) x[e] = addmod(x[e], lds[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))], q);
