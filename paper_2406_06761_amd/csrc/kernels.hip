@@ -7,8 +7,8 @@
 //
 // Key switching for CtRotate (paper §2.1) follows the hybrid RNS method of
 // paper §7.1 with one digit per ciphertext limb and one special prime P:
-//   ks_digits : x_i = INTT_{q_i}(sigma(c1)_i)                      (L per item)
-//   ks_extend : D[m][i] = NTT_m(x_i mod m), m in {q_0..q_{L-1}, P}   (L(L+1) per item)
+//   ks_digits : x_i = INTT_{q_i}(sigma(c1)_i), D[i][i] = sigma(c1)_i  (L per item)
+//   ks_extend : D[m][i] = NTT_m(x_i mod m), m in {q_0..q_{L-1}, P} \ {q_i}   (L^2 per item)
 //   ks_inner  : u_t[m] = sum_i D[m][i] * key[i][t][m]               (elementwise)
 //   ks_pinv   : y_t = INTT_P(u_t[P])                                (2 per item)
 //   ks_moddown: out_t[j] = (u_t[j] - NTT_j([y_t]_centred mod q_j)) * P^-1
@@ -109,7 +109,9 @@ __device__ __forceinline__ GroupSlot xcd_group(uint32_t id, uint32_t per) {
 inline uint32_t xcd_blocks(uint32_t groups, uint32_t per) { return (groups + kXcds - 1) / kXcds * kXcds * per; }
 
 // ---------------------------------------------------------------------------
-// key switching, step 1: digits
+// key switching, step 1: digits.  The gathered sigma(c1)_i is also the
+// extended digit D[i][i] (its own modulus needs no transform) and is stored
+// as such here, so the extension kernel only transforms.
 // grid (items, L); block T
 template <int LOGN, int LOGE>
 __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_digits(const KsItem* __restrict__ items, KsArgs a,
@@ -123,6 +125,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_digits(const K
   const uint64_t q = M.q[i];
   uint64_t x[S::E];
   gather_galois<LOGN, LOGE, LastMap<LOGN, LOGE>>(x, c1, lds, a.gal, tid);  // sigma(c1)_i, INTT input order
+  store_last<LOGN, LOGE>(a.D + (((uint64_t)b * (a.L + 1) + i) * a.L + i) * S::N, x, tid);  // D[i][i]
   ntt_inv<LOGN, LOGE>(x, lds, M.inv[i], q, tid);
   uint64_t* X = a.X + ((uint64_t)b * a.L + i) * S::N;
 #pragma unroll
@@ -130,10 +133,10 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_digits(const K
 }
 
 // ---------------------------------------------------------------------------
-// key switching, step 2: extended digits D[m][i] = NTT_m(x_i mod m); for
-// i = m the extended digit is sigma(c1)_m itself (a permuted copy).
-// 1-D grid of xcd_blocks(items * L, L + 1): group (b, i) reads digit x_i of
-// item b, its L + 1 members are the target moduli m; block T
+// key switching, step 2: extended digits D[m][i] = NTT_m(x_i mod m) for the
+// L moduli m != i of Q P (D[i][i] is written by the digit kernel).
+// 1-D grid of xcd_blocks(items * L, L): group (b, i) reads digit x_i of item
+// b, its L members are the target moduli m; block T
 template <int LOGN, int LOGE>
 __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const KsItem* __restrict__ items, KsArgs a,
                                                                          int n_items, DevModuli M) {
@@ -142,17 +145,12 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const K
   __shared__ uint64_t lds[S::LDS_WORDS];
   const int tid = threadIdx.x;
   const int L = a.L;
-  const GroupSlot gs = xcd_group(blockIdx.x, L + 1);
+  const GroupSlot gs = xcd_group(blockIdx.x, L);
   if (gs.group >= (uint32_t)(n_items * L)) return;  // padding block (whole block, before any barrier)
-  const int b = gs.group / L, i = gs.group % L, m = gs.member;
+  const int b = gs.group / L, i = gs.group % L;
+  const int m = (int)gs.member < i ? (int)gs.member : (int)gs.member + 1;  // the moduli of Q P other than q_i
   uint64_t* D = a.D + (((uint64_t)b * (L + 1) + m) * L + i) * S::N;
   uint64_t d[S::E];
-  if (i == m) {
-    gather_galois<LOGN, LOGE, FM>(d, sel_in(items + b, a.in_sel, a.in_off) + ((uint64_t)L + m) * S::N, lds, a.gal, tid);
-#pragma unroll
-    for (int e = 0; e < S::E; ++e) D[FM::idx(tid, e)] = d[e];
-    return;
-  }
   const uint64_t q = M.q[m];
   const uint64_t* X = a.X + ((uint64_t)b * L + i) * S::N;
 #pragma unroll
@@ -574,7 +572,7 @@ hipError_t launch_ks_digits(const KsItem* items, int n_items, const KsArgs& a, c
 
 hipError_t launch_ks_extend(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  WALLY_DISPATCH_LOGN(k_ks_extend, WALLY_KS_LOGE, dim3(xcd_blocks(n_items * a.L, a.L + 1)), items, a, n_items, M);
+  WALLY_DISPATCH_LOGN(k_ks_extend, WALLY_KS_LOGE, dim3(xcd_blocks(n_items * a.L, a.L)), items, a, n_items, M);
   return hipGetLastError();
 }
 
