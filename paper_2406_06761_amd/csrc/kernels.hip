@@ -168,29 +168,36 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const K
 // words per thread through 16-byte loads).  D words are below 54 q (the
 // forward transform's lazy bound), key words below q.
 // grid (n / 512, L+1, items); block 256
+template <int L>
 __global__ __launch_bounds__(256) void k_ks_inner(const KsItem* __restrict__ items, KsArgs a, DevModuli M) {
+  constexpr int MM = L + 1;
   const int m = blockIdx.y, b = blockIdx.z;
-  const int L = a.L, MM = a.L + 1;
   const uint64_t n = 1ull << a.log_n;
   const uint64_t p = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 2;
   WALLY_GLOBAL const uint64_t* key = gmem(items[b].key);
   const uint64_t* D = a.D + ((uint64_t)b * MM + m) * L * n + p;
   const ModConst mc = M.mc[m];
-  u128w a00{0, 0}, a01{0, 0}, a10{0, 0}, a11{0, 0};  // [t][word]
+  // all 3L loads of a thread are issued before the first product (L is a
+  // compile-time constant), so each thread keeps 48 L bytes in flight
+  u64x2 d[L], k0[L], k1[L];
+#pragma unroll
   for (int i = 0; i < L; ++i) {
-    const ulonglong2 d = *reinterpret_cast<const ulonglong2*>(D + (uint64_t)i * n);
-    const u64x2 k0 = *(WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + 0) * MM + m) * n + p);
-    const u64x2 k1 = *(WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + 1) * MM + m) * n + p);
-    mac128(a00, d.x, k0.x);
-    mac128(a01, d.y, k0.y);
-    mac128(a10, d.x, k1.x);
-    mac128(a11, d.y, k1.y);
+    d[i] = *(WALLY_GLOBAL const u64x2*)(D + (uint64_t)i * n);
+    k0[i] = *(WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + 0) * MM + m) * n + p);
+    k1[i] = *(WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + 1) * MM + m) * n + p);
+  }
+  u128w a00{0, 0}, a01{0, 0}, a10{0, 0}, a11{0, 0};  // [t][word]
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    mac128(a00, d[i].x, k0[i].x);
+    mac128(a01, d[i].y, k0[i].y);
+    mac128(a10, d[i].x, k1[i].x);
+    mac128(a11, d[i].y, k1[i].y);
   }
   uint64_t* U = a.U + ((uint64_t)b * 2 * MM + m) * n + p;  // U[b][t][m], m = L is the P part
-  *reinterpret_cast<ulonglong2*>(U) = ulonglong2{reduce128(a00, mc.q, mc.r64, mc.r64p, mc.onep),
-                                                 reduce128(a01, mc.q, mc.r64, mc.r64p, mc.onep)};
-  *reinterpret_cast<ulonglong2*>(U + (uint64_t)MM * n) = ulonglong2{reduce128(a10, mc.q, mc.r64, mc.r64p, mc.onep),
-                                                                    reduce128(a11, mc.q, mc.r64, mc.r64p, mc.onep)};
+  *(WALLY_GLOBAL u64x2*)U = u64x2{reduce128(a00, mc.q, mc.r64, mc.r64p, mc.onep), reduce128(a01, mc.q, mc.r64, mc.r64p, mc.onep)};
+  *(WALLY_GLOBAL u64x2*)(U + (uint64_t)MM * n) =
+      u64x2{reduce128(a10, mc.q, mc.r64, mc.r64p, mc.onep), reduce128(a11, mc.q, mc.r64, mc.r64p, mc.onep)};
 }
 
 // ---------------------------------------------------------------------------
@@ -578,7 +585,18 @@ hipError_t launch_ks_extend(const KsItem* items, int n_items, const KsArgs& a, c
 
 hipError_t launch_ks_inner(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ks_inner, dim3((1u << a.log_n) / 512, a.L + 1, n_items), dim3(256), 0, st, items, a, M);
+  const dim3 grid((1u << a.log_n) / 512, a.L + 1, n_items);
+  switch (a.L) {
+    case 1: hipLaunchKernelGGL(k_ks_inner<1>, grid, dim3(256), 0, st, items, a, M); break;
+    case 2: hipLaunchKernelGGL(k_ks_inner<2>, grid, dim3(256), 0, st, items, a, M); break;
+    case 3: hipLaunchKernelGGL(k_ks_inner<3>, grid, dim3(256), 0, st, items, a, M); break;
+    case 4: hipLaunchKernelGGL(k_ks_inner<4>, grid, dim3(256), 0, st, items, a, M); break;
+    case 5: hipLaunchKernelGGL(k_ks_inner<5>, grid, dim3(256), 0, st, items, a, M); break;
+    case 6: hipLaunchKernelGGL(k_ks_inner<6>, grid, dim3(256), 0, st, items, a, M); break;
+    case 7: hipLaunchKernelGGL(k_ks_inner<7>, grid, dim3(256), 0, st, items, a, M); break;
+    case 8: hipLaunchKernelGGL(k_ks_inner<8>, grid, dim3(256), 0, st, items, a, M); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
