@@ -149,6 +149,66 @@ def test_small_end_to_end(pair):
         assert dec_ok, (name, i)
 
 
+@pytest.mark.parametrize("log_n,L,bits", [(12, 1, 36), (12, 2, 36), (12, 5, 40), (12, 8, 36), (13, 6, 50)])
+def test_rotate_parity_other_limb_counts(log_n, L, bits):
+    """Key switching at limb counts the presets do not use (the kernels are
+    instantiated per limb count): both rotations, word for word."""
+    from paper_2406_06761_amd.wally import Context, to_device, to_host
+
+    p = Params(log_n=log_n, L=L, limb_bits=bits, t_bits=20, dim=64)
+    o = Oracle(p)
+    c = Context(log_n, L, bits, 20, 64, max_batch=4)
+    try:
+        rng = np.random.default_rng(7 + L)
+        count = 3
+        ct = np.stack([o.uniform(rng, p.q, count=2) for _ in range(count)])
+        keys = np.stack([o.uniform(rng, p.moduli, count=2 * L).reshape(L, 2, L + 1, p.n) for _ in range(count)])
+        for which, gal in ((0, p.gal_baby), (1, p.gal_giant)):
+            dct, dk = to_device(ct), to_device(keys)
+            dout = torch.empty_like(dct)
+            c.diag_rotate(dct, dk, dout, which)
+            torch.cuda.synchronize()
+            got = to_host(dout)
+            for k in range(count):
+                assert (got[k] == o.rotate(ct[k], keys[k], gal)).all(), (L, which, k)
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("log_n,L,bits", [(12, 2, 50), (13, 6, 50)])
+def test_end_to_end_other_limb_counts(log_n, L, bits):
+    """Scoring through the batched path at other limb counts: response words
+    equal the oracle's and decrypt to the dot products."""
+    from paper_2406_06761_amd.wally import Context, query_array, to_device, to_host
+
+    p = Params(log_n=log_n, L=L, limb_bits=bits, t_bits=20, dim=64)
+    o = Oracle(p)
+    c = Context(log_n, L, bits, 20, 64, max_batch=4)
+    try:
+        sizes = np.array([300], dtype=np.int64)
+        emb = synth.embeddings(300, 64, seed=61, norm="l2")
+        offs = synth.offsets(sizes)
+        c.encode_clusters(emb, offs)
+        qv = synth.query_vectors(2, 64, "l2", seed=62)
+        rng = np.random.default_rng(63)
+        packets = [o.make_query(qv[i], rng) for i in range(2)]
+        outs = [torch.zeros((1, 2, L, p.n), dtype=torch.int64, device="cuda") for _ in range(2)]
+        dev = [(to_device(ct), to_device(kb), to_device(kg)) for ct, kb, kg, _ in packets]
+        q = query_array(np.zeros(2, dtype=np.uint32), [d[0].data_ptr() for d in dev], [d[1].data_ptr() for d in dev],
+                        [d[2].data_ptr() for d in dev], [x.data_ptr() for x in outs])
+        c.score_batch(q)
+        torch.cuda.synchronize()
+        pt = o.encode_cluster(emb)
+        refs = o.score_many([(ct, kb, kg, pt) for ct, kb, kg, _ in packets], threads=2)
+        for i in range(2):
+            got = to_host(outs[i])
+            assert (got == refs[i]).all(), (L, i)
+            dec = o.decrypt(packets[i][3], got[0]).astype(np.int64)
+            assert (dec[:300] == (emb.astype(np.int64) @ qv[i].astype(np.int64)) % p.t).all(), (L, i)
+    finally:
+        c.close()
+
+
 def _read_device(ptr, words):
     """Copy `words` uint64 from a device address into host memory."""
     import ctypes
