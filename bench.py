@@ -508,6 +508,17 @@ def main():
             traffic = stored_traffic(roofline["kernel"], preset_name)
             if traffic is not None:
                 roofline["traffic"] = traffic * roofline["items_per_launch"]
+            # the whole key switch against HBM: counter-calibrated bytes per
+            # item of each of its kernels times the items of one step
+            ks = [k for k in kstats if k.startswith("ks_") and kstats[k][1]]
+            bpi = {k: stored_traffic(k, preset_name) for k in ks}
+            if ks and all(v is not None for v in bpi.values()):
+                ks_bytes = sum(bpi[k] * kstats[k][1] for k in ks) / args.steps
+                roofline["path_hbm"] = {
+                    "scope": "key-switch kernels (calibrated bytes per item x items per step); the giant-step sums "
+                             "and copies add a few percent more",
+                    "bytes_per_step": ks_bytes, "achieved_tbs": ks_bytes / (ms_per_step * 1e-3) / 1e12,
+                    "frac": ks_bytes / (ms_per_step * 1e-3) / HBM_PEAK}
 
     graph = None
     graph_b = None
