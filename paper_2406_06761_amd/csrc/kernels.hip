@@ -19,6 +19,13 @@
 // acc_i = sum_j PT[g i + j] * ct'_j (Server Computation algorithm, paper §5)
 // are computed for all i by one tiled kernel; a Horner step
 // R <- acc_i + Rot(R, g) adds acc_i inside ks_moddown.
+//
+// Rows that a launch touches once (keys, extended digits, key inner products,
+// sigma's source rows, acc_i, the sums' rotated copies) are read and, for the
+// extended digits and inner products, written with non-temporal accesses: a
+// launch streams hundreds of MB of them, and as ordinary accesses they would
+// displace the rows that are re-read from the caches (digits, P parts,
+// plaintexts, twiddles).
 #include "kernels.h"
 #include "ntt.h"
 
@@ -72,25 +79,32 @@ __device__ __forceinline__ WALLY_GLOBAL uint64_t* sel_out(const KsItem* it, int 
 // whose output (forward) or input (inverse) is in this order needs no
 // exchange to or from the natural order.  Rows live in global memory (the
 // pointer may be generic or global-typed).
-template <int LOGN, int LOGE, class PTR>
+template <int LOGN, int LOGE, bool NT = false, class PTR>
 __device__ __forceinline__ void load_last(uint64_t (&x)[1 << LOGE], PTR src, int tid) {
   using LM = LastMap<LOGN, LOGE>;
   static_assert(LM::LOWB == 0 && LM::RW >= 1, "pairs of the last pass are adjacent words");
 #pragma unroll
   for (int c = 0; c < (1 << LOGE) / 2; ++c) {
-    const u64x2 v = *(WALLY_GLOBAL const u64x2*)(src + LM::idx(tid, 2 * c));
+    WALLY_GLOBAL const u64x2* p = (WALLY_GLOBAL const u64x2*)(src + LM::idx(tid, 2 * c));
+    const u64x2 v = NT ? __builtin_nontemporal_load(p) : *p;
     x[2 * c] = v.x;
     x[2 * c + 1] = v.y;
   }
 }
 
-template <int LOGN, int LOGE, class PTR>
+template <int LOGN, int LOGE, bool NT = false, class PTR>
 __device__ __forceinline__ void store_last(PTR dst, const uint64_t (&x)[1 << LOGE], int tid) {
   using LM = LastMap<LOGN, LOGE>;
   static_assert(LM::LOWB == 0 && LM::RW >= 1, "pairs of the last pass are adjacent words");
 #pragma unroll
   for (int c = 0; c < (1 << LOGE) / 2; ++c)
-    *(WALLY_GLOBAL u64x2*)(dst + LM::idx(tid, 2 * c)) = u64x2{x[2 * c], x[2 * c + 1]};
+  {
+    WALLY_GLOBAL u64x2* p = (WALLY_GLOBAL u64x2*)(dst + LM::idx(tid, 2 * c));
+    if (NT)
+      __builtin_nontemporal_store(u64x2{x[2 * c], x[2 * c + 1]}, p);
+    else
+      *p = u64x2{x[2 * c], x[2 * c + 1]};
+  }
 }
 
 // XCD-aware placement. The work-groups of a launch go to the eight XCDs round
@@ -125,7 +139,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_digits(const K
   const uint64_t q = M.q[i];
   uint64_t x[S::E];
   gather_galois<LOGN, LOGE, LastMap<LOGN, LOGE>>(x, c1, lds, a.gal, tid);  // sigma(c1)_i, INTT input order
-  store_last<LOGN, LOGE>(a.D + (((uint64_t)b * (a.L + 1) + i) * a.L + i) * S::N, x, tid);  // D[i][i]
+  store_last<LOGN, LOGE, true>(a.D + (((uint64_t)b * (a.L + 1) + i) * a.L + i) * S::N, x, tid);  // D[i][i]
   ntt_inv<LOGN, LOGE>(x, lds, M.inv[i], q, tid);
   uint64_t* X = a.X + ((uint64_t)b * a.L + i) * S::N;
 #pragma unroll
@@ -159,7 +173,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const K
   // stored unreduced: the inner product's 128-bit sums take words below 54 q
   // (up to eight products of them with key words stay below 2^117) and
   // reduce once
-  store_last<LOGN, LOGE>(D, d, tid);
+  store_last<LOGN, LOGE, true>(D, d, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,9 +196,9 @@ __global__ __launch_bounds__(256) void k_ks_inner(const KsItem* __restrict__ ite
   u64x2 d[L], k0[L], k1[L];
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    d[i] = *(WALLY_GLOBAL const u64x2*)(D + (uint64_t)i * n);
-    k0[i] = *(WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + 0) * MM + m) * n + p);
-    k1[i] = *(WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + 1) * MM + m) * n + p);
+    d[i] = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(D + (uint64_t)i * n));
+    k0[i] = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + 0) * MM + m) * n + p));
+    k1[i] = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + 1) * MM + m) * n + p));
   }
   u128w a00{0, 0}, a01{0, 0}, a10{0, 0}, a11{0, 0};  // [t][word]
 #pragma unroll
@@ -195,9 +209,10 @@ __global__ __launch_bounds__(256) void k_ks_inner(const KsItem* __restrict__ ite
     mac128(a11, d[i].y, k1[i].y);
   }
   uint64_t* U = a.U + ((uint64_t)b * 2 * MM + m) * n + p;  // U[b][t][m], m = L is the P part
-  *(WALLY_GLOBAL u64x2*)U = u64x2{reduce128(a00, mc.q, mc.r64, mc.r64p, mc.onep), reduce128(a01, mc.q, mc.r64, mc.r64p, mc.onep)};
-  *(WALLY_GLOBAL u64x2*)(U + (uint64_t)MM * n) =
-      u64x2{reduce128(a10, mc.q, mc.r64, mc.r64p, mc.onep), reduce128(a11, mc.q, mc.r64, mc.r64p, mc.onep)};
+  __builtin_nontemporal_store(u64x2{reduce128(a00, mc.q, mc.r64, mc.r64p, mc.onep), reduce128(a01, mc.q, mc.r64, mc.r64p, mc.onep)},
+                              (WALLY_GLOBAL u64x2*)U);
+  __builtin_nontemporal_store(u64x2{reduce128(a10, mc.q, mc.r64, mc.r64p, mc.onep), reduce128(a11, mc.q, mc.r64, mc.r64p, mc.onep)},
+                              (WALLY_GLOBAL u64x2*)(U + (uint64_t)MM * n));
 }
 
 // ---------------------------------------------------------------------------
@@ -214,7 +229,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_pinv(KsArgs a,
   const uint64_t P = M.q[L];
   const uint64_t* U = a.U + (((uint64_t)b * 2 + t) * MM + L) * S::N;
   uint64_t y[S::E];
-  load_last<LOGN, LOGE>(y, U, tid);
+  load_last<LOGN, LOGE, true>(y, U, tid);
   ntt_inv<LOGN, LOGE>(y, lds, M.inv[L], P, tid);  // out FirstMap order
   uint64_t* Y = a.Y + ((uint64_t)b * 2 + t) * S::N;
 #pragma unroll
@@ -256,7 +271,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_wa
   const uint64_t* U = a.U + (((uint64_t)b * 2 + t) * MM + j) * S::N;
 #pragma unroll
   for (int c = 0; c < S::E / 2; ++c) {
-    const u64x2 u = *(WALLY_GLOBAL const u64x2*)(U + LM::idx(tid, 2 * c));
+    const u64x2 u = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(U + LM::idx(tid, 2 * c)));
     z[2 * c] = csub(shoup(u.x + zb - z[2 * c], M.pinv[j], M.pinvp[j], q), q);
     z[2 * c + 1] = csub(shoup(u.y + zb - z[2 * c + 1], M.pinv[j], M.pinvp[j], q), q);
   }
@@ -266,7 +281,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_wa
     WALLY_GLOBAL const uint64_t* acc = gmem(items[b].acc) + (uint64_t)a.giant * 2 * L * S::N + toff;
 #pragma unroll
     for (int c = 0; c < S::E / 2; ++c) {
-      const u64x2 v = *(WALLY_GLOBAL const u64x2*)(acc + LM::idx(tid, 2 * c));
+      const u64x2 v = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(acc + LM::idx(tid, 2 * c)));
       z[2 * c] = addmod(z[2 * c], v.x, q);
       z[2 * c + 1] = addmod(z[2 * c + 1], v.y, q);
     }
@@ -327,7 +342,7 @@ __global__ __launch_bounds__(256) void k_mac_tiles(const KsItem* __restrict__ it
       WALLY_GLOBAL const uint64_t* ctp = gmem(it.ctp) + ((uint64_t)(t0 + p) * L + j) * n + x;
 #pragma unroll
       for (int jj = 0; jj < G; ++jj) {
-        const uint64_t v = ctp[jj * ctw];
+        const uint64_t v = __builtin_nontemporal_load(&ctp[jj * ctw]);
         cl[p][jj] = (uint32_t)(v & M27);
         ch[p][jj] = (uint32_t)(v >> 27);
       }

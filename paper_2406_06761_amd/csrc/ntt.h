@@ -243,7 +243,8 @@ __device__ __forceinline__ uint32_t galois_src(uint32_t i, uint32_t gal) {
 
 // x <- sigma_gal(src) in the register mapping MAP: the row is read with
 // coalesced loads into LDS and permuted there (a direct gather from global
-// memory would touch a different cache line in every lane).
+// memory would touch a different cache line in every lane).  The source row is
+// read once, so the loads are non-temporal.
 template <int LOGN, int LOGE, class MAP, class SRC>
 __device__ __forceinline__ void gather_galois(uint64_t (&x)[1 << LOGE], SRC src, uint64_t* lds, uint32_t gal,
                                               int tid) {
@@ -251,7 +252,7 @@ __device__ __forceinline__ void gather_galois(uint64_t (&x)[1 << LOGE], SRC src,
   using FM = FirstMap<LOGN, LOGE>;
   uint64_t* wa = lds + lds_base<LOGN, LOGE, FM>(tid);
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = src[FM::idx(tid, e)];
+  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = __builtin_nontemporal_load(&src[FM::idx(tid, e)]);
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < S::E; ++e) x[e] = lds[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))];
@@ -268,7 +269,7 @@ __device__ __forceinline__ void add_galois(uint64_t (&x)[1 << LOGE], SRC src, ui
   using FM = FirstMap<LOGN, LOGE>;
   uint64_t* wa = lds + lds_base<LOGN, LOGE, FM>(tid);
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = src[FM::idx(tid, e)];
+  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = __builtin_nontemporal_load(&src[FM::idx(tid, e)]);
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < S::E; ++e) x[e] = addmod(x[e], lds[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))], q);
