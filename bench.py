@@ -71,11 +71,17 @@ KERNEL_SOURCES = ["kernels.hip", "ntt.h", "arith.h", "kernels.h"]
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with comments and blank lines removed, so
+    that an edit of a comment does not invalidate the stored counters."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update((Path(__file__).resolve().parent / "paper_2406_06761_amd" / "csrc" / f).read_bytes())
+        text = (Path(__file__).resolve().parent / "paper_2406_06761_amd" / "csrc" / f).read_text()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
+        h.update("\n".join(ln for ln in lines if ln.strip()).encode())
     return h.hexdigest()
 
 

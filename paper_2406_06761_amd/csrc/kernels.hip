@@ -13,9 +13,10 @@
 //   ks_pinv   : y_t = INTT_P(u_t[P])                                (2 per item)
 //   ks_moddown: out_t[j] = (u_t[j] - NTT_j([y_t]_centred mod q_j)) * P^-1
 //               (+ sigma(c0)_j for t = 0) (+ acc_i)                (2L per item)
-// Each transform kernel does one NTT per workgroup with natural-order global
-// I/O, so the compute-bound transforms stay light on registers and the
-// memory-bound inner product runs at full occupancy.  The giant-step sums
+// Each transform kernel does one NTT per workgroup, with coalesced row I/O
+// (lane-consecutive words, or lane-consecutive word pairs where a row is in
+// the last pass's order), so the compute-bound transforms stay light on
+// registers and the memory-bound inner product runs at full occupancy.  The giant-step sums
 // acc_i = sum_j PT[g i + j] * ct'_j (Server Computation algorithm, paper §5)
 // are computed for all i by one tiled kernel; a Horner step
 // R <- acc_i + Rot(R, g) adds acc_i inside ks_moddown.
