@@ -282,6 +282,99 @@ def crt_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def fold_bench(args):
+    """Folded small-cluster layout (not in the paper): the paper-scale workload
+    scored with the per-cluster layout and then with the folded one (clusters
+    of at most n/B entries spread each entry over B slots and score d_pad/B
+    diagonals, plus log2 B rotate-and-add steps), same queries, same packet
+    pool (uniform residues; each packet also carries the fold keys).  The value
+    is the folded layout's scores per second; the per-cluster layout's is
+    reported beside it."""
+    import torch
+
+    from paper_2406_06761_amd import synth
+    from paper_2406_06761_amd.wally import LAYOUT_FOLDED, LAYOUT_PER_CLUSTER, PATH_BATCHED, Context, query_array
+
+    torch.cuda.set_device(0)
+    w = synth.paper_workload(n_real=args.real or 50_000)
+    log(f"generating {w.n_entries} x {w.dim} int8 entries")
+    emb = synth.embeddings_parallel(w.n_entries, w.dim, norm=w.norm, threads=16)
+    offs = synth.offsets(w.sizes)
+    nq = len(w.targets)
+    scores = int(w.sizes[w.targets].sum())
+    pool_t, legs = None, {}
+    for name, layout in (("per_cluster", LAYOUT_PER_CLUSTER), ("folded", LAYOUT_FOLDED)):
+        kw = {"fold_max": args.fold_max} if layout == LAYOUT_FOLDED else {}
+        ctx = Context.preset("paper", max_batch=args.max_batch, wave_sets=args.wave_sets, layout=layout, **kw)
+        info = ctx.info
+        n, L = info.n, info.L
+        t0 = time.perf_counter()
+        ctx.encode_clusters(emb, offs)
+        torch.cuda.synchronize()
+        enc = time.perf_counter() - t0
+        index_bytes = int(ctx.bytes_allocated)
+        folds = np.array([ctx.cluster_fold(c)[0] for c in range(len(w.sizes))], dtype=np.int64)
+        chunks = np.array([ctx.cluster_info(c)[0] for c in range(len(w.sizes))], dtype=np.int64)
+        if pool_t is None:
+            pool = min(args.pool, nq)
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(synth.SEED_CRYPTO)
+            qs = [info.q[j] for j in range(L)]
+            mods = qs + [info.P]
+            cts = synth.uniform_residues(gen, (pool, 2), qs, n, device="cuda")
+            kbs = synth.uniform_residues(gen, (pool, L, 2), mods, n, device="cuda")
+            kgs = synth.uniform_residues(gen, (pool, L, 2), mods, n, device="cuda")
+            n_fold_keys = max(1, int(args.fold_max).bit_length() - 1)
+            kfs = synth.uniform_residues(gen, (pool, n_fold_keys * L, 2), mods, n, device="cuda")
+            pool_t = (pool, cts, kbs, kgs, kfs)
+        pool, cts, kbs, kgs, kfs = pool_t
+        q_chunks = chunks[w.targets]
+        ctw = int(info.ct_words)
+        out_off = np.zeros(nq, dtype=np.int64)
+        out_off[1:] = np.cumsum(q_chunks)[:-1]
+        outs = torch.empty(int(q_chunks.sum()) * ctw, dtype=torch.int64, device="cuda")
+        pidx = np.arange(nq) % pool
+        q = query_array(w.targets, cts.data_ptr() + pidx * cts[0].numel() * 8,
+                        kbs.data_ptr() + pidx * kbs[0].numel() * 8, kgs.data_ptr() + pidx * kgs[0].numel() * 8,
+                        outs.data_ptr() + out_off * ctw * 8, kfs.data_ptr() + pidx * kfs[0].numel() * 8)
+        for i in range(args.warmup):
+            ctx.score_batch(q, path=PATH_BATCHED)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ctx.score_batch(q, path=PATH_BATCHED)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        qf = folds[w.targets]
+        hist = {int(b): int((qf == b).sum()) for b in np.unique(qf)}
+        # key switches per query: (g'-1) baby + per chunk (h'-1) giant + log2 B fold
+        ks = 0
+        for b, cnt in hist.items():
+            D = info.d_pad // b
+            g = 1 << ((D.bit_length() - 1 + 1) // 2)
+            h = D // g
+            sel = qf == b
+            ks += cnt * (g - 1) + int(q_chunks[sel].sum()) * (h - 1 + (b.bit_length() - 1))
+        legs[name] = {"ms_per_step": ms, "scores_per_s": scores / (ms * 1e-3), "encode_s": enc,
+                      "index_gib": index_bytes / 2**30, "queries_per_fold": hist,
+                      "key_switches_per_query": ks / nq}
+        log(f"{name}: {ms:.1f} ms per batch, {scores / (ms * 1e-3):.3e} scores/s, index {index_bytes / 2**30:.1f} GiB, "
+            f"{ks / nq:.1f} key switches per query, queries per fold {hist}")
+        del outs
+        ctx.close()
+        torch.cuda.empty_cache()
+    f, pc = legs["folded"], legs["per_cluster"]
+    line = {"metric": "encrypted query-entry scores/sec (batched path, folded small-cluster layout)",
+            "value": f["scores_per_s"], "unit": "scores/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": f["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"3.2M x 192 int8, 1800 lognormal(0.8) clusters, {w.n_real // 1000}k Zipf(1.1) "
+                                   f"queries + NB(2,0.5) fakes", "layout": "folded", "fold_max": args.fold_max,
+                       "queries": nq, "scores_per_step": scores},
+            "speedup_vs_per_cluster_layout": pc["ms_per_step"] / f["ms_per_step"], "legs": legs}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +401,10 @@ def main():
     ap.add_argument("--no-compress", action="store_true", help="skip the response-compression leg")
     ap.add_argument("--plaintext-crt", action="store_true",
                     help="score 15-bit entries under two plaintext moduli (paper 7.3) instead")
+    ap.add_argument("--folded", action="store_true",
+                    help="paper workload with the folded small-cluster layout (not in the paper), "
+                         "next to the per-cluster layout")
+    ap.add_argument("--fold-max", type=int, default=16, help="largest fold factor of the folded layout")
     args = ap.parse_args()
     if args.serve_rates is None:
         args.serve_rates = "5000,20000,50000" if args.workload == "paper" else ""
@@ -320,6 +417,9 @@ def main():
 
     if args.plaintext_crt:
         crt_bench(args)
+        return
+    if args.folded:
+        fold_bench(args)
         return
 
     import torch

@@ -56,6 +56,20 @@ extern "C" {
  * at the cluster's slot base (wally_cluster_info) and the other slots of a
  * shared chunk score other clusters' entries. */
 #define WALLY_LAYOUT_COPACK 1
+/* Not in the paper; a refinement of the diagonal packing (§4.1) for clusters
+ * that fill a small part of a chunk.  Cluster c gets a fold factor B_c, the
+ * largest power of two <= fold_max with B_c N_c <= n and d_pad / B_c >= 4
+ * (B_c = 1 for clusters of more than n/2 entries, which are laid out exactly
+ * as in WALLY_LAYOUT_PER_CLUSTER).  With D = d_pad / B_c, an entry owns B_c
+ * slots that each accumulate D of its coordinates: a chunk holds n / B_c
+ * entries, entry e (index inside its chunk) is scored in flat slot
+ * (e / D) d_pad + e mod D, and the chunk has D plaintexts instead of d_pad.
+ * Scoring runs the baby-step giant-step split on the D diagonals
+ * (g' = 2^ceil(log2(D)/2), h' = D / g'), then log2 B_c rotate-and-add steps
+ * R = R + Rot(R, r) for r = d_pad/2, d_pad/4, ..., D, which sum the partial
+ * products.  The query ciphertext is the usual one; the client sends the
+ * giant-step key for g' and the fold keys (wally_cluster_fold). */
+#define WALLY_LAYOUT_FOLDED 2
 
 #define WALLY_PATH_BATCHED 0 /* queries of all clusters share launches        */
 #define WALLY_PATH_PLAIN 1   /* one launch sequence per cluster (baseline)     */
@@ -69,13 +83,14 @@ typedef struct {
   uint32_t limb_bits;  /* 30..54 bits per ciphertext prime                  */
   uint32_t t_bits;     /* plaintext modulus just above 2^t_bits (< limb_bits)*/
   uint32_t dim;        /* embedding dimension d                             */
-  uint32_t layout;     /* WALLY_LAYOUT_PER_CLUSTER or WALLY_LAYOUT_COPACK     */
+  uint32_t layout;     /* WALLY_LAYOUT_PER_CLUSTER, _COPACK or _FOLDED       */
   int32_t device;      /* HIP device ordinal                                */
   uint32_t max_batch;  /* queries resident per wave (0 = 512, at most 32768;
                           max_batch x chunks of the largest cluster at most
                           32768, else scoring returns WALLY_EINVAL)          */
   uint32_t wave_sets;  /* waves in flight on separate streams (0 = 2)       */
-  uint32_t reserved;   /* must be 0                                         */
+  uint32_t fold_max;   /* WALLY_LAYOUT_FOLDED: largest fold factor, a power
+                          of two (0 = 16); must be 0 for the other layouts  */
   uint64_t hbm_budget; /* bytes the context may allocate (0 = 90% of free)  */
 } wally_params_desc;
 
@@ -97,7 +112,10 @@ typedef struct {
 } wally_params_info;
 
 /* One query: every pointer is a device pointer.  `out` receives
- * chunks(cluster) consecutive ciphertexts. */
+ * chunks(cluster) consecutive ciphertexts.  In WALLY_LAYOUT_FOLDED, key_giant
+ * is the key for the cluster's own giant step (wally_cluster_fold) and
+ * key_fold holds its log2(fold) fold keys, in the order of gal_fold (NULL
+ * allowed when the fold factor is 1); the other layouts ignore key_fold. */
 typedef struct {
   uint32_t cluster;
   uint32_t reserved;
@@ -105,6 +123,7 @@ typedef struct {
   const uint64_t* key_baby;  /* [L][2][L+1][n]                              */
   const uint64_t* key_giant; /* [L][2][L+1][n]                              */
   uint64_t* out;             /* [chunks][2][L][n]                           */
+  const uint64_t* key_fold;  /* [log2 fold][L][2][L+1][n]                   */
 } wally_query;
 
 /* Derive the parameters (rules above), build the NTT tables on the host and
@@ -150,12 +169,24 @@ int wally_encode_clusters_i16(wally_ctx* ctx, const int16_t* emb, uint64_t n_ent
 int wally_compress_responses(wally_ctx* ctx, const uint64_t* in, uint64_t chunks, uint8_t* out, void* hip_stream);
 
 /* Chunks of cluster c, the slot of its first entry in its first chunk (0 in
- * the per-cluster layout) and the device address of its plaintexts
- * [chunks][d_pad][L][n] (read-only for the caller).  Entry e of the cluster
- * is scored in slot (slot_base + e) mod n of chunk (slot_base + e) / n of the
- * response.  Any output pointer may be NULL.  EINVAL for c >= K. */
+ * the per-cluster and folded layouts) and the device address of its
+ * plaintexts [chunks][D][L][n] (D = d_pad except in the folded layout;
+ * read-only for the caller).  Entry e of the cluster is scored in slot
+ * (slot_base + e) mod n of chunk (slot_base + e) / n of the response (folded
+ * layout: see WALLY_LAYOUT_FOLDED).  Any output pointer may be NULL.  EINVAL
+ * for c >= K. */
 int wally_cluster_info(const wally_ctx* ctx, uint32_t c, uint32_t* n_chunks, uint32_t* slot_base,
                        const uint64_t** plaintexts);
+
+/* Fold factor of cluster c and what the client needs for its query: the
+ * baby-step and giant-step counts g', h' (g' h' = d_pad / fold), the Galois
+ * element X -> X^(3^g' mod 2n) of its giant-step key and the log2(fold)
+ * elements X -> X^(3^r mod 2n), r = d_pad/2, d_pad/4, ..., d_pad/fold, of its
+ * fold keys (gal_fold must have room for 8).  In the other layouts fold = 1
+ * and g', h' are the context's g, h.  Any output pointer may be NULL.  EINVAL
+ * for c >= K. */
+int wally_cluster_fold(const wally_ctx* ctx, uint32_t c, uint32_t* fold, uint32_t* g, uint32_t* h,
+                       uint64_t* gal_giant, uint64_t* gal_fold);
 
 /* Score nq queries (Server Computation algorithm, paper §5): for each, g-1
  * baby-step rotations, then per chunk the giant-step sums of plaintext

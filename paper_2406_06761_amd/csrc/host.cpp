@@ -208,6 +208,10 @@ struct wally_ctx {
   std::vector<uint32_t> chunks;      // chunks scored per cluster
   std::vector<uint64_t> chunk_base;  // first chunk of each cluster
   std::vector<uint32_t> slot_base;   // slot of each cluster's first entry in its first chunk
+  std::vector<uint32_t> fold;        // fold factor of each cluster (1 unless folded)
+  std::vector<uint64_t> chunk_pt;    // word offset of each chunk's plaintexts in pt
+  uint32_t fold_max = 1;
+  uint64_t gal_fold[8] = {};         // X -> X^(3^r mod 2n), r = d_pad/2, d_pad/4, ...
   uint32_t max_chunks = 0;
   uint64_t n_chunks_total = 0;
   uint64_t* pt = nullptr;
@@ -266,28 +270,59 @@ struct ChunkSeg {
 struct ChunkLayout {
   std::vector<std::vector<ChunkSeg>> segs;  // per chunk, in slot order
   std::vector<uint64_t> first;
-  std::vector<uint32_t> chunks, base;
+  std::vector<uint32_t> chunks, base, fold;
 };
 
-void plan_layout(uint32_t layout, const uint64_t* offsets, uint32_t k, uint32_t n, ChunkLayout& out) {
+// Fold factor of a cluster in the folded layout (not in the paper): the
+// largest power of two B <= fold_max with B N_c <= n and d_pad / B >= 4.
+uint32_t fold_factor(uint64_t size, uint32_t n, uint32_t d_pad, uint32_t fold_max) {
+  uint32_t B = 1;
+  while (2 * B <= fold_max && 2 * B * size <= n && d_pad / (2 * B) >= 4) B *= 2;
+  return B;
+}
+
+// Baby/giant split of the d_pad / B diagonals of a fold class.
+struct FoldCls {
+  uint32_t B, g, h, gal_giant;
+};
+FoldCls fold_cls(const wally_ctx* c, uint32_t B) {
+  const uint32_t D = c->d_pad / B;
+  int lg = 0;
+  while ((1u << lg) < D) ++lg;
+  const uint32_t g = 1u << ((lg + 1) / 2);
+  return FoldCls{B, g, D / g, (uint32_t)powmod(3, g, 2ull * c->n)};
+}
+
+void plan_layout(uint32_t layout, const uint64_t* offsets, uint32_t k, uint32_t n, uint32_t d_pad, uint32_t fold_max,
+                 ChunkLayout& out) {
   out.segs.clear();
   out.first.assign(k, 0);
   out.chunks.assign(k, 0);
   out.base.assign(k, 0);
-  auto own_chunks = [&](uint32_t c) {
+  out.fold.assign(k, 1);
+  // chunks of cap = n / B entries each
+  auto own_chunks = [&](uint32_t c, uint32_t cap) {
     const uint64_t sz = offsets[c + 1] - offsets[c];
     out.first[c] = out.segs.size();
-    out.chunks[c] = (uint32_t)((sz + n - 1) / n);
-    for (uint64_t off = 0; off < sz; off += n) out.segs.push_back({ChunkSeg{c, off, std::min<uint64_t>(n, sz - off)}});
+    out.chunks[c] = (uint32_t)((sz + cap - 1) / cap);
+    for (uint64_t off = 0; off < sz; off += cap)
+      out.segs.push_back({ChunkSeg{c, off, std::min<uint64_t>(cap, sz - off)}});
   };
   if (layout == WALLY_LAYOUT_PER_CLUSTER) {
-    for (uint32_t c = 0; c < k; ++c) own_chunks(c);
+    for (uint32_t c = 0; c < k; ++c) own_chunks(c, n);
+    return;
+  }
+  if (layout == WALLY_LAYOUT_FOLDED) {
+    for (uint32_t c = 0; c < k; ++c) {
+      out.fold[c] = fold_factor(offsets[c + 1] - offsets[c], n, d_pad, fold_max);
+      own_chunks(c, n / out.fold[c]);
+    }
     return;
   }
   std::vector<uint32_t> small;
   for (uint32_t c = 0; c < k; ++c) {
     if (offsets[c + 1] - offsets[c] > n)
-      own_chunks(c);
+      own_chunks(c, n);
     else
       small.push_back(c);
   }
@@ -496,20 +531,23 @@ KsArgs base_args(const wally_ctx* c, const WaveWork& s) {
 // chunk, split in sub-waves of at most B giant items.
 struct WavePlan {
   int w = 0;
+  FoldCls cls{1, 0, 0, 0};  // fold class shared by the wave's clusters
   size_t ng = 0, nt = 0;
   std::vector<std::pair<size_t, size_t>> sub_tiles;  // per sub-wave: [first tile, end tile)
 };
 
 void plan_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w, CopyItem* copy, KsItem* baby,
                KsItem* giant, MacTile* tiles, WavePlan& p) {
-  const uint64_t ctw = c->ctw(), ptw = c->ptw();
+  const uint64_t ctw = c->ctw();
+  p.cls = fold_cls(c, c->fold[qs[0]->cluster]);  // the waves of make_waves and serving are of one class
+  const FoldCls& fc = p.cls;
   std::vector<std::pair<uint64_t, uint32_t>> order;  // (global chunk index, item)
   std::vector<std::pair<int, uint32_t>> gq;           // (query slot, chunk)
   for (int k = 0; k < w; ++k) {
     const wally_query& q = *qs[k];
     uint64_t* ctp = s.ctp + (uint64_t)k * c->g * ctw;
     copy[k] = CopyItem{q.ct, ctp};
-    baby[k] = KsItem{q.key_baby, ctp, nullptr, nullptr, nullptr, nullptr, nullptr};
+    baby[k] = KsItem{q.key_baby, ctp, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     for (uint32_t ch = 0; ch < c->chunks[q.cluster]; ++ch) {
       order.push_back({c->chunk_base[q.cluster] + ch, (uint32_t)gq.size()});
       gq.push_back({k, ch});
@@ -532,12 +570,13 @@ void plan_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w, C
       const size_t slot = k - g0;
       KsItem it{};
       it.key = q.key_giant;
+      it.key_fold = q.key_fold;
       it.fin = q.out + (uint64_t)gi.second * ctw;
-      it.pt = c->pt + order[k].first * ptw;
+      it.pt = c->pt + c->chunk_pt[order[k].first];
       it.ctp = s.ctp + (uint64_t)gi.first * c->g * ctw;
       it.buf0 = s.R0 + slot * ctw;
       it.buf1 = s.R1 + slot * ctw;
-      it.acc = c->h == 1 ? it.fin : s.ACC + slot * c->h * ctw;
+      it.acc = fc.h == 1 && fc.B == 1 ? it.fin : s.ACC + slot * c->h * ctw;
       giant[k] = it;
       const bool start = k == g0 || order[k].first != order[k - 1].first || tiles[p.nt - 1].count >= c->tile_items;
       if (start) tiles[p.nt++] = MacTile{(uint32_t)(k - g0), 0};
@@ -553,9 +592,10 @@ int launch_wave(wally_ctx* c, WaveWork& s, const WavePlan& p, const CopyItem* co
                 const KsItem* giant, const MacTile* tiles, hipStream_t st) {
   const uint64_t ctw = c->ctw();
   const int w = p.w;
+  const FoldCls& fc = p.cls;
   // baby steps: ct'_0 = ct, ct'_j = Rot(ct'_{j-1}, 1)
   HIP_OK(c, timed(c, st, WALLY_KERNEL_COPY, w, [&] { return launch_copy_ct(copy, w, ctw, st); }));
-  for (int j = 1; j < c->g; ++j) {
+  for (int j = 1; j < (int)fc.g; ++j) {
     KsArgs a = base_args(c, s);
     a.gal = c->gal_baby;
     a.in_sel = 0;
@@ -565,7 +605,9 @@ int launch_wave(wally_ctx* c, WaveWork& s, const WavePlan& p, const CopyItem* co
     HIP_OK(c, keyswitch(c, baby, w, a, st));
   }
   // giant steps per (query, chunk): acc_i for all i, then
-  // R = acc_{h-1}; R = acc_i + Rot(R, g) for i = h-2 .. 0
+  // R = acc_{h-1}; R = acc_i + Rot(R, g) for i = h-2 .. 0;
+  // folded layout: then R = R + Rot(R, r) for r = d_pad/2, ..., d_pad/B
+  const int n_fold = __builtin_ctz(fc.B);
   for (size_t sw = 0; sw < p.sub_tiles.size(); ++sw) {
     const size_t g0 = sw * (size_t)c->B;
     const int cnt = (int)std::min<size_t>(c->B, p.ng - g0);
@@ -573,17 +615,32 @@ int launch_wave(wally_ctx* c, WaveWork& s, const WavePlan& p, const CopyItem* co
     const MacTile* tl = tiles + p.sub_tiles[sw].first;
     const int ntile = (int)(p.sub_tiles[sw].second - p.sub_tiles[sw].first);
     KsArgs a = base_args(c, s);
-    HIP_OK(c, timed(c, st, WALLY_KERNEL_MAC, cnt, [&] { return launch_mac_tiles(items, tl, ntile, a, c->h, c->M, st); }));
+    a.g = (int)fc.g;
+    HIP_OK(c, timed(c, st, WALLY_KERNEL_MAC, cnt, [&] { return launch_mac_tiles(items, tl, ntile, a, fc.h, c->M, st); }));
     int cur = 3;  // acc
-    uint64_t cur_off = (uint64_t)(c->h - 1) * ctw;
+    uint64_t cur_off = (uint64_t)(fc.h - 1) * ctw;
     int next = 0;
-    for (int i = c->h - 2; i >= 0; --i) {
+    for (int i = (int)fc.h - 2; i >= 0; --i) {
       KsArgs b = base_args(c, s);
-      b.gal = c->gal_giant;
+      b.gal = fc.gal_giant;
       b.in_sel = cur;
       b.in_off = cur_off;
-      b.out_sel = i == 0 ? 2 : next;
+      b.out_sel = i == 0 && n_fold == 0 ? 2 : next;
       b.giant = i;
+      HIP_OK(c, keyswitch(c, items, cnt, b, st));
+      cur = next;
+      cur_off = 0;
+      next = 1 - next;
+    }
+    for (int f = 0; f < n_fold; ++f) {
+      KsArgs b = base_args(c, s);
+      b.gal = (uint32_t)c->gal_fold[f];
+      b.in_sel = cur;
+      b.in_off = cur_off;
+      b.out_sel = f == n_fold - 1 ? 2 : next;
+      b.add_in = 1;
+      b.key_fold = 1;
+      b.key_off = (uint64_t)f * c->keyw();
       HIP_OK(c, keyswitch(c, items, cnt, b, st));
       cur = next;
       cur_off = 0;
@@ -615,6 +672,9 @@ int validate_query(wally_ctx* c, const wally_query& q, uint64_t idx) {
                                         (unsigned long long)idx, q.cluster, c->K);
   if (!q.ct || !q.key_baby || !q.key_giant || !q.out)
     return set_err(c, WALLY_EINVAL, "query %llu: null pointer", (unsigned long long)idx);
+  if (c->fold[q.cluster] > 1 && !q.key_fold)
+    return set_err(c, WALLY_EINVAL, "query %llu: cluster %u is folded (fold %u) and needs its fold keys",
+                   (unsigned long long)idx, q.cluster, c->fold[q.cluster]);
   if (((uintptr_t)q.ct | (uintptr_t)q.out) & 15)
     return set_err(c, WALLY_EINVAL, "query %llu: ct/out must be 16-byte aligned", (unsigned long long)idx);
   return WALLY_OK;
@@ -651,10 +711,16 @@ int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
   if (desc->limb_bits < 30 || desc->limb_bits > 54) return WALLY_EINVAL;  // 27-bit halves in the sums
   if (desc->t_bits < 2 || desc->t_bits + 2 > desc->limb_bits) return WALLY_EINVAL;
   if (desc->dim < 1) return WALLY_EINVAL;
-  if (desc->layout != WALLY_LAYOUT_PER_CLUSTER && desc->layout != WALLY_LAYOUT_COPACK) return WALLY_EINVAL;
+  if (desc->layout != WALLY_LAYOUT_PER_CLUSTER && desc->layout != WALLY_LAYOUT_COPACK &&
+      desc->layout != WALLY_LAYOUT_FOLDED)
+    return WALLY_EINVAL;
+  // fold_max: a power of two (at most 256, the fold keys gal_fold has room for) in the folded layout
+  if (desc->layout != WALLY_LAYOUT_FOLDED && desc->fold_max != 0) return WALLY_EINVAL;
+  if (desc->fold_max & (desc->fold_max - 1) || desc->fold_max > 256) return WALLY_EINVAL;
   wally_ctx* c = new (std::nothrow) wally_ctx();
   if (!c) return WALLY_ENOMEM;
   c->layout = desc->layout;
+  c->fold_max = desc->layout == WALLY_LAYOUT_FOLDED ? (desc->fold_max ? desc->fold_max : 16) : 1;
   c->device = desc->device;
   c->log_n = desc->log_n;
   c->n = 1 << c->log_n;
@@ -674,6 +740,7 @@ int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
   const uint64_t two_n = 2ull * c->n;
   c->gal_baby = 3;
   c->gal_giant = (uint32_t)powmod(3, c->g, two_n);
+  for (int f = 0, r = dp / 2; f < 8 && r >= 1; ++f, r /= 2) c->gal_fold[f] = powmod(3, r, two_n);
   // moduli: L + 1 largest NTT-friendly primes below 2^limb_bits, then t
   {
     uint64_t top = (desc->limb_bits == 64) ? ~0ull : (1ull << desc->limb_bits) - 1;
@@ -834,15 +901,24 @@ int encode_clusters(wally_ctx* c, const void* emb, int elem, uint64_t n_entries,
   for (uint32_t i = 0; i < k; ++i)
     if (offsets[i + 1] <= offsets[i]) return set_err(c, WALLY_EINVAL, "cluster %u is empty or offsets decrease", i);
   ChunkLayout lay;
-  plan_layout(c->layout, offsets, k, c->n, lay);
+  plan_layout(c->layout, offsets, k, c->n, c->d_pad, c->fold_max, lay);
   const uint64_t total = lay.segs.size();
+  // plaintexts per chunk: d_pad / fold of the chunk's cluster
+  std::vector<uint32_t> chunk_fold(total, 1);
+  for (uint32_t cl = 0; cl < k; ++cl)
+    for (uint32_t j = 0; j < lay.chunks[cl]; ++j) chunk_fold[lay.first[cl] + j] = lay.fold[cl];
+  std::vector<uint64_t> chunk_pt(total);
+  uint64_t pt_words = 0;
+  for (uint64_t ch = 0; ch < total; ++ch) {
+    chunk_pt[ch] = pt_words;
+    pt_words += c->ptw() / chunk_fold[ch];
+  }
   // drop the previous index and workspaces, then allocate the new one
   free_sets(c);
   dfree(c, c->pt);
   c->pt = nullptr;
   c->K = 0;
-  const uint64_t ptw = c->ptw();
-  if ((rc = dalloc(c, total * ptw * 8, (void**)&c->pt))) return rc;
+  if ((rc = dalloc(c, pt_words * 8, (void**)&c->pt))) return rc;
   // rows in chunk order: a chunk's entries are consecutive rows from slot 0
   // (a copy only where clusters share chunks)
   const uint64_t row_bytes = (uint64_t)c->d * elem;
@@ -871,12 +947,12 @@ int encode_clusters(wally_ctx* c, const void* emb, int elem, uint64_t n_entries,
   for (uint64_t ch = 0; ch < total; ++ch) {
     uint64_t cnt = 0;
     for (const auto& sg : lay.segs[ch]) cnt += sg.count;
-    jobs[ch] = EncodeJob{demb + row * row_bytes, cnt, c->pt + ch * ptw};
+    jobs[ch] = EncodeJob{demb + row * row_bytes, cnt, c->pt + chunk_pt[ch], chunk_fold[ch], fold_cls(c, chunk_fold[ch]).g};
     row += cnt;
   }
   hipError_t e = hipMemcpy(demb, src, n_entries * row_bytes, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(djobs, jobs.data(), total * sizeof(EncodeJob), hipMemcpyHostToDevice);
-  EncodeArgs a{c->log_n, c->L, (uint32_t)c->d, (uint32_t)c->d_pad, (uint32_t)c->g, elem == 2 ? 1u : 0u, c->slot_of};
+  EncodeArgs a{c->log_n, c->L, (uint32_t)c->d, (uint32_t)c->d_pad, elem == 2 ? 1u : 0u, c->slot_of};
   const uint64_t step = 4096;
   for (uint64_t j0 = 0; e == hipSuccess && j0 < total; j0 += step)
     e = launch_encode(djobs + j0, (int)std::min(step, total - j0), a, c->M, nullptr);
@@ -888,6 +964,8 @@ int encode_clusters(wally_ctx* c, const void* emb, int elem, uint64_t n_entries,
   c->chunks = std::move(lay.chunks);
   c->chunk_base = std::move(lay.first);
   c->slot_base = std::move(lay.base);
+  c->fold = std::move(lay.fold);
+  c->chunk_pt = std::move(chunk_pt);
   c->max_chunks = *std::max_element(c->chunks.begin(), c->chunks.end());
   c->n_chunks_total = total;
   return WALLY_OK;
@@ -932,7 +1010,20 @@ int wally_cluster_info(const wally_ctx* c, uint32_t cl, uint32_t* n_chunks, uint
   if (!c || cl >= c->K) return WALLY_EINVAL;
   if (n_chunks) *n_chunks = c->chunks[cl];
   if (slot_base) *slot_base = c->slot_base[cl];
-  if (plaintexts) *plaintexts = c->pt + c->chunk_base[cl] * c->ptw();
+  if (plaintexts) *plaintexts = c->pt + c->chunk_pt[c->chunk_base[cl]];
+  return WALLY_OK;
+}
+
+int wally_cluster_fold(const wally_ctx* c, uint32_t cl, uint32_t* fold, uint32_t* g, uint32_t* h, uint64_t* gal_giant,
+                       uint64_t* gal_fold) {
+  if (!c || cl >= c->K) return WALLY_EINVAL;
+  const FoldCls fc = fold_cls(c, c->fold[cl]);
+  if (fold) *fold = fc.B;
+  if (g) *g = fc.g;
+  if (h) *h = fc.h;
+  if (gal_giant) *gal_giant = fc.gal_giant;
+  if (gal_fold)
+    for (uint32_t f = 0; (1u << f) < fc.B; ++f) gal_fold[f] = c->gal_fold[f];
   return WALLY_OK;
 }
 
@@ -952,15 +1043,20 @@ void make_waves(wally_ctx* c, const wally_query* q, uint64_t nq, int path, std::
                 std::vector<std::pair<uint64_t, uint64_t>>& waves) {
   ord.resize(nq);
   for (uint64_t i = 0; i < nq; ++i) ord[i] = &q[i];
-  // by first chunk, then cluster: clusters that share a chunk land in the same waves and tiles
+  // by fold class (a wave runs one baby/giant split), then first chunk, then
+  // cluster: clusters that share a chunk land in the same waves and tiles
   const std::vector<uint64_t>& fc = c->chunk_base;
-  std::stable_sort(ord.begin(), ord.end(), [&fc](const wally_query* a, const wally_query* b) {
+  const std::vector<uint32_t>& fo = c->fold;
+  std::stable_sort(ord.begin(), ord.end(), [&fc, &fo](const wally_query* a, const wally_query* b) {
+    if (fo[a->cluster] != fo[b->cluster]) return fo[a->cluster] < fo[b->cluster];
     return fc[a->cluster] != fc[b->cluster] ? fc[a->cluster] < fc[b->cluster] : a->cluster < b->cluster;
   });
   waves.clear();
   for (uint64_t i = 0; i < nq;) {
     uint64_t j = i;
-    while (j < nq && j - i < (uint64_t)c->B && (path != WALLY_PATH_PLAIN || ord[j]->cluster == ord[i]->cluster)) ++j;
+    while (j < nq && j - i < (uint64_t)c->B && fo[ord[j]->cluster] == fo[ord[i]->cluster] &&
+           (path != WALLY_PATH_PLAIN || ord[j]->cluster == ord[i]->cluster))
+      ++j;
     waves.push_back({i, j});
     i = j;
   }
@@ -1192,9 +1288,15 @@ int serve_pump(wally_ctx* c) {
     if (!s.busy && !c->pending.empty()) {
       std::vector<const wally_query*> qs;
       std::vector<ServeReq> taken;
-      while (!c->pending.empty() && (int)taken.size() < c->B) {
-        taken.push_back(c->pending.front());
-        c->pending.pop_front();
+      // the oldest request's fold class, then the later requests of that class in order
+      const uint32_t cls = c->fold[c->pending.front().q.cluster];
+      for (auto it = c->pending.begin(); it != c->pending.end() && (int)taken.size() < c->B;) {
+        if (c->fold[it->q.cluster] == cls) {
+          taken.push_back(*it);
+          it = c->pending.erase(it);
+        } else {
+          ++it;
+        }
       }
       for (auto& r : taken) qs.push_back(&r.q);
       if ((rc = enqueue_wave(c, s, qs.data(), (int)qs.size()))) return rc;
@@ -1324,7 +1426,7 @@ int wally_diag_rotate(wally_ctx* c, const uint64_t* in, const uint64_t* keys, ui
     HIP_OK(c, hipStreamSynchronize(s.stream));
     for (int k = 0; k < w; ++k)
       s.baby_host[k] = KsItem{keys + (i0 + k) * c->keyw(), const_cast<uint64_t*>(in) + (i0 + k) * ctw,
-                              out + (i0 + k) * ctw, nullptr, nullptr, nullptr, nullptr};
+                              out + (i0 + k) * ctw, nullptr, nullptr, nullptr, nullptr, nullptr};
     HIP_OK(c, hipMemcpyAsync(s.baby_dev, s.baby_host, w * sizeof(KsItem), hipMemcpyHostToDevice, st));
     KsArgs a = base_args(c, s);
     a.gal = which ? c->gal_giant : c->gal_baby;

@@ -36,6 +36,7 @@ struct KsItem {
   const uint64_t* pt;    // plaintexts of the chunk [d_pad][L][n] (giant steps)
   const uint64_t* ctp;   // rotated query copies [g][2][L][n] (giant steps)
   uint64_t* acc;         // giant-step sums [h][2][L][n] (giant steps); sel 3 reads it
+  const uint64_t* key_fold;  // fold keys [log2 B][L][2][L+1][n] (folded layout)
 };
 
 // A tile of giant items that share one plaintext chunk (consecutive items).
@@ -49,6 +50,9 @@ struct KsArgs {
   int in_sel, out_sel;
   uint64_t in_off, out_off;
   int giant;   // giant-step index i to fuse acc_i, or -1
+  int add_in;  // 1: add the (unpermuted) input to the output (fold step R + Rot(R))
+  int key_fold;     // 1: key = item.key_fold + key_off (a fold step), else item.key
+  uint64_t key_off;
   int g;
   uint64_t* X;  // scratch [items][L][n]
   uint64_t* U;  // scratch [items][2][L+1][n]: key inner products (m = L: the P part)
@@ -63,13 +67,14 @@ struct CopyItem {
 
 struct EncodeJob {
   const void* emb;      // first entry of the chunk, row-major [.][d], int8 or int16 (EncodeArgs::wide)
-  uint64_t n_entries;   // entries of the cluster in this chunk (<= n)
-  uint64_t* out;        // [d_pad][L][n]
+  uint64_t n_entries;   // entries of the cluster in this chunk (<= n / fold)
+  uint64_t* out;        // [d_pad / fold][L][n]
+  uint32_t fold, g;     // fold factor and baby steps of the chunk's cluster (1 and the context's g unless folded)
 };
 
 struct EncodeArgs {
   int log_n, L;
-  uint32_t d, d_pad, g;
+  uint32_t d, d_pad;
   uint32_t wide;            // entries are int16 (else int8)
   const uint32_t* slot_of;  // NTT index -> slot
 };

@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void k_ks_inner(const KsItem* __restrict__ ite
   const int m = blockIdx.y, b = blockIdx.z;
   const uint64_t n = 1ull << a.log_n;
   const uint64_t p = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 2;
-  WALLY_GLOBAL const uint64_t* key = gmem(items[b].key);
+  WALLY_GLOBAL const uint64_t* key = a.key_fold ? gmem(items[b].key_fold) + a.key_off : gmem(items[b].key);
   const uint64_t* D = a.D + ((uint64_t)b * MM + m) * L * n + p;
   const ModConst mc = M.mc[m];
   // all 3L loads of a thread are issued before the first product (L is a
@@ -278,6 +278,15 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_wa
   }
   if (t == 0) add_galois<LOGN, LOGE, LM>(z, sel_in(items + b, a.in_sel, a.in_off) + (uint64_t)j * S::N, lds, a.gal, q, tid);
   const uint64_t toff = ((uint64_t)t * L + j) * S::N;
+  if (a.add_in) {  // fold step: + the input itself, unpermuted (R + Rot(R))
+    WALLY_GLOBAL const uint64_t* r = sel_in(items + b, a.in_sel, a.in_off) + toff;
+#pragma unroll
+    for (int c = 0; c < S::E / 2; ++c) {
+      const u64x2 v = *(WALLY_GLOBAL const u64x2*)(r + LM::idx(tid, 2 * c));
+      z[2 * c] = addmod(z[2 * c], v.x, q);
+      z[2 * c + 1] = addmod(z[2 * c + 1], v.y, q);
+    }
+  }
   if (a.giant >= 0) {  // Horner step: + acc_i
     WALLY_GLOBAL const uint64_t* acc = gmem(items[b].acc) + (uint64_t)a.giant * 2 * L * S::N + toff;
 #pragma unroll
@@ -385,6 +394,10 @@ __global__ __launch_bounds__(256) void k_copy_ct(const CopyItem* __restrict__ it
 //   slot s of the chunk belongs to entry base + s; diagonal m holds coordinate
 //   ((s mod d_pad) + m) mod d_pad of that entry (0 past the cluster or past d);
 //   plaintext g*i + j is that diagonal rotated right by g*i within each row;
+//   with a fold factor B (folded layout, not in the paper) the chunk has
+//   D = d_pad / B diagonals and slot s = W d_pad + u (window W, u < d_pad)
+//   belongs to entry W D + (u mod D), so an entry spreads its coordinates
+//   over B slots (B = 1 is the paper's layout);
 //   slots -> polynomial mod t (inverse NTT mod t after placing slot s at the
 //   NTT index holding it); centred lift; NTT in every ciphertext limb.
 // grid (jobs, d_pad); block T
@@ -398,7 +411,9 @@ __global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_encode(const EncodeJ
   const uint32_t m = blockIdx.y;
   const uint32_t half = S::N / 2;
   const uint32_t dp = a.d_pad, d = a.d;
-  const uint32_t rot = (a.g * (m / a.g)) % half;
+  const uint32_t nd = a.d_pad / jb.fold;  // diagonals of this chunk
+  if (m >= nd) return;                     // whole block, before any barrier
+  const uint32_t rot = (jb.g * (m / jb.g)) % half;
   const int it = a.L + 1;  // index of t in the modulus tables
   const uint64_t t = M.q[it];
   uint64_t x[16];
@@ -408,8 +423,9 @@ __global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_encode(const EncodeJ
     const uint32_t s = a.slot_of[pos];  // slot whose value sits at NTT index pos
     const uint32_t row = s / half, c = s % half;
     const uint32_t s2 = row * half + (c + half - rot) % half;  // pre-rotation (right by g*i)
-    const uint64_t entry = s2;
-    const uint32_t coord = ((s2 % dp) + m) % dp;
+    const uint32_t u = s2 % dp;
+    const uint64_t entry = (uint64_t)(s2 / dp) * nd + u % nd;
+    const uint32_t coord = (u + m) % dp;
     int v = 0;
     if (entry < jb.n_entries && coord < d)
       v = a.wide ? gmem((const int16_t*)jb.emb)[entry * d + coord] : gmem((const int8_t*)jb.emb)[entry * d + coord];
@@ -633,6 +649,7 @@ hipError_t launch_mac_tiles(const KsItem* items, const MacTile* tiles, int n_til
   if (n_tiles <= 0) return hipSuccess;
   const dim3 grid((1u << a.log_n) / 64, a.L, n_tiles);
   switch (a.g) {
+    case 2: hipLaunchKernelGGL((k_mac_tiles<2, 2>), grid, dim3(256), 0, st, items, tiles, a, h, M); break;
     case 4: hipLaunchKernelGGL((k_mac_tiles<4, 2>), grid, dim3(256), 0, st, items, tiles, a, h, M); break;
     case 8: hipLaunchKernelGGL((k_mac_tiles<8, 2>), grid, dim3(256), 0, st, items, tiles, a, h, M); break;
     case 16: hipLaunchKernelGGL((k_mac_tiles<16, 2>), grid, dim3(256), 0, st, items, tiles, a, h, M); break;

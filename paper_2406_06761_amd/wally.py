@@ -17,10 +17,10 @@ LIB_PATH = HERE / "libwally.so"
 
 OK, EINVAL, ENOMEM, EAGAIN, EPENDING, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 PATH_BATCHED, PATH_PLAIN, PATH_GRAPH = 0, 1, 2
-LAYOUT_PER_CLUSTER, LAYOUT_COPACK = 0, 1
+LAYOUT_PER_CLUSTER, LAYOUT_COPACK, LAYOUT_FOLDED = 0, 1, 2
 
 QUERY_DTYPE = np.dtype([("cluster", "<u4"), ("reserved", "<u4"), ("ct", "<u8"), ("key_baby", "<u8"),
-                        ("key_giant", "<u8"), ("out", "<u8")])
+                        ("key_giant", "<u8"), ("out", "<u8"), ("key_fold", "<u8")])
 
 
 class WallyError(RuntimeError):
@@ -33,7 +33,7 @@ class ParamsDesc(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("num_limbs", ctypes.c_uint32), ("limb_bits", ctypes.c_uint32),
                 ("t_bits", ctypes.c_uint32), ("dim", ctypes.c_uint32), ("layout", ctypes.c_uint32),
                 ("device", ctypes.c_int32), ("max_batch", ctypes.c_uint32), ("wave_sets", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("hbm_budget", ctypes.c_uint64)]
+                ("fold_max", ctypes.c_uint32), ("hbm_budget", ctypes.c_uint64)]
 
 
 class ParamsInfo(ctypes.Structure):
@@ -48,14 +48,16 @@ class ParamsInfo(ctypes.Structure):
 
 class Query(ctypes.Structure):
     _fields_ = [("cluster", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("ct", ctypes.c_void_p),
-                ("key_baby", ctypes.c_void_p), ("key_giant", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+                ("key_baby", ctypes.c_void_p), ("key_giant", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("key_fold", ctypes.c_void_p)]
 
 
 assert ctypes.sizeof(Query) == QUERY_DTYPE.itemsize
 
 # every symbol declared in include/wally.h and include/wally_diag.h
 SYMBOLS = [
-    "wally_params_init", "wally_params_query", "wally_encode_clusters", "wally_cluster_info", "wally_score_batch",
+    "wally_params_init", "wally_params_query", "wally_encode_clusters", "wally_cluster_info", "wally_cluster_fold",
+    "wally_score_batch",
     "wally_tune", "wally_compress_responses", "wally_encode_clusters_i16",
     "wally_serve_start", "wally_serve_submit", "wally_serve_poll", "wally_serve_stop", "wally_strerror",
     "wally_last_error", "wally_destroy", "wally_diag_ntt", "wally_diag_rotate", "wally_diag_kernel_timing",
@@ -95,6 +97,8 @@ def load():
         "wally_encode_clusters": ([vp, vp, u64, vp, u32], i32),
         "wally_encode_clusters_i16": ([vp, vp, u64, vp, u32], i32),
         "wally_cluster_info": ([vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(vp)], i32),
+        "wally_cluster_fold": ([vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32),
+                                ctypes.POINTER(u64), ctypes.POINTER(u64)], i32),
         "wally_score_batch": ([vp, vp, u64, i32, vp], i32),
         "wally_compress_responses": ([vp, vp, u64, vp, vp], i32),
         "wally_tune": ([vp, vp, u64, vp, vp, vp, ctypes.POINTER(TuneEntry), u32, ctypes.POINTER(u32)], i32),
@@ -134,9 +138,10 @@ class Context:
     """One parameter set on one device (wally_params_init ... wally_destroy)."""
 
     def __init__(self, log_n, num_limbs, limb_bits, t_bits, dim, device=0, max_batch=0, hbm_budget=0, wave_sets=0,
-                 layout=LAYOUT_PER_CLUSTER):
+                 layout=LAYOUT_PER_CLUSTER, fold_max=0):
         self.lib = load()
-        d = ParamsDesc(log_n, num_limbs, limb_bits, t_bits, dim, layout, device, max_batch, wave_sets, 0, hbm_budget)
+        d = ParamsDesc(log_n, num_limbs, limb_bits, t_bits, dim, layout, device, max_batch, wave_sets, fold_max,
+                       hbm_budget)
         h = ctypes.c_void_p()
         rc = self.lib.wally_params_init(ctypes.byref(d), ctypes.byref(h))
         if rc:
@@ -189,6 +194,15 @@ class Context:
                     "wally_cluster_info")
         return n.value, p.value, b.value
 
+    def cluster_fold(self, c):
+        """(fold, g, h, giant Galois element, [fold Galois elements]) of cluster c."""
+        f, g, h = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        gg = ctypes.c_uint64()
+        gf = (ctypes.c_uint64 * 8)()
+        self._check(self.lib.wally_cluster_fold(self.h, c, ctypes.byref(f), ctypes.byref(g), ctypes.byref(h),
+                                                ctypes.byref(gg), gf), "wally_cluster_fold")
+        return f.value, g.value, h.value, gg.value, [gf[k] for k in range(f.value.bit_length() - 1)]
+
     def compress_responses(self, responses, out, stream=None):
         """responses: device tensor of [chunks][2][L][n] words; out: device
         uint8 tensor of chunks * info.compressed_chunk_bytes bytes."""
@@ -224,9 +238,9 @@ class Context:
     def serve_start(self, stream=None):
         self._check(self.lib.wally_serve_start(self.h, _stream_handle(stream)), "wally_serve_start")
 
-    def serve_submit(self, cluster, ct, key_baby, key_giant, out):
+    def serve_submit(self, cluster, ct, key_baby, key_giant, out, key_fold=None):
         """Returns a ticket, or None when admission refused (EAGAIN)."""
-        q = Query(cluster, 0, ct, key_baby, key_giant, out)
+        q = Query(cluster, 0, ct, key_baby, key_giant, out, key_fold)
         t = ctypes.c_uint64()
         rc = self.lib.wally_serve_submit(self.h, ctypes.byref(q), ctypes.byref(t))
         if rc == EAGAIN:
@@ -285,7 +299,7 @@ def to_host(t) -> np.ndarray:
     return t.detach().cpu().numpy().view(np.uint64)
 
 
-def query_array(clusters, cts, keys_baby, keys_giant, outs) -> np.ndarray:
+def query_array(clusters, cts, keys_baby, keys_giant, outs, keys_fold=None) -> np.ndarray:
     """Build the wally_query array from per-query cluster ids and device pointers."""
     q = np.zeros(len(clusters), dtype=QUERY_DTYPE)
     q["cluster"] = clusters
@@ -293,4 +307,6 @@ def query_array(clusters, cts, keys_baby, keys_giant, outs) -> np.ndarray:
     q["key_baby"] = keys_baby
     q["key_giant"] = keys_giant
     q["out"] = outs
+    if keys_fold is not None:
+        q["key_fold"] = keys_fold
     return q

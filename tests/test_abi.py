@@ -33,9 +33,9 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     from paper_2406_06761_amd import wally
 
-    # wally_query: two uint32 then four pointers
-    assert ctypes.sizeof(wally.Query) == 40
-    assert wally.Query.ct.offset == 8 and wally.Query.out.offset == 32
+    # wally_query: two uint32 then five pointers
+    assert ctypes.sizeof(wally.Query) == 48
+    assert wally.Query.ct.offset == 8 and wally.Query.out.offset == 32 and wally.Query.key_fold.offset == 40
     # wally_params_desc: 10 x 32-bit fields then the 64-bit budget
     assert ctypes.sizeof(wally.ParamsDesc) == 48 and wally.ParamsDesc.hbm_budget.offset == 40
     assert wally.ParamsInfo.q.offset == 24
@@ -56,6 +56,10 @@ def test_error_strings_and_null_handling():
     d = wally.ParamsDesc(12, 3, 36, 20, 4096, 0, 0, 0, 0, 0, 0)  # d_pad does not divide n/2
     assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL
     d = wally.ParamsDesc(12, 3, 36, 20, 64, 0, 0, 32769, 0, 0, 0)  # wave beyond the grid limits
+    assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL
+    d = wally.ParamsDesc(12, 3, 36, 20, 64, 0, 0, 0, 0, 8, 0)  # fold_max outside the folded layout
+    assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL
+    d = wally.ParamsDesc(12, 3, 36, 20, 64, wally.LAYOUT_FOLDED, 0, 0, 0, 12, 0)  # not a power of two
     assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL
 
 
