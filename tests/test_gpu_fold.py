@@ -174,3 +174,106 @@ def test_folded_query_without_fold_keys_is_rejected(work):
             c.score_batch(q)
     finally:
         c.close()
+
+
+def test_paper_scale_folded_sampled_parity():
+    """The paper-scale index (3.2M x 192, 1,800 clusters) in the folded layout
+    and its whole 53,710-query batch, in the benchmark's launch configuration
+    (default wave size and streams, fold_max 16).  Pool packets of uniform
+    residues for most queries; for each fold class its hottest cluster's first
+    real query carries a real encryption, and so does the first fake (Enc(0));
+    those responses and two pool-packet responses are compared word for word
+    with the oracle, and the real ones decrypt to the int64 dot products."""
+    from paper_2406_06761_amd.wally import PATH_BATCHED, query_array, to_device, to_host
+
+    p = preset("paper")
+    o = Oracle(p)
+    n, L = p.n, p.L
+    w = synth.paper_workload()
+    emb = synth.embeddings_parallel(w.n_entries, w.dim, norm=w.norm, threads=16)
+    offs = synth.offsets(w.sizes)
+    shapes = [fold.shape(p, fold.fold_factor(int(s), n, p.d_pad)) for s in w.sizes]
+    c = _ctx_paper()
+    try:
+        c.encode_clusters(emb, offs)
+        for k in range(0, len(w.sizes), 37):
+            fs = shapes[k]
+            assert c.cluster_fold(k) == (fs.B, fs.g, fs.h, fs.gal_giant, list(fs.gal_fold)), k
+            assert c.cluster_info(k)[0] == fold.n_chunks(int(w.sizes[k]), fs), k
+        nq = len(w.targets)
+        q_chunks = np.array([fold.n_chunks(int(w.sizes[t]), shapes[t]) for t in w.targets], dtype=np.int64)
+        ctw = 2 * L * n
+        out_off = np.zeros(nq, dtype=np.int64)
+        out_off[1:] = np.cumsum(q_chunks)[:-1]
+        outs = torch.zeros(int(q_chunks.sum()) * ctw, dtype=torch.int64, device="cuda")
+        pool = 2048
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(synth.SEED_CRYPTO)
+        cts = synth.uniform_residues(gen, (pool, 2), p.q, n, device="cuda")
+        kbs = synth.uniform_residues(gen, (pool, L, 2), p.moduli, n, device="cuda")
+        kgs = synth.uniform_residues(gen, (pool, L, 2), p.moduli, n, device="cuda")
+        kfs = synth.uniform_residues(gen, (pool, 4 * L, 2), p.moduli, n, device="cuda")
+        pidx = np.arange(nq) % pool
+        ptr = [t.data_ptr() + pidx * t[0].numel() * 8 for t in (cts, kbs, kgs, kfs)]
+        real = w.targets[: w.n_real]
+        counts = np.bincount(real, minlength=len(w.sizes))
+        folds = np.array([fs.B for fs in shapes])
+        picks = []
+        for B in sorted(set(folds[real].tolist())):
+            hot = int(np.argmax(np.where(folds == B, counts, -1)))
+            picks.append(int(np.nonzero(real == hot)[0][0]))
+        picks.append(w.n_real)  # the first fake
+        rng = np.random.default_rng(synth.SEED_CRYPTO + 21)
+        keep = []
+        for i in picks:
+            t = int(w.targets[i])
+            fs = shapes[t]
+            vec = (synth.embeddings(1, w.dim, seed=synth.SEED_QUERIES, norm=w.norm, row_start=i)[0]
+                   if i < w.n_real else np.zeros(w.dim, dtype=np.int8))
+            s = o.secret_key(rng)
+            ct = o.encrypt(s, o.query_slots(vec), rng)
+            kb = o.galois_key(s, p.gal_baby, rng)
+            kg, kf = fold.make_keys(o, s, fs, rng)
+            dev = [to_device(a) for a in (ct, kb, kg, kf if len(kf) else np.zeros(1, dtype=np.uint64))]
+            keep.append((i, t, vec, s, (ct, kb, kg, kf), dev))
+            for a, d in zip(ptr, dev):
+                a[i] = d.data_ptr()
+        q = query_array(w.targets, *ptr[:3], outs.data_ptr() + out_off * ctw * 8, ptr[3])
+        print(f"folded paper index: scoring {nq} queries", flush=True)
+        c.score_batch(q, path=PATH_BATCHED)
+        torch.cuda.synchronize()
+        print("folded paper index: scored", flush=True)
+        jobs, metas = [], []
+        for i, t, vec, s, pk, _ in keep:
+            jobs.append((pk, t))
+            metas.append((i, t, vec, s))
+        for i in (1, nq - 1):
+            t = int(w.targets[i])
+            pi = i % pool
+            nf = shapes[t].B.bit_length() - 1
+            pk = (to_host(cts[pi]).reshape(2, L, n), to_host(kbs[pi]).reshape(L, 2, L + 1, n),
+                  to_host(kgs[pi]).reshape(L, 2, L + 1, n), to_host(kfs[pi]).reshape(4, L, 2, L + 1, n)[:nf])
+            jobs.append((pk, t))
+            metas.append((i, t, None, None))
+        rows = {t: emb[int(offs[t]) : int(offs[t + 1])] for _, t in jobs}
+        with ThreadPoolExecutor(8) as ex:
+            refs = list(ex.map(lambda j: fold.score(o, *j[0], fold.encode_cluster(o, rows[j[1]], shapes[j[1]]),
+                                                    shapes[j[1]]), jobs))
+        half_t = (p.t - 1) // 2
+        for (i, t, vec, s), ref in zip(metas, refs):
+            got = to_host(outs[out_off[i] * ctw : (out_off[i] + q_chunks[i]) * ctw]).reshape(ref.shape)
+            assert (got == ref).all(), (i, t, shapes[t].B)
+            if vec is None:
+                continue
+            dec = np.stack([o.decrypt(s, r).astype(np.int64) for r in got])
+            sc = fold.scores_of(dec, len(rows[t]), shapes[t], p.d_pad)
+            sc = np.where(sc > half_t, sc - p.t, sc)
+            assert (sc == rows[t].astype(np.int64) @ vec.astype(np.int64)).all(), (i, t, shapes[t].B)
+    finally:
+        c.close()
+
+
+def _ctx_paper():
+    from paper_2406_06761_amd.wally import LAYOUT_FOLDED, Context
+
+    return Context.preset("paper", layout=LAYOUT_FOLDED, fold_max=16)
