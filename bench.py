@@ -135,7 +135,7 @@ def cpu_baseline(workload, sample, threads, params_name):
             "sample": f"{sample} seeded queries of the batch ({scores} scores), {dt:.1f} s wall"}
 
 
-def serve_rates(ctx, w, chunks, cts, kbs, kgs, pool, rates, duration, log_every=1.0):
+def serve_rates(ctx, w, chunks, cts, kbs, kgs, pool, rates, duration, log_every=1.0, kfs=None):
     """Serving through wally_serve_*: Poisson arrivals at each rate; a query is
     submitted when it arrives (retried while admission refuses it), latency is
     arrival -> the poll that reports it done."""
@@ -173,7 +173,8 @@ def serve_rates(ctx, w, chunks, cts, kbs, kgs, pool, rates, duration, log_every=
                 q = int(picks[k])
                 pi = q % pool
                 c = int(w.targets[q])
-                t = ctx.serve_submit(c, cts[pi].data_ptr(), kbs[pi].data_ptr(), kgs[pi].data_ptr(), outs[slot].data_ptr())
+                t = ctx.serve_submit(c, cts[pi].data_ptr(), kbs[pi].data_ptr(), kgs[pi].data_ptr(), outs[slot].data_ptr(),
+                                     kfs[pi].data_ptr() if kfs is not None else None)
                 if t is None:
                     refused += 1
                     deferred.add(k)
@@ -283,29 +284,39 @@ def crt_bench(args):
 
 
 def fold_bench(args):
-    """Folded small-cluster layout (not in the paper): the paper-scale workload
-    scored with the per-cluster layout and then with the folded one (clusters
-    of at most n/B entries spread each entry over B slots and score d_pad/B
+    """Folded small-cluster layout (not in the paper): the workload scored with
+    the paper's per-cluster layout (co-packed for the large index, whose
+    per-cluster layout does not fit) and then with the folded one (clusters of
+    at most n/B entries spread each entry over B slots and score d_pad/B
     diagonals, plus log2 B rotate-and-add steps), same queries, same packet
     pool (uniform residues; each packet also carries the fold keys).  The value
-    is the folded layout's scores per second; the per-cluster layout's is
-    reported beside it."""
+    is the folded layout's scores per second; the other layout's is reported
+    beside it."""
     import torch
 
     from paper_2406_06761_amd import synth
-    from paper_2406_06761_amd.wally import LAYOUT_FOLDED, LAYOUT_PER_CLUSTER, PATH_BATCHED, Context, query_array
+    from paper_2406_06761_amd.wally import (LAYOUT_COPACK, LAYOUT_FOLDED, LAYOUT_PER_CLUSTER, PATH_BATCHED, Context,
+                                            query_array)
 
     torch.cuda.set_device(0)
-    w = synth.paper_workload(n_real=args.real or 50_000)
+    if args.workload == "large":
+        w = synth.paper_workload(n_real=args.real or 1_000_000, entries=8_000_000, k=4000, dim=384, sigma=1.0,
+                                 name="large")
+        preset_name, base = "large", ("copack", LAYOUT_COPACK)
+        desc = f"8M x 384 int8, 4000 lognormal(1.0) clusters, {w.n_real // 1000}k Zipf(1.1) queries + NB(2,0.5) fakes"
+    else:
+        w = synth.paper_workload(n_real=args.real or 50_000)
+        preset_name, base = "paper", ("per_cluster", LAYOUT_PER_CLUSTER)
+        desc = f"3.2M x 192 int8, 1800 lognormal(0.8) clusters, {w.n_real // 1000}k Zipf(1.1) queries + NB(2,0.5) fakes"
     log(f"generating {w.n_entries} x {w.dim} int8 entries")
     emb = synth.embeddings_parallel(w.n_entries, w.dim, norm=w.norm, threads=16)
     offs = synth.offsets(w.sizes)
     nq = len(w.targets)
     scores = int(w.sizes[w.targets].sum())
     pool_t, legs = None, {}
-    for name, layout in (("per_cluster", LAYOUT_PER_CLUSTER), ("folded", LAYOUT_FOLDED)):
+    for name, layout in (base, ("folded", LAYOUT_FOLDED)):
         kw = {"fold_max": args.fold_max} if layout == LAYOUT_FOLDED else {}
-        ctx = Context.preset("paper", max_batch=args.max_batch, wave_sets=args.wave_sets, layout=layout, **kw)
+        ctx = Context.preset(preset_name, max_batch=args.max_batch, wave_sets=args.wave_sets, layout=layout, **kw)
         info = ctx.info
         n, L = info.n, info.L
         t0 = time.perf_counter()
@@ -332,18 +343,25 @@ def fold_bench(args):
         ctw = int(info.ct_words)
         out_off = np.zeros(nq, dtype=np.int64)
         out_off[1:] = np.cumsum(q_chunks)[:-1]
-        outs = torch.empty(int(q_chunks.sum()) * ctw, dtype=torch.int64, device="cuda")
+        if int(q_chunks.sum()) * ctw * 8 > 64 << 30:  # responses beyond 64 GiB share a ring of chunk slots
+            ring = 16384
+            out_off = out_off % (ring - int(chunks.max()))
+            outs = torch.empty(ring * ctw, dtype=torch.int64, device="cuda")
+        else:
+            outs = torch.empty(int(q_chunks.sum()) * ctw, dtype=torch.int64, device="cuda")
         pidx = np.arange(nq) % pool
         q = query_array(w.targets, cts.data_ptr() + pidx * cts[0].numel() * 8,
                         kbs.data_ptr() + pidx * kbs[0].numel() * 8, kgs.data_ptr() + pidx * kgs[0].numel() * 8,
                         outs.data_ptr() + out_off * ctw * 8, kfs.data_ptr() + pidx * kfs[0].numel() * 8)
         for i in range(args.warmup):
             ctx.score_batch(q, path=PATH_BATCHED)
-        torch.cuda.synchronize()
+            torch.cuda.synchronize()
+            log(f"{name}: warm-up step done")
         t0 = time.perf_counter()
         for i in range(args.steps):
             ctx.score_batch(q, path=PATH_BATCHED)
-        torch.cuda.synchronize()
+            torch.cuda.synchronize()
+            log(f"{name}: step {i} done")
         ms = (time.perf_counter() - t0) / args.steps * 1e3
         qf = folds[w.targets]
         hist = {int(b): int((qf == b).sum()) for b in np.unique(qf)}
@@ -351,7 +369,7 @@ def fold_bench(args):
         ks = 0
         for b, cnt in hist.items():
             D = info.d_pad // b
-            g = 1 << ((D.bit_length() - 1 + 1) // 2)
+            g = 1 << (D.bit_length() // 2)  # 2^ceil(log2(D) / 2)
             h = D // g
             sel = qf == b
             ks += cnt * (g - 1) + int(q_chunks[sel].sum()) * (h - 1 + (b.bit_length() - 1))
@@ -363,15 +381,14 @@ def fold_bench(args):
         del outs
         ctx.close()
         torch.cuda.empty_cache()
-    f, pc = legs["folded"], legs["per_cluster"]
+    f, pc = legs["folded"], legs[base[0]]
     line = {"metric": "encrypted query-entry scores/sec (batched path, folded small-cluster layout)",
             "value": f["scores_per_s"], "unit": "scores/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": f["ms_per_step"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-            "config": {"workload": f"3.2M x 192 int8, 1800 lognormal(0.8) clusters, {w.n_real // 1000}k Zipf(1.1) "
-                                   f"queries + NB(2,0.5) fakes", "layout": "folded", "fold_max": args.fold_max,
+            "config": {"workload": desc, "layout": "folded", "fold_max": args.fold_max,
                        "queries": nq, "scores_per_step": scores},
-            "speedup_vs_per_cluster_layout": pc["ms_per_step"] / f["ms_per_step"], "legs": legs}
+            f"speedup_vs_{base[0]}_layout": pc["ms_per_step"] / f["ms_per_step"], "legs": legs}
     print(json.dumps(line), flush=True)
 
 
@@ -405,6 +422,10 @@ def main():
                     help="paper workload with the folded small-cluster layout (not in the paper), "
                          "next to the per-cluster layout")
     ap.add_argument("--fold-max", type=int, default=16, help="largest fold factor of the folded layout")
+    ap.add_argument("--fold-steps", type=int, default=2,
+                    help="timed steps of the folded layout after the paper layout's legs (0 = skip)")
+    ap.add_argument("--fold-serve-rates", default="20000",
+                    help="Poisson rates (QPS) served on the folded layout when serving is measured ('' = skip)")
     args = ap.parse_args()
     if args.serve_rates is None:
         args.serve_rates = "5000,20000,50000" if args.workload == "paper" else ""
@@ -670,6 +691,52 @@ def main():
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         serving = serve_rates(ctx, w, chunks, cts, kbs, kgs, pool, rates, args.serve_seconds)
 
+    # Folded small-cluster layout (not in the paper) on the same batch: the
+    # per-cluster index is dropped first, the folded one encoded, and the same
+    # queries (plus fold keys from the pool) scored on the batched path.
+    folded = None
+    if args.workload == "paper" and args.fold_steps > 0:
+        from paper_2406_06761_amd.wally import LAYOUT_FOLDED
+
+        ctx.close()
+        torch.cuda.empty_cache()
+        fctx = Context.preset(preset_name, max_batch=args.max_batch, wave_sets=args.wave_sets, layout=LAYOUT_FOLDED,
+                              fold_max=args.fold_max)
+        emb = synth.embeddings_parallel(w.n_entries, w.dim, norm=w.norm, threads=16)
+        t0 = time.perf_counter()
+        fctx.encode_clusters(emb, synth.offsets(w.sizes))
+        torch.cuda.synchronize()
+        f_enc = time.perf_counter() - t0
+        del emb
+        n_keys = max(1, args.fold_max.bit_length() - 1)
+        kfs = synth.uniform_residues(gen, (pool, n_keys * L, 2), mods, n, device="cuda")
+        qf = q.copy()
+        qf["key_fold"] = kfs.data_ptr() + pidx * kfs[0].numel() * 8
+        # a folded query never has more chunks than in the per-cluster layout: the response slots are reused
+        assert all(fctx.cluster_info(c)[0] <= chunks[c] for c in range(len(w.sizes)))
+        fctx.score_batch(qf, path=PATH_BATCHED)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.fold_steps):
+            fctx.score_batch(qf, path=PATH_BATCHED)
+        torch.cuda.synchronize()
+        fdt = time.perf_counter() - t0
+        folds = np.array([fctx.cluster_fold(c)[0] for c in range(len(w.sizes))])
+        f_serving = None
+        if args.serve_rates and args.fold_serve_rates:
+            f_chunks = np.array([fctx.cluster_info(c)[0] for c in range(len(w.sizes))], dtype=np.int64)
+            f_serving = serve_rates(fctx, w, f_chunks, cts, kbs, kgs, pool,
+                                    [float(x) for x in args.fold_serve_rates.split(",") if x], args.serve_seconds,
+                                    kfs=kfs)
+        folded = {"serving": f_serving, "scores_per_s": scores * args.fold_steps / fdt, "ms_per_step": fdt / args.fold_steps * 1e3,
+                  "speedup_vs_per_cluster_layout": (scores * args.fold_steps / fdt) / value,
+                  "index_gib": fctx.bytes_allocated / 2**30, "encode_s": f_enc, "fold_max": args.fold_max,
+                  "queries_per_fold": {int(b): int((folds[w.targets] == b).sum()) for b in np.unique(folds)}}
+        log(f"folded layout: {folded['ms_per_step']:.1f} ms/step, {folded['scores_per_s']:.4g} scores/s "
+            f"({folded['speedup_vs_per_cluster_layout']:.2f}x the per-cluster layout)")
+        fctx.close()
+        del kfs
+
     cpu = None
     if not args.no_cpu and args.cpu_sample > 0:
         threads = min(16, os.cpu_count() or 1)
@@ -708,6 +775,7 @@ def main():
         "serving": serving,
         "roofline": roofline,
         "kernels_ms": {k: v[2] for k, v in kstats.items()},
+        "folded_layout": folded,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -176,37 +176,47 @@ def test_folded_query_without_fold_keys_is_rejected(work):
         c.close()
 
 
-def test_paper_scale_folded_sampled_parity():
-    """The paper-scale index (3.2M x 192, 1,800 clusters) in the folded layout
-    and its whole 53,710-query batch, in the benchmark's launch configuration
-    (default wave size and streams, fold_max 16).  Pool packets of uniform
-    residues for most queries; for each fold class its hottest cluster's first
-    real query carries a real encryption, and so does the first fake (Enc(0));
-    those responses and two pool-packet responses are compared word for word
-    with the oracle, and the real ones decrypt to the int64 dot products."""
-    from paper_2406_06761_amd.wally import PATH_BATCHED, query_array, to_device, to_host
+def _folded_sampled_parity(pname, w, batch, pool=2048):
+    """Score logical queries `batch` of workload `w` on its folded index (the
+    benchmark's launch configuration: default wave size and streams, fold_max
+    16).  Pool packets of uniform residues for most queries; for each fold
+    class its hottest cluster's first real query carries a real encryption,
+    and so does the first fake (Enc(0)); those responses and two pool-packet
+    responses are compared word for word with the oracle, and the real ones
+    decrypt to the int64 dot products (the no-wrap bound of paper §7.3 makes
+    the centred lift the integer)."""
+    from paper_2406_06761_amd.wally import LAYOUT_FOLDED, PATH_BATCHED, Context, query_array, to_device, to_host
 
-    p = preset("paper")
+    p = preset(pname)
     o = Oracle(p)
     n, L = p.n, p.L
-    w = synth.paper_workload()
     emb = synth.embeddings_parallel(w.n_entries, w.dim, norm=w.norm, threads=16)
     offs = synth.offsets(w.sizes)
     shapes = [fold.shape(p, fold.fold_factor(int(s), n, p.d_pad)) for s in w.sizes]
-    c = _ctx_paper()
+    real = w.targets[: w.n_real]
+    counts = np.bincount(real, minlength=len(w.sizes))
+    folds = np.array([fs.B for fs in shapes])
+    picks = []
+    for B in sorted(set(folds[real].tolist())):
+        hot = int(np.argmax(np.where(folds == B, counts, -1)))
+        picks.append(int(np.nonzero(real == hot)[0][0]))
+    picks.append(w.n_real)  # the first fake
+    batch = np.array(sorted(set(int(b) for b in batch) | set(picks)), dtype=np.int64)
+    pos = {int(i): k for k, i in enumerate(batch)}
+    targets = w.targets[batch]
+    c = Context.preset(pname, layout=LAYOUT_FOLDED, fold_max=16)
     try:
         c.encode_clusters(emb, offs)
         for k in range(0, len(w.sizes), 37):
             fs = shapes[k]
             assert c.cluster_fold(k) == (fs.B, fs.g, fs.h, fs.gal_giant, list(fs.gal_fold)), k
             assert c.cluster_info(k)[0] == fold.n_chunks(int(w.sizes[k]), fs), k
-        nq = len(w.targets)
-        q_chunks = np.array([fold.n_chunks(int(w.sizes[t]), shapes[t]) for t in w.targets], dtype=np.int64)
+        nq = len(batch)
+        q_chunks = np.array([fold.n_chunks(int(w.sizes[t]), shapes[t]) for t in targets], dtype=np.int64)
         ctw = 2 * L * n
         out_off = np.zeros(nq, dtype=np.int64)
         out_off[1:] = np.cumsum(q_chunks)[:-1]
         outs = torch.zeros(int(q_chunks.sum()) * ctw, dtype=torch.int64, device="cuda")
-        pool = 2048
         gen = torch.Generator(device="cuda")
         gen.manual_seed(synth.SEED_CRYPTO)
         cts = synth.uniform_residues(gen, (pool, 2), p.q, n, device="cuda")
@@ -215,17 +225,10 @@ def test_paper_scale_folded_sampled_parity():
         kfs = synth.uniform_residues(gen, (pool, 4 * L, 2), p.moduli, n, device="cuda")
         pidx = np.arange(nq) % pool
         ptr = [t.data_ptr() + pidx * t[0].numel() * 8 for t in (cts, kbs, kgs, kfs)]
-        real = w.targets[: w.n_real]
-        counts = np.bincount(real, minlength=len(w.sizes))
-        folds = np.array([fs.B for fs in shapes])
-        picks = []
-        for B in sorted(set(folds[real].tolist())):
-            hot = int(np.argmax(np.where(folds == B, counts, -1)))
-            picks.append(int(np.nonzero(real == hot)[0][0]))
-        picks.append(w.n_real)  # the first fake
         rng = np.random.default_rng(synth.SEED_CRYPTO + 21)
         keep = []
         for i in picks:
+            k = pos[i]
             t = int(w.targets[i])
             fs = shapes[t]
             vec = (synth.embeddings(1, w.dim, seed=synth.SEED_QUERIES, norm=w.norm, row_start=i)[0]
@@ -235,45 +238,55 @@ def test_paper_scale_folded_sampled_parity():
             kb = o.galois_key(s, p.gal_baby, rng)
             kg, kf = fold.make_keys(o, s, fs, rng)
             dev = [to_device(a) for a in (ct, kb, kg, kf if len(kf) else np.zeros(1, dtype=np.uint64))]
-            keep.append((i, t, vec, s, (ct, kb, kg, kf), dev))
+            keep.append((k, t, vec, s, (ct, kb, kg, kf), dev))
             for a, d in zip(ptr, dev):
-                a[i] = d.data_ptr()
-        q = query_array(w.targets, *ptr[:3], outs.data_ptr() + out_off * ctw * 8, ptr[3])
-        print(f"folded paper index: scoring {nq} queries", flush=True)
+                a[k] = d.data_ptr()
+        q = query_array(targets, *ptr[:3], outs.data_ptr() + out_off * ctw * 8, ptr[3])
+        print(f"{w.name} folded: scoring {nq} queries", flush=True)
         c.score_batch(q, path=PATH_BATCHED)
         torch.cuda.synchronize()
-        print("folded paper index: scored", flush=True)
+        print(f"{w.name} folded: scored", flush=True)
         jobs, metas = [], []
-        for i, t, vec, s, pk, _ in keep:
+        for k, t, vec, s, pk, _ in keep:
             jobs.append((pk, t))
-            metas.append((i, t, vec, s))
-        for i in (1, nq - 1):
-            t = int(w.targets[i])
-            pi = i % pool
+            metas.append((k, t, vec, s))
+        for k in (1, nq - 1):
+            t = int(targets[k])
+            pi = k % pool
             nf = shapes[t].B.bit_length() - 1
             pk = (to_host(cts[pi]).reshape(2, L, n), to_host(kbs[pi]).reshape(L, 2, L + 1, n),
                   to_host(kgs[pi]).reshape(L, 2, L + 1, n), to_host(kfs[pi]).reshape(4, L, 2, L + 1, n)[:nf])
             jobs.append((pk, t))
-            metas.append((i, t, None, None))
+            metas.append((k, t, None, None))
         rows = {t: emb[int(offs[t]) : int(offs[t + 1])] for _, t in jobs}
         with ThreadPoolExecutor(8) as ex:
             refs = list(ex.map(lambda j: fold.score(o, *j[0], fold.encode_cluster(o, rows[j[1]], shapes[j[1]]),
                                                     shapes[j[1]]), jobs))
         half_t = (p.t - 1) // 2
-        for (i, t, vec, s), ref in zip(metas, refs):
-            got = to_host(outs[out_off[i] * ctw : (out_off[i] + q_chunks[i]) * ctw]).reshape(ref.shape)
-            assert (got == ref).all(), (i, t, shapes[t].B)
+        for (k, t, vec, s), ref in zip(metas, refs):
+            got = to_host(outs[out_off[k] * ctw : (out_off[k] + q_chunks[k]) * ctw]).reshape(ref.shape)
+            assert (got == ref).all(), (int(batch[k]), t, shapes[t].B)
             if vec is None:
                 continue
             dec = np.stack([o.decrypt(s, r).astype(np.int64) for r in got])
             sc = fold.scores_of(dec, len(rows[t]), shapes[t], p.d_pad)
             sc = np.where(sc > half_t, sc - p.t, sc)
-            assert (sc == rows[t].astype(np.int64) @ vec.astype(np.int64)).all(), (i, t, shapes[t].B)
+            assert (sc == rows[t].astype(np.int64) @ vec.astype(np.int64)).all(), (int(batch[k]), t, shapes[t].B)
+        return len(metas)
     finally:
         c.close()
 
 
-def _ctx_paper():
-    from paper_2406_06761_amd.wally import LAYOUT_FOLDED, Context
+def test_paper_scale_folded_sampled_parity():
+    """The paper-scale index (3.2M x 192, 1,800 clusters) folded, with its whole
+    53,710-query batch."""
+    w = synth.paper_workload()
+    assert _folded_sampled_parity("paper", w, range(len(w.targets))) >= 5
 
-    return Context.preset("paper", layout=LAYOUT_FOLDED, fold_max=16)
+
+def test_large_index_folded_sampled_parity():
+    """The 8M x 384 index (4,000 lognormal(1.0) clusters, (g, h) = (32, 16))
+    folded: about 175 GiB, which fits one GPU without co-packing; the first
+    8,192 logical queries of its 1M-query batch plus the samples."""
+    w = synth.paper_workload(n_real=1_000_000, entries=8_000_000, k=4000, dim=384, sigma=1.0, name="large")
+    assert _folded_sampled_parity("large", w, range(8192), pool=256) >= 5
