@@ -176,6 +176,51 @@ def test_folded_query_without_fold_keys_is_rejected(work):
         c.close()
 
 
+def test_fold_max_one_is_the_paper_layout(work):
+    """fold_max = 1: every cluster keeps fold 1 and its plaintexts are the
+    paper layout's (oracle.c encoding)."""
+    o, emb, offs, shapes, rows, *_ = work
+    c = _ctx(fold_max=1)
+    try:
+        c.encode_clusters(emb, offs)
+        for k in (1, 7):
+            assert c.cluster_fold(k) == (1, o.p.g, o.p.h, o.p.gal_giant, [])
+            want = o.encode_cluster(rows[k])
+            chunks, ptr, _ = c.cluster_info(k)
+            assert chunks == want.shape[0]
+            assert (_read_device(ptr, want.size).reshape(want.shape) == want).all(), k
+    finally:
+        c.close()
+
+
+def test_tuner_and_compression_on_folded(work):
+    """The schedule tuner runs on a folded index and leaves it exact; folded
+    responses compress byte for byte as the oracle's (paper §7.1)."""
+    o = work[0]
+    ref = work[9]
+    c = _ctx(max_batch=4)
+    try:
+        c.encode_clusters(work[1], work[2])
+        q, outs, keep = _queries(o, work)
+        res = c.tune(q, batches=(3, 6), sets=(1, 2), tiles=(2, 8))
+        assert len(res) == 8
+        for t in outs:
+            t.zero_()
+        c.score_batch(q)
+        torch.cuda.synchronize()
+        _check(o, work, outs, decrypt_each_cluster=False)
+        cb = c.info.compressed_chunk_bytes
+        for i in (0, 3):
+            comp = torch.empty(outs[i].shape[0] * cb, dtype=torch.uint8, device="cuda")
+            c.compress_responses(outs[i], comp)
+            torch.cuda.synchronize()
+            blob = comp.cpu().numpy().tobytes()
+            for j in range(outs[i].shape[0]):
+                assert blob[j * cb : (j + 1) * cb] == o.compress(ref[i][j]), (i, j)
+    finally:
+        c.close()
+
+
 def _folded_sampled_parity(pname, w, batch, pool=2048):
     """Score logical queries `batch` of workload `w` on its folded index (the
     benchmark's launch configuration: default wave size and streams, fold_max
@@ -250,7 +295,8 @@ def _folded_sampled_parity(pname, w, batch, pool=2048):
         for k, t, vec, s, pk, _ in keep:
             jobs.append((pk, t))
             metas.append((k, t, vec, s))
-        for k in (1, nq - 1):
+        real_pos = {pos[i] for i in picks}
+        for k in [k for k in (1, 2, nq - 2, nq - 1) if k not in real_pos][:2]:  # positions with pool packets
             t = int(targets[k])
             pi = k % pool
             nf = shapes[t].B.bit_length() - 1
