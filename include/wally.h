@@ -188,6 +188,44 @@ int wally_cluster_info(const wally_ctx* ctx, uint32_t c, uint32_t* n_chunks, uin
 int wally_cluster_fold(const wally_ctx* ctx, uint32_t c, uint32_t* fold, uint32_t* g, uint32_t* h,
                        uint64_t* gal_giant, uint64_t* gal_fold);
 
+/* Index PIR for metadata fetch (paper §4.2, "Overview of MulPIR" and
+ * "Reducing evaluation key size"): the query expansion and the first
+ * dimension of MulPIR.  The database is d1 x d2 coefficient-encoded
+ * plaintexts (a plaintext is n coefficients in [0, t), lifted centred to each
+ * limb).  A query for row i is Enc(2^-c X^i) with c = ceil(log2 d1), in NTT
+ * form like any ciphertext.  The server expands it: starting from [ct], at
+ * level a = 0 .. c-1 each ciphertext x at position b gives x + y at b and
+ * (x - y) X^(-2^a) at b + 2^a, with y = Subs(x, g_a), g_a = n/2^a + 1 (the
+ * automorphism X -> X^(g_a) followed by key switching); entry r then
+ * encrypts [r == i].  Column k of the answer is sum_{r < d1} e_r PT[k][r], an
+ * encryption of PT[k][i].  Key reduction: the client sends keys for levels
+ * a0 .. c-1 only; a level a < a0 applies Subs(., g_a0) 2^(a0 - a) times
+ * (g_a0^(2^(a0-a)) = g_a mod 2n holds for a0 <= floor((log2 n - 1)/2)).
+ * The second dimension (ciphertext products) is not provided: the answer is
+ * the d2 columns. */
+typedef struct {
+  const uint64_t* ct;   /* [2][L][n] query                                     */
+  const uint64_t* keys; /* [c - a0][L][2][L+1][n] Galois keys of g_a0 .. g_(c-1) */
+  uint64_t* out;        /* [d2][2][L][n] answer                                */
+} wally_pir_query;
+
+/* Encode a PIR database: coeffs host, [d2][d1][n] uint32 values below t
+ * (column k, row r); d1 <= 2048, d2 <= 2048.  first_key_level: a0, or
+ * UINT32_MAX for the paper's choice min(c - 1, floor((log2 n - 1)/2)).
+ * Replaces the previous PIR database.  Synchronous.  EINVAL, ENOMEM, EDEVICE. */
+int wally_pir_encode(wally_ctx* ctx, const uint32_t* coeffs, uint32_t d1, uint32_t d2, uint32_t first_key_level);
+
+/* Expansion depth c, first key level a0 and the Galois elements of the keys a
+ * query carries (gal_keys[k] = g_(a0+k), room for c - a0 <= 11 entries).  Any
+ * output pointer may be NULL.  EINVAL without a PIR database. */
+int wally_pir_info(const wally_ctx* ctx, uint32_t* levels, uint32_t* first_key_level, uint64_t* gal_keys);
+
+/* Answer nq PIR queries (device pointers) on hip_stream: expansion and first
+ * dimension, up to 64 queries at a time (fewer for deep expansions, so that a
+ * wave's expansion buffers stay within 8 GiB).  Returns once enqueued; caller buffers must
+ * stay alive until the stream completes.  EINVAL, ESTATE. */
+int wally_pir_answer(wally_ctx* ctx, const wally_pir_query* q, uint64_t nq, void* hip_stream);
+
 /* Score nq queries (Server Computation algorithm, paper §5): for each, g-1
  * baby-step rotations, then per chunk the giant-step sums of plaintext
  * products combined by h-1 giant rotations.  q: host array of descriptors

@@ -46,14 +46,15 @@ def first_key_level(n: int, c: int) -> int:
     return min(c - 1, (n.bit_length() - 2) // 2)
 
 
-def key_levels(n: int, c: int):
-    """Levels whose Galois keys the client sends, in order."""
-    return list(range(first_key_level(n, c), c))
+def key_levels(n: int, c: int, a0=None):
+    """Levels whose Galois keys the client sends, in order (a0 defaults to
+    first_key_level; any lower a0 trades key size for fewer substitutions)."""
+    return list(range(first_key_level(n, c) if a0 is None else a0, c))
 
 
-def make_keys(oracle, s, c: int, rng):
-    """Keys [levels][L][2][L+1][n] for key_levels(n, c)."""
-    return np.stack([oracle.galois_key(s, galois(oracle.n, a), rng) for a in key_levels(oracle.n, c)])
+def make_keys(oracle, s, c: int, rng, a0=None):
+    """Keys [levels][L][2][L+1][n] for key_levels(n, c, a0)."""
+    return np.stack([oracle.galois_key(s, galois(oracle.n, a), rng) for a in key_levels(oracle.n, c, a0)])
 
 
 def encrypt_poly(oracle, s, m, rng):
@@ -113,10 +114,11 @@ def _add(oracle, a, b):
     return (a + b) % q
 
 
-def expand(oracle, ct, keys, c: int):
+def expand(oracle, ct, keys, c: int, a0=None):
     """The 2^c expanded ciphertexts [2^c][2][L][n] of one query."""
     n = oracle.n
-    a0 = first_key_level(n, c)
+    a0 = first_key_level(n, c) if a0 is None else a0
+    assert a0 <= first_key_level(n, c)
     cts = [np.asarray(ct, dtype=np.uint64)]
     for a in range(c):
         ka = max(a, a0)
@@ -145,6 +147,6 @@ def first_dimension(oracle, expanded, pts, d1: int):
     return np.stack(out)
 
 
-def answer(oracle, ct, keys, pts, d1: int):
+def answer(oracle, ct, keys, pts, d1: int, a0=None):
     """Server side of one query: expansion, then the first dimension."""
-    return first_dimension(oracle, expand(oracle, ct, keys, levels(d1)), pts, d1)
+    return first_dimension(oracle, expand(oracle, ct, keys, levels(d1), a0), pts, d1)

@@ -215,6 +215,24 @@ struct wally_ctx {
   uint32_t max_chunks = 0;
   uint64_t n_chunks_total = 0;
   uint64_t* pt = nullptr;
+  // index PIR database (paper §4.2): plaintexts [d2][d1][L][n], expansion
+  // depth c, lowest key level a0, X^-(2^a) tables [c][L][n]
+  uint64_t* pir_pt = nullptr;
+  uint32_t pir_d1 = 0, pir_d2 = 0, pir_c = 0, pir_a0 = 0, pir_wq = 0;
+  ulonglong2* pir_w = nullptr;
+  // PIR workspace: expansion lists [wave][2^c], substitution results
+  // [wave][2^(c-1)] (two, for repeated substitutions), key-switch scratch,
+  // descriptors (allocated on the first answer after an encode)
+  uint64_t* pir_lev[2] = {};
+  uint64_t* pir_y[2] = {};
+  uint64_t *pir_X = nullptr, *pir_U = nullptr, *pir_Y = nullptr, *pir_D = nullptr;
+  KsItem* pir_items_dev = nullptr;
+  KsItem* pir_items_host = nullptr;
+  CopyItem* pir_copy_dev = nullptr;
+  CopyItem* pir_copy_host = nullptr;
+  uint64_t** pir_out_dev = nullptr;
+  uint64_t** pir_out_host = nullptr;
+  hipEvent_t pir_staged = nullptr;
   // response compression: constants and a coefficient-form scratch
   CompressArgs comp{};
   uint64_t* comp_scratch = nullptr;
@@ -1386,6 +1404,10 @@ void wally_destroy(wally_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   free_sets(c);
+  if (c->pir_items_host) (void)hipHostFree(c->pir_items_host);
+  if (c->pir_copy_host) (void)hipHostFree(c->pir_copy_host);
+  if (c->pir_out_host) (void)hipHostFree(c->pir_out_host);
+  if (c->pir_staged) (void)hipEventDestroy(c->pir_staged);
   while (!c->allocs.empty()) dfree(c, c->allocs.back().first);
   if (c->fork) (void)hipEventDestroy(c->fork);
   if (c->graph_done) (void)hipEventDestroy(c->graph_done);
@@ -1395,6 +1417,242 @@ void wally_destroy(wally_ctx* c) {
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
+
+// ---------------------------------------------------------------------------
+// Index PIR for metadata fetch (paper §4.2, MulPIR): oblivious expansion of
+// the query ciphertext by substitutions, with the paper's key reduction, and
+// the first dimension (plaintext products summed over the expanded rows).
+
+namespace {
+constexpr uint32_t kPirWaveMax = 64;    // queries expanded together, at most
+constexpr uint64_t kPirWaveBytes = 8ull << 30;  // expansion buffers of one wave, at most
+constexpr int kPirKsItems = 1024;       // key-switch items per launch (scratch size)
+constexpr uint32_t kPirMaxLevels = 11;  // d1 <= 2048
+
+void pir_free_work(wally_ctx* c) {
+  if (c->pir_staged) (void)hipEventSynchronize(c->pir_staged);
+  for (int k = 0; k < 2; ++k) {
+    dfree(c, c->pir_lev[k]);
+    dfree(c, c->pir_y[k]);
+    c->pir_lev[k] = c->pir_y[k] = nullptr;
+  }
+  dfree(c, c->pir_X);
+  dfree(c, c->pir_U);
+  dfree(c, c->pir_Y);
+  dfree(c, c->pir_D);
+  dfree(c, c->pir_items_dev);
+  dfree(c, c->pir_copy_dev);
+  dfree(c, c->pir_out_dev);
+  c->pir_X = c->pir_U = c->pir_Y = c->pir_D = nullptr;
+  c->pir_items_dev = nullptr;
+  c->pir_copy_dev = nullptr;
+  c->pir_out_dev = nullptr;
+  if (c->pir_items_host) (void)hipHostFree(c->pir_items_host);
+  if (c->pir_copy_host) (void)hipHostFree(c->pir_copy_host);
+  if (c->pir_out_host) (void)hipHostFree(c->pir_out_host);
+  c->pir_items_host = nullptr;
+  c->pir_copy_host = nullptr;
+  c->pir_out_host = nullptr;
+}
+
+int pir_ensure_work(wally_ctx* c) {
+  if (c->pir_lev[0]) return WALLY_OK;
+  const size_t w8 = 8, ctw = c->ctw(), S = 1ull << c->pir_c, n = c->n, L = c->L;
+  // queries per wave: the two expansion lists and the two substitution
+  // buffers (3 S ciphertexts per query) within kPirWaveBytes
+  c->pir_wq = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kPirWaveMax, kPirWaveBytes / (3 * S * ctw * w8)));
+  const size_t W = c->pir_wq;
+  const size_t items = W * (S - 1);
+  int rc;
+  for (int k = 0; k < 2; ++k) {
+    if ((rc = dalloc(c, W * S * ctw * w8, (void**)&c->pir_lev[k]))) return rc;
+    if ((rc = dalloc(c, W * (S / 2) * ctw * w8, (void**)&c->pir_y[k]))) return rc;
+  }
+  if ((rc = dalloc(c, kPirKsItems * L * n * w8, (void**)&c->pir_X))) return rc;
+  if ((rc = dalloc(c, kPirKsItems * 2 * (L + 1) * n * w8, (void**)&c->pir_U))) return rc;
+  if ((rc = dalloc(c, kPirKsItems * 2 * n * w8, (void**)&c->pir_Y))) return rc;
+  if ((rc = dalloc(c, kPirKsItems * (L + 1) * L * n * w8, (void**)&c->pir_D))) return rc;
+  if ((rc = dalloc(c, items * sizeof(KsItem), (void**)&c->pir_items_dev))) return rc;
+  if ((rc = dalloc(c, W * sizeof(CopyItem), (void**)&c->pir_copy_dev))) return rc;
+  if ((rc = dalloc(c, W * sizeof(uint64_t*), (void**)&c->pir_out_dev))) return rc;
+  HIP_OK(c, hipHostMalloc((void**)&c->pir_items_host, items * sizeof(KsItem), hipHostMallocDefault));
+  HIP_OK(c, hipHostMalloc((void**)&c->pir_copy_host, W * sizeof(CopyItem), hipHostMallocDefault));
+  HIP_OK(c, hipHostMalloc((void**)&c->pir_out_host, W * sizeof(uint64_t*), hipHostMallocDefault));
+  if (!c->pir_staged) HIP_OK(c, hipEventCreateWithFlags(&c->pir_staged, hipEventDisableTiming));
+  return WALLY_OK;
+}
+
+// Expansion and first dimension of up to pir_wq queries on stream st.
+int pir_wave(wally_ctx* c, const wally_pir_query* q, uint32_t w, hipStream_t st) {
+  const uint64_t ctw = c->ctw(), S = 1ull << c->pir_c, keyw = c->keyw();
+  HIP_OK(c, hipEventSynchronize(c->pir_staged));  // host descriptors of the last wave were copied
+  // descriptors: copies, substitution items of every level, outputs
+  size_t base = 0;
+  std::vector<size_t> lev_base(c->pir_c);
+  for (uint32_t a = 0; a < c->pir_c; ++a) {
+    lev_base[a] = base;
+    const uint64_t half = 1ull << a;
+    const uint32_t ka = std::max(a, c->pir_a0);
+    uint64_t* cur = c->pir_lev[a & 1];
+    for (uint32_t i = 0; i < w; ++i)
+      for (uint64_t b = 0; b < half; ++b) {
+        KsItem it{};
+        it.key = q[i].keys + (uint64_t)(ka - c->pir_a0) * keyw;
+        it.buf0 = cur + (i * S + b) * ctw;
+        it.buf1 = c->pir_y[0] + (i * (S / 2) + b) * ctw;
+        it.fin = c->pir_y[1] + (i * (S / 2) + b) * ctw;
+        c->pir_items_host[base++] = it;
+      }
+  }
+  for (uint32_t i = 0; i < w; ++i) {
+    c->pir_copy_host[i] = CopyItem{q[i].ct, c->pir_lev[0] + i * S * ctw};
+    c->pir_out_host[i] = q[i].out;
+  }
+  HIP_OK(c, hipMemcpyAsync(c->pir_items_dev, c->pir_items_host, base * sizeof(KsItem), hipMemcpyHostToDevice, st));
+  HIP_OK(c, hipMemcpyAsync(c->pir_copy_dev, c->pir_copy_host, w * sizeof(CopyItem), hipMemcpyHostToDevice, st));
+  HIP_OK(c, hipMemcpyAsync(c->pir_out_dev, c->pir_out_host, w * sizeof(uint64_t*), hipMemcpyHostToDevice, st));
+  HIP_OK(c, hipEventRecord(c->pir_staged, st));
+  HIP_OK(c, timed(c, st, WALLY_KERNEL_COPY, w, [&] { return launch_copy_ct(c->pir_copy_dev, (int)w, ctw, st); }));
+  for (uint32_t a = 0; a < c->pir_c; ++a) {
+    const uint64_t half = 1ull << a;
+    const uint32_t ka = std::max(a, c->pir_a0);
+    const uint32_t reps = 1u << (ka - a);  // Subs(., g_ka) applied 2^(ka - a) times is Subs(., g_a)
+    const int n_items = (int)(w * half);
+    int last_out = 1;
+    for (uint32_t r = 0; r < reps; ++r) {
+      KsArgs ka_args{};
+      ka_args.log_n = c->log_n;
+      ka_args.L = c->L;
+      ka_args.gal = c->n / (1u << ka) + 1;
+      ka_args.in_sel = r == 0 ? 0 : (r % 2 == 1 ? 1 : 2);  // x, then alternately y0, y1
+      ka_args.out_sel = r % 2 == 0 ? 1 : 2;
+      ka_args.giant = -1;
+      ka_args.g = c->g;
+      ka_args.X = c->pir_X;
+      ka_args.U = c->pir_U;
+      ka_args.Y = c->pir_Y;
+      ka_args.D = c->pir_D;
+      for (int i0 = 0; i0 < n_items; i0 += kPirKsItems)
+        HIP_OK(c, keyswitch(c, c->pir_items_dev + lev_base[a] + i0, std::min(kPirKsItems, n_items - i0), ka_args, st));
+      last_out = ka_args.out_sel;
+    }
+    PirSplitArgs sa{};
+    sa.cur = c->pir_lev[a & 1];
+    sa.ybuf = c->pir_y[last_out == 1 ? 0 : 1];
+    sa.next = c->pir_lev[(a + 1) & 1];
+    sa.w = c->pir_w + (uint64_t)a * c->L * c->n;
+    sa.stride = (uint32_t)S;
+    sa.ystride = (uint32_t)(S / 2);
+    sa.half = (uint32_t)half;
+    sa.log_n = c->log_n;
+    sa.L = c->L;
+    HIP_OK(c, launch_pir_split(sa, n_items, c->M, st));
+  }
+  PirDotArgs da{};
+  da.E = c->pir_lev[c->pir_c & 1];
+  da.pt = c->pir_pt;
+  da.out = c->pir_out_dev;
+  da.stride = (uint32_t)S;
+  da.d1 = c->pir_d1;
+  da.d2 = c->pir_d2;
+  da.nq = w;
+  da.log_n = c->log_n;
+  da.L = c->L;
+  HIP_OK(c, timed(c, st, WALLY_KERNEL_MAC, w, [&] { return launch_pir_dot(da, c->M, st); }));
+  return WALLY_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int wally_pir_encode(wally_ctx* c, const uint32_t* coeffs, uint32_t d1, uint32_t d2, uint32_t first_key_level) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->serving) return set_err(c, WALLY_ESTATE, "cannot encode while serving");
+  if (!coeffs || d1 == 0 || d2 == 0) return set_err(c, WALLY_EINVAL, "empty or null PIR database");
+  uint32_t levels = 1;
+  while ((1u << levels) < d1) ++levels;
+  if (levels > kPirMaxLevels || d2 > 2048)
+    return set_err(c, WALLY_EINVAL, "PIR database %u x %u beyond the supported 2048 x 2048", d1, d2);
+  const uint32_t top = (uint32_t)(c->log_n - 1) / 2;  // g_a^2 = g_(a-1) mod 2n up to this level
+  const uint32_t a0 = first_key_level == UINT32_MAX ? std::min(levels - 1, top) : first_key_level;
+  if (a0 > std::min(levels - 1, top))
+    return set_err(c, WALLY_EINVAL, "first key level %u above %u (levels %u, squaring holds up to %u)", a0,
+                   std::min(levels - 1, top), levels, top);
+  const uint64_t n_pt = (uint64_t)d1 * d2, t = c->mods[c->L + 1];
+  for (uint64_t i = 0; i < n_pt * c->n; ++i)
+    if (coeffs[i] >= t) return set_err(c, WALLY_EINVAL, "PIR coefficient %llu is not below t", (unsigned long long)i);
+  pir_free_work(c);
+  dfree(c, c->pir_pt);
+  dfree(c, c->pir_w);
+  c->pir_pt = nullptr;
+  c->pir_w = nullptr;
+  c->pir_d1 = c->pir_d2 = 0;
+  if ((rc = dalloc(c, n_pt * c->ptw() / c->d_pad * 8, (void**)&c->pir_pt))) return rc;
+  // X^-(2^a) at NTT entry i of limb l: psi_l^(-(2 brv(i) + 1) 2^a)
+  const uint64_t two_n = 2ull * c->n;
+  std::vector<ulonglong2> w((size_t)levels * c->L * c->n);
+  for (uint32_t a = 0; a < levels; ++a)
+    for (int l = 0; l < c->L; ++l) {
+      const uint64_t q = c->mods[l];
+      for (int i = 0; i < c->n; ++i) {
+        const uint64_t e = ((2ull * bitrev(i, c->log_n) + 1) << a) % two_n;
+        const uint64_t v = powmod(c->psi[l], (two_n - e) % two_n, q);
+        w[((size_t)a * c->L + l) * c->n + i] = make_ulonglong2(v, shoup_of(v, q));
+      }
+    }
+  if ((rc = dalloc(c, w.size() * sizeof(ulonglong2), (void**)&c->pir_w))) return rc;
+  uint32_t* dco = nullptr;
+  const uint64_t chunk = 1024;  // plaintexts per upload
+  if ((rc = dalloc(c, chunk * c->n * sizeof(uint32_t), (void**)&dco))) return rc;
+  hipError_t e = hipMemcpy(c->pir_w, w.data(), w.size() * sizeof(ulonglong2), hipMemcpyHostToDevice);
+  for (uint64_t p0 = 0; e == hipSuccess && p0 < n_pt; p0 += chunk) {
+    const uint64_t cnt = std::min(chunk, n_pt - p0);
+    e = hipMemcpy(dco, coeffs + p0 * c->n, cnt * c->n * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = launch_pir_encode(dco, c->pir_pt + p0 * c->L * c->n, (int)cnt, c->log_n, c->L, c->M, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
+  dfree(c, dco);
+  if (e != hipSuccess) return set_err(c, WALLY_EDEVICE, "PIR encode failed: %s", hipGetErrorString(e));
+  c->pir_d1 = d1;
+  c->pir_d2 = d2;
+  c->pir_c = levels;
+  c->pir_a0 = a0;
+  return WALLY_OK;
+}
+
+int wally_pir_info(const wally_ctx* c, uint32_t* levels, uint32_t* first_key_level, uint64_t* gal_keys) {
+  if (!c || !c->pir_d1) return WALLY_EINVAL;
+  if (levels) *levels = c->pir_c;
+  if (first_key_level) *first_key_level = c->pir_a0;
+  if (gal_keys)
+    for (uint32_t a = c->pir_a0; a < c->pir_c; ++a) gal_keys[a - c->pir_a0] = c->n / (1u << a) + 1;
+  return WALLY_OK;
+}
+
+int wally_pir_answer(wally_ctx* c, const wally_pir_query* q, uint64_t nq, void* hip_stream) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->serving) return set_err(c, WALLY_ESTATE, "a serving session owns the device queues");
+  if (!c->pir_d1) return set_err(c, WALLY_ESTATE, "no PIR database encoded");
+  if (nq && !q) return set_err(c, WALLY_EINVAL, "null query array");
+  for (uint64_t i = 0; i < nq; ++i) {
+    if (!q[i].ct || !q[i].keys || !q[i].out)
+      return set_err(c, WALLY_EINVAL, "PIR query %llu: null pointer", (unsigned long long)i);
+    if (((uintptr_t)q[i].ct | (uintptr_t)q[i].out) & 15)
+      return set_err(c, WALLY_EINVAL, "PIR query %llu: ct/out must be 16-byte aligned", (unsigned long long)i);
+  }
+  if ((rc = pir_ensure_work(c))) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  for (uint64_t i0 = 0; i0 < nq; i0 += c->pir_wq)
+    if ((rc = pir_wave(c, q + i0, (uint32_t)std::min<uint64_t>(c->pir_wq, nq - i0), st))) return rc;
+  return WALLY_OK;
+}
+
+}  // extern "C"
 
 // ---------------------------------------------------------------------------
 // diagnostics

@@ -99,6 +99,34 @@ struct CompressArgs {
   uint64_t qpinv, qpinvp;              // Q'^-1 mod q_0 and Shoup factor
 };
 
+// Index PIR (paper §4.2, MulPIR): query expansion and the first dimension.
+// Expansion level a over `items` = queries x 2^a ciphertexts (query q, entry
+// b < 2^a): x = cur[q][b], y = Subs(x, g_a) (in ybuf[q][b]);
+//   next[q][b] = x + y,  next[q][b + 2^a] = (x - y) * X^(-2^a)
+// with w = NTT(X^(-2^a)) per limb as (value, Shoup factor) pairs [L][n].
+struct PirSplitArgs {
+  const uint64_t* cur;
+  const uint64_t* ybuf;
+  uint64_t* next;
+  const ulonglong2* w;
+  uint32_t stride;  // ciphertexts per query in cur / next (2^c)
+  uint32_t ystride; // ciphertexts per query in ybuf (2^(c-1))
+  uint32_t half;    // 2^a
+  int log_n, L;
+};
+// First dimension: out[q][k] = sum_{r < d1} E[q][r] * PT[k][r], k < d2.
+struct PirDotArgs {
+  const uint64_t* E;     // expanded ciphertexts [queries][stride][2][L][n]
+  const uint64_t* pt;    // plaintexts [d2][d1][L][n]
+  uint64_t* const* out;  // per query: [d2][2][L][n]
+  uint32_t stride, d1, d2, nq;
+  int log_n, L;
+};
+hipError_t launch_pir_encode(const uint32_t* coeffs, uint64_t* out, int n_pt, int log_n, int L, const DevModuli& M,
+                             hipStream_t st);
+hipError_t launch_pir_split(const PirSplitArgs& a, int items, const DevModuli& M, hipStream_t st);
+hipError_t launch_pir_dot(const PirDotArgs& a, const DevModuli& M, hipStream_t st);
+
 hipError_t launch_ks_digits(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
 hipError_t launch_ks_extend(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
 hipError_t launch_ks_inner(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);

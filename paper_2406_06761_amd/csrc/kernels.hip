@@ -451,6 +451,106 @@ __global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_encode(const EncodeJ
 }
 
 // ---------------------------------------------------------------------------
+// Index PIR (paper §4.2, MulPIR).  Coefficient-encoded plaintexts: values in
+// [0, t) lifted centred to each limb, then put in NTT form.  grid (plaintexts, L)
+template <int LOGN>
+__global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_pir_encode(const uint32_t* __restrict__ coeffs,
+                                                                     uint64_t* __restrict__ out, int L, DevModuli M) {
+  using S = NttShape<LOGN, 4>;
+  __shared__ uint64_t lds[S::LDS_WORDS];
+  const int tid = threadIdx.x;
+  const uint64_t p = blockIdx.x;
+  const int l = blockIdx.y;
+  const uint64_t q = M.q[l], t = M.q[L + 1];
+  const uint64_t halft = (t - 1) / 2;
+  WALLY_GLOBAL const uint32_t* src = gmem(coeffs) + p * S::N;
+  uint64_t x[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const uint64_t v = src[FirstMap<LOGN, 4>::idx(tid, e)];
+    x[e] = v > halft ? v + (q - t) : v;  // centred lift (t < q)
+  }
+  ntt_fwd_nat<LOGN, 4>(x, lds, M.fwd[l], q, tid);
+  WALLY_GLOBAL uint64_t* dst = gmem(out) + (p * L + l) * S::N;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) dst[FirstMap<LOGN, 4>::idx(tid, e)] = reduce_lazy(x[e], q, M.mc[l].onep);
+}
+
+// one expansion level after its substitutions: grid (n / 256, 2 L, items); block 256
+__global__ __launch_bounds__(256) void k_pir_split(PirSplitArgs a, DevModuli M) {
+  const uint64_t n = 1ull << a.log_n;
+  const uint32_t i = blockIdx.z;
+  const uint32_t qi = i / a.half, b = i % a.half;
+  const int tl = blockIdx.y, l = tl % a.L;
+  const uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t ctw = 2ull * a.L * n;
+  const uint64_t off = (uint64_t)tl * n + x;
+  const uint64_t q = M.q[l];
+  const uint64_t base = (uint64_t)qi * a.stride + b;
+  const uint64_t xv = gmem(a.cur)[base * ctw + off];
+  const uint64_t yv = gmem(a.ybuf)[((uint64_t)qi * a.ystride + b) * ctw + off];
+  const u64x2 w = *((WALLY_GLOBAL const u64x2*)a.w + (uint64_t)l * n + x);  // (value, Shoup factor)
+  gmem(a.next)[base * ctw + off] = addmod(xv, yv, q);
+  gmem(a.next)[(base + a.half) * ctw + off] = csub(shoup(xv + q - yv, w.x, w.y, q), q);
+}
+
+// first dimension: grid (n / 256, L, d2 x query tiles of 4); block 256.  A
+// thread keeps 27-bit-split partial sums for both parts of 4 queries; every
+// plaintext word it loads feeds 8 products; the sums are folded every 32 terms.
+constexpr int kPirQT = 4;
+__global__ __launch_bounds__(256) void k_pir_dot(PirDotArgs a, DevModuli M) {
+  const uint64_t n = 1ull << a.log_n;
+  const uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const int l = blockIdx.y;
+  const uint32_t k = blockIdx.z % a.d2, q0 = (blockIdx.z / a.d2) * kPirQT;
+  const ModConst mc = M.mc[l];
+  const uint64_t c27 = M.c27[l], c27p = M.c27p[l], q = mc.q;
+  const uint64_t ctw = 2ull * a.L * n;
+  const uint64_t M27 = (1ull << 27) - 1;
+  const int nqt = (int)min((uint32_t)kPirQT, a.nq - q0);
+  WALLY_GLOBAL const uint64_t* pt = gmem(a.pt) + (uint64_t)k * a.d1 * a.L * n + (uint64_t)l * n + x;
+  uint64_t acc[kPirQT][2];
+#pragma unroll
+  for (int j = 0; j < kPirQT; ++j) acc[j][0] = acc[j][1] = 0;
+  for (uint32_t r0 = 0; r0 < a.d1; r0 += 32) {
+    const uint32_t r1 = min(a.d1, r0 + 32);
+    uint64_t s0[kPirQT][2], s1[kPirQT][2], s2[kPirQT][2];
+#pragma unroll
+    for (int j = 0; j < kPirQT; ++j)
+#pragma unroll
+      for (int tp = 0; tp < 2; ++tp) s0[j][tp] = s1[j][tp] = s2[j][tp] = 0;
+    for (uint32_t r = r0; r < r1; ++r) {
+      const uint64_t w = pt[(uint64_t)r * a.L * n];
+      const uint64_t wl = w & M27, wh = w >> 27;
+#pragma unroll
+      for (int j = 0; j < kPirQT; ++j) {
+        if (j < nqt) {
+          WALLY_GLOBAL const uint64_t* e =
+              gmem(a.E) + ((uint64_t)(q0 + j) * a.stride + r) * ctw + (uint64_t)l * n + x;
+#pragma unroll
+          for (int tp = 0; tp < 2; ++tp) {
+            const uint64_t v = e[(uint64_t)tp * a.L * n];
+            const uint64_t vl = v & M27, vh = v >> 27;
+            s0[j][tp] += wl * vl;
+            s1[j][tp] += wl * vh + wh * vl;
+            s2[j][tp] += wh * vh;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kPirQT; ++j)
+#pragma unroll
+      for (int tp = 0; tp < 2; ++tp) acc[j][tp] = addmod(acc[j][tp], fold27(s0[j][tp], s1[j][tp], s2[j][tp], mc, c27, c27p), q);
+  }
+  for (int j = 0; j < nqt; ++j) {
+    WALLY_GLOBAL uint64_t* o = gmem(a.out[q0 + j]) + (uint64_t)k * ctw + (uint64_t)l * n + x;
+    o[0] = acc[j][0];
+    o[(uint64_t)a.L * n] = acc[j][1];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // diagnostics: in-place NTT / INTT of rows (canonical order) mod modulus `mi`
 template <int LOGN>
 __global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_ntt_rows(uint64_t* data, int mi, int inverse, DevModuli M) {
@@ -656,6 +756,30 @@ hipError_t launch_mac_tiles(const KsItem* items, const MacTile* tiles, int n_til
     case 32: hipLaunchKernelGGL((k_mac_tiles<32, 1>), grid, dim3(256), 0, st, items, tiles, a, h, M); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_pir_encode(const uint32_t* coeffs, uint64_t* out, int n_pt, int log_n, int L, const DevModuli& M,
+                             hipStream_t st) {
+  if (n_pt <= 0) return hipSuccess;
+  switch (log_n) {
+    case 12: hipLaunchKernelGGL(k_pir_encode<12>, dim3(n_pt, L), dim3(NttShape<12, 4>::T), 0, st, coeffs, out, L, M); break;
+    case 13: hipLaunchKernelGGL(k_pir_encode<13>, dim3(n_pt, L), dim3(NttShape<13, 4>::T), 0, st, coeffs, out, L, M); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pir_split(const PirSplitArgs& a, int items, const DevModuli& M, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pir_split, dim3((1u << a.log_n) / 256, 2 * a.L, items), dim3(256), 0, st, a, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_pir_dot(const PirDotArgs& a, const DevModuli& M, hipStream_t st) {
+  if (a.nq == 0 || a.d2 == 0) return hipSuccess;
+  const uint32_t tiles = (a.nq + kPirQT - 1) / kPirQT;
+  hipLaunchKernelGGL(k_pir_dot, dim3((1u << a.log_n) / 256, a.L, a.d2 * tiles), dim3(256), 0, st, a, M);
   return hipGetLastError();
 }
 

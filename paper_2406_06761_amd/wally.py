@@ -54,11 +54,15 @@ class Query(ctypes.Structure):
 
 assert ctypes.sizeof(Query) == QUERY_DTYPE.itemsize
 
+PIR_QUERY_DTYPE = np.dtype([("ct", "<u8"), ("keys", "<u8"), ("out", "<u8")])
+PIR_PAPER_KEYS = 0xFFFFFFFF  # first_key_level: the paper's choice
+
 # every symbol declared in include/wally.h and include/wally_diag.h
 SYMBOLS = [
     "wally_params_init", "wally_params_query", "wally_encode_clusters", "wally_cluster_info", "wally_cluster_fold",
     "wally_score_batch",
     "wally_tune", "wally_compress_responses", "wally_encode_clusters_i16",
+    "wally_pir_encode", "wally_pir_info", "wally_pir_answer",
     "wally_serve_start", "wally_serve_submit", "wally_serve_poll", "wally_serve_stop", "wally_strerror",
     "wally_last_error", "wally_destroy", "wally_diag_ntt", "wally_diag_rotate", "wally_diag_kernel_timing",
     "wally_diag_kernel_stats",
@@ -100,6 +104,9 @@ def load():
         "wally_cluster_fold": ([vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32),
                                 ctypes.POINTER(u64), ctypes.POINTER(u64)], i32),
         "wally_score_batch": ([vp, vp, u64, i32, vp], i32),
+        "wally_pir_encode": ([vp, vp, u32, u32, u32], i32),
+        "wally_pir_info": ([vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64)], i32),
+        "wally_pir_answer": ([vp, vp, u64, vp], i32),
         "wally_compress_responses": ([vp, vp, u64, vp, vp], i32),
         "wally_tune": ([vp, vp, u64, vp, vp, vp, ctypes.POINTER(TuneEntry), u32, ctypes.POINTER(u32)], i32),
         "wally_serve_start": ([vp, vp], i32),
@@ -202,6 +209,26 @@ class Context:
         self._check(self.lib.wally_cluster_fold(self.h, c, ctypes.byref(f), ctypes.byref(g), ctypes.byref(h),
                                                 ctypes.byref(gg), gf), "wally_cluster_fold")
         return f.value, g.value, h.value, gg.value, [gf[k] for k in range(f.value.bit_length() - 1)]
+
+    def pir_encode(self, coeffs: np.ndarray, first_key_level=PIR_PAPER_KEYS):
+        """coeffs: [d2][d1][n] values below t (wally_pir_encode)."""
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.uint32)
+        d2, d1, n = coeffs.shape
+        assert n == self.info.n
+        self._check(self.lib.wally_pir_encode(self.h, coeffs.ctypes.data, d1, d2, first_key_level), "wally_pir_encode")
+
+    def pir_info(self):
+        """(levels c, first key level a0, [Galois elements of the keys])."""
+        c, a0 = ctypes.c_uint32(), ctypes.c_uint32()
+        g = (ctypes.c_uint64 * 16)()
+        self._check(self.lib.wally_pir_info(self.h, ctypes.byref(c), ctypes.byref(a0), g), "wally_pir_info")
+        return c.value, a0.value, [g[k] for k in range(c.value - a0.value)]
+
+    def pir_answer(self, queries: np.ndarray, stream=None):
+        """queries: numpy array of PIR_QUERY_DTYPE (device pointers)."""
+        queries = np.ascontiguousarray(queries, dtype=PIR_QUERY_DTYPE)
+        self._check(self.lib.wally_pir_answer(self.h, queries.ctypes.data, len(queries), _stream_handle(stream)),
+                    "wally_pir_answer")
 
     def compress_responses(self, responses, out, stream=None):
         """responses: device tensor of [chunks][2][L][n] words; out: device

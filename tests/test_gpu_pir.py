@@ -1,0 +1,99 @@
+"""GPU parity of index PIR (paper §4.2, MulPIR expansion and first dimension)
+against the oracle (oracle/pir.py), word for word.
+
+* coefficients on both sides of the centred lift, bad inputs refused;
+* ragged d1 (not a power of two), the paper's key reduction (keys for the
+  top levels only, lower levels by repeated substitution) and keys for every
+  level; more queries than one expansion wave (64 at this depth); every answer column
+  equals the oracle's words and decrypts to the queried row's plaintext;
+* both ring sizes (small and paper-scale parameters).
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from oracle import pir
+from oracle.bfv import Oracle
+from oracle.params import preset
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _run(name, d1, d2, nq, a0=None, seed=0):
+    from paper_2406_06761_amd.wally import PIR_PAPER_KEYS, PIR_QUERY_DTYPE, Context, to_device, to_host
+
+    p = preset(name)
+    o = Oracle(p)
+    rng = np.random.default_rng(seed)
+    db = rng.integers(0, p.t, (d2, d1, p.n))
+    db[0, 0, :4] = [0, p.t - 1, (p.t - 1) // 2, (p.t + 1) // 2]  # both sides of the centred lift
+    c_lv = pir.levels(d1)
+    ctx = Context.preset(name)
+    try:
+        ctx.pir_encode(db, PIR_PAPER_KEYS if a0 is None else a0)
+        levels, a0_got, gals = ctx.pir_info()
+        a0_want = pir.first_key_level(p.n, c_lv) if a0 is None else a0
+        assert (levels, a0_got) == (c_lv, a0_want)
+        assert gals == [pir.galois(p.n, a) for a in pir.key_levels(p.n, c_lv, a0_want)]
+        rows = rng.integers(0, d1, nq)
+        packets = []
+        for i in range(nq):
+            s = o.secret_key(rng)
+            packets.append((pir.query(o, s, int(rows[i]), c_lv, rng), pir.make_keys(o, s, c_lv, rng, a0_want), s))
+        pts = np.stack([np.stack([pir.plaintext(o, db[k][r]) for r in range(d1)]) for k in range(d2)])
+        with ThreadPoolExecutor(8) as ex:
+            ref = list(ex.map(lambda pk: pir.answer(o, pk[0], pk[1], pts, d1, a0_want), packets))
+        cts = [to_device(pk[0]) for pk in packets]
+        keys = [to_device(pk[1]) for pk in packets]
+        outs = torch.zeros((nq, d2, 2, p.L, p.n), dtype=torch.int64, device="cuda")
+        q = np.zeros(nq, dtype=PIR_QUERY_DTYPE)
+        q["ct"] = [t.data_ptr() for t in cts]
+        q["keys"] = [t.data_ptr() for t in keys]
+        q["out"] = [outs[i].data_ptr() for i in range(nq)]
+        ctx.pir_answer(q)
+        torch.cuda.synchronize()
+        got = to_host(outs)
+        for i in range(nq):
+            assert (got[i] == ref[i]).all(), (name, d1, d2, i)
+        for i in range(min(nq, 3)):
+            k = i % d2
+            assert (pir.decrypt_poly(o, packets[i][2], got[i][k]) == db[k][rows[i]]).all(), (name, i)
+        return ctx, o, db, pts
+    except Exception:
+        ctx.close()
+        raise
+
+
+@pytest.mark.parametrize("d1,d2,nq,a0", [(5, 3, 70, None), (64, 2, 4, None), (8, 2, 3, 0), (1, 1, 2, None)])
+def test_pir_small(d1, d2, nq, a0):
+    ctx, *_ = _run("tiny", d1, d2, nq, a0, seed=d1 * 10 + d2)
+    ctx.close()
+
+
+def test_pir_rejects_bad_input():
+    from paper_2406_06761_amd.wally import PIR_QUERY_DTYPE, Context, WallyError
+
+    p = preset("tiny")
+    ctx = Context.preset("tiny")
+    try:
+        with pytest.raises(WallyError, match="no PIR database"):
+            ctx.pir_answer(np.zeros(1, dtype=PIR_QUERY_DTYPE))
+        db = np.zeros((2, 3, p.n), dtype=np.int64)
+        db[1, 2, 5] = p.t  # not below t
+        with pytest.raises(WallyError, match="not below t"):
+            ctx.pir_encode(db)
+        db[1, 2, 5] = 0
+        with pytest.raises(WallyError, match="first key level"):
+            ctx.pir_encode(db, 2)  # c = 2: a0 at most 1
+        ctx.pir_encode(db)
+        with pytest.raises(WallyError, match="null pointer"):
+            ctx.pir_answer(np.zeros(1, dtype=PIR_QUERY_DTYPE))
+    finally:
+        ctx.close()
+
+
+def test_pir_paper_parameters():
+    ctx, *_ = _run("paper", 9, 2, 3, None, seed=3)
+    ctx.close()
