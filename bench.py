@@ -393,11 +393,11 @@ def fold_bench(args):
 
 
 def pir_bench(args):
-    """Index PIR for metadata fetch (paper §4.2): one cuckoo table of the
-    paper's metadata example (3.2M entries of 1 KB in 256 clusters: 12,500 per
-    cluster, split over two tables, 16 entries per 16 KiB plaintext gives 391
-    plaintexts per table, arranged 64 x 7), query expansion and the first
-    dimension on the GPU for a batch of queries.  Timed twice: with the paper's
+    """Index PIR for metadata fetch (paper §4.2): one split cuckoo table of
+    the paper's metadata example (3.2M entries of 1 KB in 256 clusters:
+    12,500 per cluster; u = 0.5 and buckets of 16 entries per 16 KiB plaintext
+    give 586 buckets per table, arranged 59 x 10), query expansion and the
+    first dimension on the GPU for a batch of queries.  Timed twice: with the paper's
     key reduction (one key, lower levels by repeated substitution) and with a
     key per level.  Packets are uniform residues, as in the scoring bench."""
     import torch
@@ -405,8 +405,13 @@ def pir_bench(args):
     from paper_2406_06761_amd import synth
     from paper_2406_06761_amd.wally import PIR_QUERY_DTYPE, Context
 
+    from paper_2406_06761_amd import keyword as kw
+
     torch.cuda.set_device(0)
-    d1, d2, nq = 64, 7, args.pir_queries
+    # 12,500 entries of 1 KB per cluster, u = 0.5, 16 entries per 16 KiB bucket
+    buckets = math.ceil(1.5 * 12_500 / (2 * 16))
+    d1, d2 = kw.shape(buckets)
+    nq = args.pir_queries
     ctx = Context.preset("paper")
     info = ctx.info
     n, L = info.n, info.L
@@ -448,8 +453,8 @@ def pir_bench(args):
             "value": legs["paper_key_reduction"]["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
             "steps": args.steps, "warmup": 1, "ms_per_step": legs["paper_key_reduction"]["ms_per_batch"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-            "config": {"workload": f"PIR table {d1} x {d2} plaintexts (391 used by 6,250 1-KB entries), "
-                                   f"{nq} queries", "params": f"n={n}, L={L} x 54-bit limbs, t={info.t}"},
+            "config": {"workload": f"PIR table {d1} x {d2} plaintexts ({buckets} cuckoo buckets of 16 1-KB "
+                                   f"entries; 12,500 entries in two tables), {nq} queries", "params": f"n={n}, L={L} x 54-bit limbs, t={info.t}"},
             "legs": legs, "best_queries_per_s": best["queries_per_s"]}
     print(json.dumps(line), flush=True)
 

@@ -1455,8 +1455,17 @@ void pir_free_work(wally_ctx* c) {
   c->pir_out_host = nullptr;
 }
 
+int pir_alloc_work(wally_ctx* c);
+
+// The PIR workspace, all or nothing: a failed allocation frees what was taken.
 int pir_ensure_work(wally_ctx* c) {
   if (c->pir_lev[0]) return WALLY_OK;
+  const int rc = pir_alloc_work(c);
+  if (rc) pir_free_work(c);
+  return rc;
+}
+
+int pir_alloc_work(wally_ctx* c) {
   const size_t w8 = 8, ctw = c->ctw(), S = 1ull << c->pir_c, n = c->n, L = c->L;
   // queries per wave: the two expansion lists and the two substitution
   // buffers (3 S ciphertexts per query) within kPirWaveBytes

@@ -97,3 +97,54 @@ def test_pir_rejects_bad_input():
 def test_pir_paper_parameters():
     ctx, *_ = _run("paper", 9, 2, 3, None, seed=3)
     ctx.close()
+
+
+def test_keyword_pir_end_to_end():
+    """Keyword PIR (paper §4.2): 700 entries of 256 bytes in split cuckoo
+    tables over plaintext buckets; for each looked-up keyword the client
+    sends one index-PIR query per table (row of its bucket), decrypts the
+    column of its bucket and finds its value in exactly one table; an absent
+    keyword is found in neither."""
+    from paper_2406_06761_amd import keyword as kw
+    from paper_2406_06761_amd.wally import PIR_QUERY_DTYPE, Context, to_device, to_host
+
+    p = preset("tiny")
+    o = Oracle(p)
+    rng = np.random.default_rng(17)
+    eb = 256
+    items = {b"doc-%d" % i: rng.integers(0, 256, rng.integers(1, eb - kw.TAG_BYTES + 1), dtype=np.uint8).tobytes()
+             for i in range(700)}
+    t = kw.build(items, p.n, eb, seed=9)
+    d1, d2 = kw.shape(t.size)
+    c_lv = pir.levels(d1)
+    lookups = [b"doc-0", b"doc-351", b"doc-699", b"nowhere"]
+    found = {k: [] for k in lookups}
+    ctx = Context.preset("tiny")
+    try:
+        for side in (0, 1):
+            ctx.pir_encode(kw.pack(t, side, p.n))
+            a0 = ctx.pir_info()[1]
+            packets, where = [], []
+            for key in lookups:
+                r, col = kw.locate(key, t.size, t.seed)[side]
+                s = o.secret_key(rng)
+                packets.append((to_device(pir.query(o, s, r, c_lv, rng)),
+                                to_device(pir.make_keys(o, s, c_lv, rng, a0)), s))
+                where.append(col)
+            outs = torch.zeros((len(lookups), d2, 2, p.L, p.n), dtype=torch.int64, device="cuda")
+            q = np.zeros(len(lookups), dtype=PIR_QUERY_DTYPE)
+            q["ct"] = [pk[0].data_ptr() for pk in packets]
+            q["keys"] = [pk[1].data_ptr() for pk in packets]
+            q["out"] = [outs[i].data_ptr() for i in range(len(lookups))]
+            ctx.pir_answer(q)
+            torch.cuda.synchronize()
+            got = to_host(outs)
+            for i, key in enumerate(lookups):
+                v = kw.extract(pir.decrypt_poly(o, packets[i][2], got[i][where[i]]), key, eb)
+                if v is not None:
+                    found[key].append(v)
+    finally:
+        ctx.close()
+    assert found[b"nowhere"] == []
+    for key in lookups[:3]:
+        assert len(found[key]) == 1 and found[key][0][: len(items[key])] == items[key], key
