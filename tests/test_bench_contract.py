@@ -1,0 +1,34 @@
+"""bench.py's command-line contract, checked on the CPU: more than one GPU is
+refused with a message (the path has no cross-GPU step), and the roofline
+helpers count the work the kernels do per item."""
+import subprocess
+import sys
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, str(ROOT / "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_work_per_item_and_inner_bytes():
+    sys.path.insert(0, str(ROOT))
+    import bench
+
+    n, L = 8192, 4
+    bf = n // 2 * 13  # butterflies of one 8192-point transform
+    assert bench.per_item_work("ks_extend", n, L, 16, 16) == L * L * bf
+    assert bench.per_item_work("ks_digits", n, L, 16, 16) == L * (bf + n)
+    assert bench.per_item_work("ks_inner", n, L, 16, 16) == 2 * L * (L + 1) * n
+    assert bench.per_item_work("ks_moddown", n, L, 16, 16) == 2 * L * bf + 2 * L * n
+    # one key switch: 30 transforms, the n^-1 scalings of its L + 2 inverse
+    # transforms, the inner products and the P^-1 products
+    ks = sum(bench.per_item_work(k, n, L, 16, 16) for k in ("ks_digits", "ks_extend", "ks_inner", "ks_pinv",
+                                                              "ks_moddown"))
+    assert ks == 30 * bf + (L + 2) * n + 2 * L * (L + 1) * n + 2 * L * n == 2_039_808
+    # key 2.5 MiB + extended digits 1.25 MiB in, inner products 640 KiB out
+    assert bench.inner_bytes(n, L) == 4.375 * 2**20
