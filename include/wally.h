@@ -223,7 +223,9 @@ int wally_pir_info(const wally_ctx* ctx, uint32_t* levels, uint32_t* first_key_l
 /* Answer nq PIR queries (device pointers) on hip_stream: expansion and first
  * dimension, up to 64 queries at a time (fewer for deep expansions, so that a
  * wave's expansion buffers stay within 8 GiB).  Returns once enqueued; caller buffers must
- * stay alive until the stream completes.  EINVAL, ESTATE. */
+ * stay alive until the stream completes.  The workspace is shared: a call's
+ * work runs after the previous call's, whatever stream that was on, and
+ * wally_pir_encode waits for answers in flight.  EINVAL, ESTATE. */
 int wally_pir_answer(wally_ctx* ctx, const wally_pir_query* q, uint64_t nq, void* hip_stream);
 
 /* Score nq queries (Server Computation algorithm, paper §5): for each, g-1

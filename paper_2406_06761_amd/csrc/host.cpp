@@ -233,6 +233,7 @@ struct wally_ctx {
   uint64_t** pir_out_dev = nullptr;
   uint64_t** pir_out_host = nullptr;
   hipEvent_t pir_staged = nullptr;
+  hipEvent_t pir_done = nullptr;  // after the last answer's work; the next call (any stream) and frees wait for it
   // response compression: constants and a coefficient-form scratch
   CompressArgs comp{};
   uint64_t* comp_scratch = nullptr;
@@ -1408,6 +1409,7 @@ void wally_destroy(wally_ctx* c) {
   if (c->pir_copy_host) (void)hipHostFree(c->pir_copy_host);
   if (c->pir_out_host) (void)hipHostFree(c->pir_out_host);
   if (c->pir_staged) (void)hipEventDestroy(c->pir_staged);
+  if (c->pir_done) (void)hipEventDestroy(c->pir_done);
   while (!c->allocs.empty()) dfree(c, c->allocs.back().first);
   if (c->fork) (void)hipEventDestroy(c->fork);
   if (c->graph_done) (void)hipEventDestroy(c->graph_done);
@@ -1430,6 +1432,7 @@ constexpr int kPirKsItems = 1024;       // key-switch items per launch (scratch 
 constexpr uint32_t kPirMaxLevels = 11;  // d1 <= 2048
 
 void pir_free_work(wally_ctx* c) {
+  if (c->pir_done) (void)hipEventSynchronize(c->pir_done);  // answers in flight read the workspace
   if (c->pir_staged) (void)hipEventSynchronize(c->pir_staged);
   for (int k = 0; k < 2; ++k) {
     dfree(c, c->pir_lev[k]);
@@ -1592,7 +1595,7 @@ int wally_pir_encode(wally_ctx* c, const uint32_t* coeffs, uint32_t d1, uint32_t
   const uint64_t n_pt = (uint64_t)d1 * d2, t = c->mods[c->L + 1];
   for (uint64_t i = 0; i < n_pt * c->n; ++i)
     if (coeffs[i] >= t) return set_err(c, WALLY_EINVAL, "PIR coefficient %llu is not below t", (unsigned long long)i);
-  pir_free_work(c);
+  pir_free_work(c);  // waits for answers still reading the database
   dfree(c, c->pir_pt);
   dfree(c, c->pir_w);
   c->pir_pt = nullptr;
@@ -1656,8 +1659,12 @@ int wally_pir_answer(wally_ctx* c, const wally_pir_query* q, uint64_t nq, void* 
   }
   if ((rc = pir_ensure_work(c))) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
+  // the workspace is shared: this call's work follows the last call's, whatever stream that was on
+  if (c->pir_done) HIP_OK(c, hipStreamWaitEvent(st, c->pir_done, 0));
+  else HIP_OK(c, hipEventCreateWithFlags(&c->pir_done, hipEventDisableTiming));
   for (uint64_t i0 = 0; i0 < nq; i0 += c->pir_wq)
     if ((rc = pir_wave(c, q + i0, (uint32_t)std::min<uint64_t>(c->pir_wq, nq - i0), st))) return rc;
+  HIP_OK(c, hipEventRecord(c->pir_done, st));
   return WALLY_OK;
 }
 

@@ -148,3 +148,44 @@ def test_keyword_pir_end_to_end():
     assert found[b"nowhere"] == []
     for key in lookups[:3]:
         assert len(found[key]) == 1 and found[key][0][: len(items[key])] == items[key], key
+
+
+def test_answers_on_two_streams_then_reencode():
+    """Two answer calls on different streams, back to back, then an immediate
+    re-encode with another database: the shared workspace orders the calls and
+    the re-encode waits for them, so both answers equal the oracle's."""
+    from paper_2406_06761_amd.wally import PIR_QUERY_DTYPE, Context, to_device, to_host
+
+    p = preset("tiny")
+    o = Oracle(p)
+    rng = np.random.default_rng(23)
+    d1, d2 = 6, 2
+    db = rng.integers(0, p.t, (d2, d1, p.n))
+    pts = np.stack([np.stack([pir.plaintext(o, db[k][r]) for r in range(d1)]) for k in range(d2)])
+    c_lv = pir.levels(d1)
+    ctx = Context.preset("tiny")
+    try:
+        ctx.pir_encode(db)
+        a0 = ctx.pir_info()[1]
+        packets = []
+        for i in range(8):
+            s = o.secret_key(rng)
+            packets.append((pir.query(o, s, i % d1, c_lv, rng), pir.make_keys(o, s, c_lv, rng, a0)))
+        ref = [pir.answer(o, ct, k, pts, d1, a0) for ct, k in packets]
+        dev = [(to_device(ct), to_device(k)) for ct, k in packets]
+        outs = torch.zeros((8, d2, 2, p.L, p.n), dtype=torch.int64, device="cuda")
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        for half in range(2):
+            q = np.zeros(4, dtype=PIR_QUERY_DTYPE)
+            idx = range(4 * half, 4 * half + 4)
+            q["ct"] = [dev[i][0].data_ptr() for i in idx]
+            q["keys"] = [dev[i][1].data_ptr() for i in idx]
+            q["out"] = [outs[i].data_ptr() for i in idx]
+            ctx.pir_answer(q, stream=streams[half])
+        ctx.pir_encode(rng.integers(0, p.t, (d2, d1, p.n)))  # frees the old database once the answers are done
+        torch.cuda.synchronize()
+        got = to_host(outs)
+        for i in range(8):
+            assert (got[i] == ref[i]).all(), i
+    finally:
+        ctx.close()
