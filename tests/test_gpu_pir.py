@@ -174,6 +174,7 @@ def test_answers_on_two_streams_then_reencode():
         ref = [pir.answer(o, ct, k, pts, d1, a0) for ct, k in packets]
         dev = [(to_device(ct), to_device(k)) for ct, k in packets]
         outs = torch.zeros((8, d2, 2, p.L, p.n), dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()  # inputs and outputs are made on the default stream
         streams = [torch.cuda.Stream(), torch.cuda.Stream()]
         for half in range(2):
             q = np.zeros(4, dtype=PIR_QUERY_DTYPE)
