@@ -494,60 +494,56 @@ __global__ __launch_bounds__(256) void k_pir_split(PirSplitArgs a, DevModuli M) 
   gmem(a.next)[(base + a.half) * ctw + off] = csub(shoup(xv + q - yv, w.x, w.y, q), q);
 }
 
-// first dimension: grid (n / 256, L, d2 x query tiles of 4); block 256.  A
-// thread keeps 27-bit-split partial sums for both parts of 4 queries; every
-// plaintext word it loads feeds 8 products; the sums are folded every 32 terms.
-constexpr int kPirQT = 4;
+// first dimension: grid (n / 512, L, column pairs x query pairs); block 256.
+// A thread takes two adjacent coefficients (16-byte loads) of two columns and
+// two queries, both ciphertext parts: per row r it loads 2 plaintext pairs and
+// 4 ciphertext pairs and does 16 products into 128-bit lazy sums (d1 <= 2048
+// products of words below 2^54 stay below 2^119), reduced once at the end.
 __global__ __launch_bounds__(256) void k_pir_dot(PirDotArgs a, DevModuli M) {
   const uint64_t n = 1ull << a.log_n;
-  const uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t x = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 2;
   const int l = blockIdx.y;
-  const uint32_t k = blockIdx.z % a.d2, q0 = (blockIdx.z / a.d2) * kPirQT;
+  const uint32_t kpairs = (a.d2 + 1) / 2;
+  const uint32_t k0 = (blockIdx.z % kpairs) * 2, q0 = (blockIdx.z / kpairs) * 2;
+  const bool k1v = k0 + 1 < a.d2, q1v = q0 + 1 < a.nq;
   const ModConst mc = M.mc[l];
-  const uint64_t c27 = M.c27[l], c27p = M.c27p[l], q = mc.q;
-  const uint64_t ctw = 2ull * a.L * n;
-  const uint64_t M27 = (1ull << 27) - 1;
-  const int nqt = (int)min((uint32_t)kPirQT, a.nq - q0);
-  WALLY_GLOBAL const uint64_t* pt = gmem(a.pt) + (uint64_t)k * a.d1 * a.L * n + (uint64_t)l * n + x;
-  uint64_t acc[kPirQT][2];
+  const uint64_t ctw = 2ull * a.L * n, ptw = (uint64_t)a.L * n;
+  WALLY_GLOBAL const uint64_t* pt0 = gmem(a.pt) + (uint64_t)k0 * a.d1 * ptw + (uint64_t)l * n + x;
+  WALLY_GLOBAL const uint64_t* pt1 = pt0 + (k1v ? (uint64_t)a.d1 * ptw : 0);
+  WALLY_GLOBAL const uint64_t* e0 = gmem(a.E) + (uint64_t)q0 * a.stride * ctw + (uint64_t)l * n + x;
+  WALLY_GLOBAL const uint64_t* e1 = e0 + (q1v ? (uint64_t)a.stride * ctw : 0);
+  u128w acc[2][2][2][2] = {};  // [column][query][part][coefficient]
+  for (uint32_t r = 0; r < a.d1; ++r) {
+    const u64x2 w[2] = {*(WALLY_GLOBAL const u64x2*)(pt0 + (uint64_t)r * ptw),
+                        *(WALLY_GLOBAL const u64x2*)(pt1 + (uint64_t)r * ptw)};
+    u64x2 v[2][2];
 #pragma unroll
-  for (int j = 0; j < kPirQT; ++j) acc[j][0] = acc[j][1] = 0;
-  for (uint32_t r0 = 0; r0 < a.d1; r0 += 32) {
-    const uint32_t r1 = min(a.d1, r0 + 32);
-    uint64_t s0[kPirQT][2], s1[kPirQT][2], s2[kPirQT][2];
-#pragma unroll
-    for (int j = 0; j < kPirQT; ++j)
-#pragma unroll
-      for (int tp = 0; tp < 2; ++tp) s0[j][tp] = s1[j][tp] = s2[j][tp] = 0;
-    for (uint32_t r = r0; r < r1; ++r) {
-      const uint64_t w = pt[(uint64_t)r * a.L * n];
-      const uint64_t wl = w & M27, wh = w >> 27;
-#pragma unroll
-      for (int j = 0; j < kPirQT; ++j) {
-        if (j < nqt) {
-          WALLY_GLOBAL const uint64_t* e =
-              gmem(a.E) + ((uint64_t)(q0 + j) * a.stride + r) * ctw + (uint64_t)l * n + x;
-#pragma unroll
-          for (int tp = 0; tp < 2; ++tp) {
-            const uint64_t v = e[(uint64_t)tp * a.L * n];
-            const uint64_t vl = v & M27, vh = v >> 27;
-            s0[j][tp] += wl * vl;
-            s1[j][tp] += wl * vh + wh * vl;
-            s2[j][tp] += wh * vh;
-          }
-        }
-      }
+    for (int tp = 0; tp < 2; ++tp) {
+      v[0][tp] = *(WALLY_GLOBAL const u64x2*)(e0 + (uint64_t)r * ctw + (uint64_t)tp * ptw);
+      v[1][tp] = *(WALLY_GLOBAL const u64x2*)(e1 + (uint64_t)r * ctw + (uint64_t)tp * ptw);
     }
 #pragma unroll
-    for (int j = 0; j < kPirQT; ++j)
+    for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-      for (int tp = 0; tp < 2; ++tp) acc[j][tp] = addmod(acc[j][tp], fold27(s0[j][tp], s1[j][tp], s2[j][tp], mc, c27, c27p), q);
+      for (int qq = 0; qq < 2; ++qq)
+#pragma unroll
+        for (int tp = 0; tp < 2; ++tp) {
+          mac128(acc[kk][qq][tp][0], w[kk].x, v[qq][tp].x);
+          mac128(acc[kk][qq][tp][1], w[kk].y, v[qq][tp].y);
+        }
   }
-  for (int j = 0; j < nqt; ++j) {
-    WALLY_GLOBAL uint64_t* o = gmem(a.out[q0 + j]) + (uint64_t)k * ctw + (uint64_t)l * n + x;
-    o[0] = acc[j][0];
-    o[(uint64_t)a.L * n] = acc[j][1];
-  }
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+    for (int qq = 0; qq < 2; ++qq) {
+      if ((kk && !k1v) || (qq && !q1v)) continue;
+      WALLY_GLOBAL uint64_t* o = gmem(a.out[q0 + qq]) + (uint64_t)(k0 + kk) * ctw + (uint64_t)l * n + x;
+#pragma unroll
+      for (int tp = 0; tp < 2; ++tp)
+        *(WALLY_GLOBAL u64x2*)(o + (uint64_t)tp * ptw) =
+            u64x2{reduce128(acc[kk][qq][tp][0], mc.q, mc.r64, mc.r64p, mc.onep),
+                  reduce128(acc[kk][qq][tp][1], mc.q, mc.r64, mc.r64p, mc.onep)};
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -778,8 +774,8 @@ hipError_t launch_pir_split(const PirSplitArgs& a, int items, const DevModuli& M
 
 hipError_t launch_pir_dot(const PirDotArgs& a, const DevModuli& M, hipStream_t st) {
   if (a.nq == 0 || a.d2 == 0) return hipSuccess;
-  const uint32_t tiles = (a.nq + kPirQT - 1) / kPirQT;
-  hipLaunchKernelGGL(k_pir_dot, dim3((1u << a.log_n) / 256, a.L, a.d2 * tiles), dim3(256), 0, st, a, M);
+  const uint32_t pairs = ((a.d2 + 1) / 2) * ((a.nq + 1) / 2);
+  hipLaunchKernelGGL(k_pir_dot, dim3((1u << a.log_n) / 512, a.L, pairs), dim3(256), 0, st, a, M);
   return hipGetLastError();
 }
 
