@@ -392,69 +392,79 @@ def fold_bench(args):
     print(json.dumps(line), flush=True)
 
 
-def pir_bench(args):
+def pir_legs(nq, steps):
     """Index PIR for metadata fetch (paper §4.2): one split cuckoo table of
     the paper's metadata example (3.2M entries of 1 KB in 256 clusters:
     12,500 per cluster; u = 0.5 and buckets of 16 entries per 16 KiB plaintext
     give 586 buckets per table, arranged 59 x 10), query expansion and the
-    first dimension on the GPU for a batch of queries.  Timed twice: with the paper's
-    key reduction (one key, lower levels by repeated substitution) and with a
-    key per level.  Packets are uniform residues, as in the scoring bench."""
+    first dimension on the GPU for a batch of nq queries.  Timed twice: with
+    the paper's key reduction (one key, lower levels by repeated substitution)
+    and with a key per level.  Packets are uniform residues, as in the scoring
+    bench.  Returns ((d1, d2), {variant: figures})."""
     import torch
 
+    from paper_2406_06761_amd import keyword as kw
     from paper_2406_06761_amd import synth
     from paper_2406_06761_amd.wally import PIR_QUERY_DTYPE, Context
 
-    from paper_2406_06761_amd import keyword as kw
-
-    torch.cuda.set_device(0)
-    # 12,500 entries of 1 KB per cluster, u = 0.5, 16 entries per 16 KiB bucket
     buckets = math.ceil(1.5 * 12_500 / (2 * 16))
     d1, d2 = kw.shape(buckets)
-    nq = args.pir_queries
     ctx = Context.preset("paper")
-    info = ctx.info
-    n, L = info.n, info.L
-    rng = np.random.default_rng(synth.SEED_DB)
-    db = rng.integers(0, 1 << 16, (d2, d1, n), dtype=np.uint32)  # 2 bytes of metadata per coefficient
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(synth.SEED_CRYPTO)
-    qs = [info.q[j] for j in range(L)]
-    pool = min(nq, 256)
-    cts = synth.uniform_residues(gen, (pool, 2), qs, n, device="cuda")
-    outs = torch.empty((nq, d2 * 2 * L * n), dtype=torch.int64, device="cuda")
-    legs = {}
-    for name, a0 in (("paper_key_reduction", 0xFFFFFFFF), ("key_per_level", 0)):
-        ctx.pir_encode(db, a0)
-        c, a0_, gals = ctx.pir_info()
-        keys = synth.uniform_residues(gen, (pool, len(gals) * L, 2), qs + [info.P], n, device="cuda")
-        pidx = np.arange(nq) % pool
-        q = np.zeros(nq, dtype=PIR_QUERY_DTYPE)
-        q["ct"] = cts.data_ptr() + pidx * cts[0].numel() * 8
-        q["keys"] = keys.data_ptr() + pidx * keys[0].numel() * 8
-        q["out"] = outs.data_ptr() + np.arange(nq) * outs[0].numel() * 8
-        ctx.pir_answer(q)  # warm-up (workspace)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ctx.pir_answer(q)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        subs = sum((1 << a) * (1 << (max(a, a0_) - a)) for a in range(c))
-        legs[name] = {"first_key_level": a0_, "keys_per_query": len(gals), "substitutions_per_query": subs,
-                      "ms_per_batch": dt * 1e3, "queries_per_s": nq / dt,
-                      "pt_ct_products_per_s": nq * d1 * d2 / dt}
-        log(f"pir {name}: a0={a0_}, {len(gals)} keys, {subs} substitutions per query, {dt * 1e3:.1f} ms for "
-            f"{nq} queries, {nq / dt:.0f} queries/s")
-        del keys
-    ctx.close()
+    try:
+        info = ctx.info
+        n, L = info.n, info.L
+        rng = np.random.default_rng(synth.SEED_DB)
+        db = rng.integers(0, 1 << 16, (d2, d1, n), dtype=np.uint32)  # 2 bytes of metadata per coefficient
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(synth.SEED_CRYPTO)
+        qs = [info.q[j] for j in range(L)]
+        pool = min(nq, 256)
+        cts = synth.uniform_residues(gen, (pool, 2), qs, n, device="cuda")
+        outs = torch.empty((nq, d2 * 2 * L * n), dtype=torch.int64, device="cuda")
+        legs = {}
+        for name, a0 in (("paper_key_reduction", 0xFFFFFFFF), ("key_per_level", 0)):
+            ctx.pir_encode(db, a0)
+            c, a0_, gals = ctx.pir_info()
+            keys = synth.uniform_residues(gen, (pool, len(gals) * L, 2), qs + [info.P], n, device="cuda")
+            pidx = np.arange(nq) % pool
+            q = np.zeros(nq, dtype=PIR_QUERY_DTYPE)
+            q["ct"] = cts.data_ptr() + pidx * cts[0].numel() * 8
+            q["keys"] = keys.data_ptr() + pidx * keys[0].numel() * 8
+            q["out"] = outs.data_ptr() + np.arange(nq) * outs[0].numel() * 8
+            ctx.pir_answer(q)  # warm-up (workspace)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ctx.pir_answer(q)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            subs = sum((1 << a) * (1 << (max(a, a0_) - a)) for a in range(c))
+            legs[name] = {"first_key_level": a0_, "keys_per_query": len(gals), "substitutions_per_query": subs,
+                          "ms_per_batch": dt * 1e3, "queries_per_s": nq / dt,
+                          "pt_ct_products_per_s": nq * d1 * d2 / dt}
+            log(f"pir {name}: a0={a0_}, {len(gals)} keys, {subs} substitutions per query, {dt * 1e3:.1f} ms for "
+                f"{nq} queries, {nq / dt:.0f} queries/s")
+            del keys
+    finally:
+        ctx.close()
+    return (d1, d2), legs
+
+
+def pir_bench(args):
+    """PIR mode of the benchmark: one JSON line for the metadata-fetch table."""
+    import torch
+
+    torch.cuda.set_device(0)
+    nq = args.pir_queries
+    (d1, d2), legs = pir_legs(nq, args.steps)
     best = max(legs.values(), key=lambda v: v["queries_per_s"])
     line = {"metric": "PIR queries/sec (metadata fetch: expansion + first dimension, one table)",
             "value": legs["paper_key_reduction"]["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
             "steps": args.steps, "warmup": 1, "ms_per_step": legs["paper_key_reduction"]["ms_per_batch"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-            "config": {"workload": f"PIR table {d1} x {d2} plaintexts ({buckets} cuckoo buckets of 16 1-KB "
-                                   f"entries; 12,500 entries in two tables), {nq} queries", "params": f"n={n}, L={L} x 54-bit limbs, t={info.t}"},
+            "config": {"workload": f"PIR table {d1} x {d2} plaintexts (586 cuckoo buckets of 16 1-KB "
+                                   f"entries; 12,500 entries in two tables), {nq} queries",
+                       "params": "n=8192, L=4 x 54-bit limbs"},
             "legs": legs, "best_queries_per_s": best["queries_per_s"]}
     print(json.dumps(line), flush=True)
 
@@ -811,6 +821,19 @@ def main():
         fctx.close()
         del kfs
 
+    # Index PIR for metadata fetch (a metadata table of the paper's example),
+    # after the scoring legs; a failure here is reported, not fatal to the line.
+    pir = None
+    if args.workload == "paper" and args.pir_queries > 0:
+        ctx.close()
+        torch.cuda.empty_cache()
+        try:
+            shape_, legs_ = pir_legs(args.pir_queries, 1)
+            pir = {"table": list(shape_), "queries": args.pir_queries, "legs": legs_}
+        except Exception as exc:  # the scoring line must still be printed
+            pir = {"error": str(exc)}
+            log(f"pir leg failed: {exc}")
+
     cpu = None
     if not args.no_cpu and args.cpu_sample > 0:
         threads = min(16, os.cpu_count() or 1)
@@ -850,6 +873,7 @@ def main():
         "roofline": roofline,
         "kernels_ms": {k: v[2] for k, v in kstats.items()},
         "folded_layout": folded,
+        "pir_metadata_fetch": pir,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
