@@ -109,10 +109,17 @@ typedef struct {
   uint32_t drop_bits[2];         /* low bits dropped from c0, c1 (compression) */
   uint32_t compressed_widths[2]; /* bits per serialized coefficient of c0, c1  */
   uint64_t compressed_chunk_bytes; /* bytes of one compressed response ciphertext */
+  uint64_t hbm_budget;           /* device bytes the context may use            */
+  uint64_t serve_request_bytes;  /* serving admission charge of a one-chunk
+                                    request: ciphertext + two keys + response */
+  uint64_t serve_inflight_limit; /* one-chunk requests admitted at once: (budget
+                                    - allocated - workspaces not yet allocated)
+                                    / serve_request_bytes                    */
 } wally_params_info;
 
-/* One query: every pointer is a device pointer.  `out` receives
- * chunks(cluster) consecutive ciphertexts.  In WALLY_LAYOUT_FOLDED, key_giant
+/* One query: every pointer is a device pointer, 16-byte aligned (the
+ * kernels move rows in 16-byte accesses; a misaligned pointer is refused with
+ * EINVAL).  `out` receives chunks(cluster) consecutive ciphertexts.  In WALLY_LAYOUT_FOLDED, key_giant
  * is the key for the cluster's own giant step (wally_cluster_fold) and
  * key_fold holds its log2(fold) fold keys, in the order of gal_fold (NULL
  * allowed when the fold factor is 1); the other layouts ignore key_fold. */
@@ -126,13 +133,32 @@ typedef struct {
   const uint64_t* key_fold;  /* [log2 fold][L][2][L+1][n]                   */
 } wally_query;
 
-/* Derive the parameters (rules above), build the NTT tables on the host and
- * upload them to `desc->device`.  On success *out owns all device memory it
- * allocates.  EINVAL for unsupported sizes, ENOMEM, EDEVICE. */
+/* Set up one parameter set on one device.
+ *
+ * Defined by: the ring R_Q = Z_Q[X]/(X^n + 1) with n slots mod t in two rows
+ * of n/2 (paper §2.1, "Somewhat Homomorphic Encryption" and "Vectorized
+ * SHE"); the RNS form of BFV with hybrid key switching, which needs the
+ * ciphertext primes and one special prime P (§7.1, "Residue Number System
+ * (RNS) variant of BFV"); the parameter choices of §7.3 ("SHE parameters":
+ * ring degree, limbs of a few tens of bits, plaintext modulus just above a
+ * power of two); the baby-step giant-step split of the d_pad diagonals of
+ * §4.1 (g * h = d_pad).  The concrete rules are the conventions at the top of
+ * this file.
+ *
+ * desc: host, read only.  log_n 12 or 13; num_limbs 1..8; limb_bits 30..54;
+ * t_bits >= 2 with t_bits + 2 <= limb_bits; dim >= 2 with d_pad <= n/2 and
+ * d_pad <= 1024 (so g is 2, 4, 8, 16 or 32); max_batch <= 32768; fold_max a
+ * power of two <= 256, and 0 outside WALLY_LAYOUT_FOLDED.
+ * out: host; on success *out is a new context that owns every device
+ * allocation it makes (all counted against hbm_budget) until wally_destroy.
+ * Errors: EINVAL for any value outside the ranges above (nothing is
+ * allocated, *out = NULL), ENOMEM, EDEVICE. */
 int wally_params_init(const wally_params_desc* desc, wally_ctx** out);
 
-/* Parameter values and byte sizes (the client side needs them to build
- * ciphertexts and keys). */
+/* Parameter values and byte sizes: what the client side needs to build
+ * ciphertexts and keys for this context (§2.1; §7.1 and §7.3 for the moduli),
+ * plus the serving admission figures of wally_serve_submit.
+ * ctx: read only; out: host, filled completely.  EINVAL for NULL. */
 int wally_params_query(const wally_ctx* ctx, wally_params_info* out);
 
 /* Server Initialization (paper §5; diagonal packing §4.1): encode K clusters
@@ -168,13 +194,18 @@ int wally_encode_clusters_i16(wally_ctx* ctx, const int16_t* emb, uint64_t n_ent
  * null or misaligned pointers. */
 int wally_compress_responses(wally_ctx* ctx, const uint64_t* in, uint64_t chunks, uint8_t* out, void* hip_stream);
 
-/* Chunks of cluster c, the slot of its first entry in its first chunk (0 in
- * the per-cluster and folded layouts) and the device address of its
- * plaintexts [chunks][D][L][n] (D = d_pad except in the folded layout;
- * read-only for the caller).  Entry e of the cluster is scored in slot
- * (slot_base + e) mod n of chunk (slot_base + e) / n of the response (folded
- * layout: see WALLY_LAYOUT_FOLDED).  Any output pointer may be NULL.  EINVAL
- * for c >= K. */
+/* Where cluster c sits in the encoded index, so that a client can map
+ * response slots to entries.  Defined by the packing of §4.1 ("Reducing
+ * Communication in Nearest Neighbor Search": entry k n + s of a cluster in
+ * slot s of its chunk k) and the Server Initialization algorithm of §5 (one
+ * plaintext set per chunk of a cluster).
+ * Outputs (host, any may be NULL): the number of chunks of cluster c, the
+ * slot of its first entry in its first chunk (0 in the per-cluster and folded
+ * layouts) and the device address of its plaintexts [chunks][D][L][n] (D =
+ * d_pad except in the folded layout; read only, owned by the context, valid
+ * until the next encode or wally_destroy).  Entry e of the cluster is scored
+ * in slot (slot_base + e) mod n of chunk (slot_base + e) / n of the response
+ * (folded layout: see WALLY_LAYOUT_FOLDED).  EINVAL for c >= K or NULL ctx. */
 int wally_cluster_info(const wally_ctx* ctx, uint32_t c, uint32_t* n_chunks, uint32_t* slot_base,
                        const uint64_t** plaintexts);
 
@@ -259,10 +290,32 @@ typedef struct {
 int wally_tune(wally_ctx* ctx, const wally_query* q, uint64_t nq, const uint32_t* batches, const uint32_t* sets,
                const uint32_t* tiles, wally_tune_entry* out, uint32_t max_out, uint32_t* n_out);
 
-/* Serving (continuous batching).  start: begin accepting work on hip_stream.
- * submit: non-blocking; EAGAIN when the in-flight budget is full (retry
- * after poll).  poll: non-blocking; writes up to `max` finished tickets.
- * stop: waits for in-flight work and ends the session. */
+/* Serving (continuous batching).  The protocol runs in epochs and the server
+ * must finish every query of an epoch before it ends (§3.1, "Epochs");
+ * queries need no synchronisation with each other (§8), so requests that
+ * arrive while others are on the GPU join the next wave that a workspace set
+ * frees, and their work overlaps on the device.  Each request is scored as in
+ * wally_score_batch (§5, Server Computation algorithm) and its words do not
+ * depend on the other requests in its wave.
+ *
+ * start: begin a session on hip_stream (work enqueued before the call is
+ * ordered before the session's waves); allocates the workspace sets if they
+ * are not there.  ESTATE if already serving or nothing is encoded.
+ * submit: non-blocking.  `q` (host, copied) is validated as in
+ * wally_score_batch; its device buffers are borrowed until the ticket is
+ * returned by poll.  Admission by HBM: a request holds device memory for its
+ * ciphertext, its keys and its response chunks while it is in the library
+ * (serve_request_bytes in wally_params_info for a one-chunk request); it is
+ * admitted only while bytes allocated by the context (index, tables,
+ * workspaces) + bytes of the admitted, unfinished requests + its own bytes <=
+ * hbm_budget.  EAGAIN when that does not hold now (retry after poll), ENOMEM
+ * when the request alone can never fit.  *ticket (host) receives its ticket.
+ * poll: non-blocking; writes up to `max` finished tickets to done (host) and
+ * their count to *n_done.
+ * stop: waits for all admitted requests and ends the session.
+ * All four: one thread at a time per context (calls are serialised by a
+ * lock); ESTATE outside a session (start inside one); EDEVICE after a device
+ * fault. */
 int wally_serve_start(wally_ctx* ctx, void* hip_stream);
 int wally_serve_submit(wally_ctx* ctx, const wally_query* q, uint64_t* ticket);
 int wally_serve_poll(wally_ctx* ctx, uint64_t* done, uint32_t max, uint32_t* n_done);

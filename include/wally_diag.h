@@ -43,6 +43,22 @@ int wally_diag_rotate(wally_ctx* ctx, const uint64_t* in, const uint64_t* keys, 
 #define WALLY_KERNEL_COPY 6     /* query copy into the baby-step buffer      */
 #define WALLY_KERNEL_COUNT 7
 
+/* Register-resident butterfly rate: the peak of the transforms' arithmetic.
+ * One launch of `blocks` workgroups of 256 threads; each thread keeps 16
+ * words mod q_0 in registers (word e of thread t starts at
+ * ((t * 16 + e) * 0x9E3779B97F4A7C15 mod 2^64) mod q_0) and runs `iters`
+ * radix-16 passes: stage s = 0..3 pairs words e and e + 8 / 2^s with twiddle
+ * W_s = psi_0^(s+1) mod q_0 and its Shoup factor floor(W_s 2^64 / q_0), as a
+ * forward lazy Cooley-Tukey butterfly (inverse = 0; words wrap mod 2^64, no
+ * reduction) or an inverse Gentleman-Sande butterfly (inverse = 1), the
+ * butterflies of the negacyclic NTT (paper §7.1, Harvey butterflies with lazy
+ * reduction).  That is 32 butterflies per pass and thread, blocks * 256 * 32 *
+ * iters in all.  out (device, [blocks * 256][16] words) receives the final
+ * words; *ms (host) the launch's duration from events on hip_stream (the call
+ * waits for it).  EINVAL for blocks or iters of 0 or a NULL pointer. */
+int wally_diag_bfly_rate(wally_ctx* ctx, int inverse, uint32_t blocks, uint32_t iters, uint64_t* out, double* ms,
+                         void* hip_stream);
+
 typedef struct {
   uint64_t launches;
   uint64_t items;   /* work items over all launches (items x grid.y blocks) */

@@ -176,11 +176,13 @@ struct WaveWork {
   hipEvent_t done = nullptr;    // wave finished
   bool busy = false;
   std::vector<uint64_t> tickets;  // serving: tickets of the wave in flight
+  uint64_t held_bytes = 0;        // serving: admission bytes of those requests
 };
 
 struct ServeReq {
   wally_query q;
   uint64_t ticket;
+  uint64_t bytes;  // admission charge (request_bytes)
 };
 
 struct TimerRec {
@@ -263,7 +265,7 @@ struct wally_ctx {
   std::deque<ServeReq> pending;
   std::deque<uint64_t> finished;
   uint64_t next_ticket = 1;
-  uint64_t max_pending = 0;
+  uint64_t serve_bytes = 0;  // admission bytes of the admitted, unfinished requests
   // optional per-launch timing (events on the launch stream)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -530,6 +532,23 @@ int ensure_sets(wally_ctx* c) {
   return WALLY_OK;
 }
 
+// Device bytes ensure_sets allocates for one workspace set (the descriptor
+// tables included), at the current wave size and largest chunk count.
+uint64_t set_bytes(const wally_ctx* c) {
+  const uint64_t B = c->B, w8 = 8, giant_cap = B * std::max<uint32_t>(1, c->max_chunks);
+  const uint64_t n = c->n, L = c->L, ctw = c->ctw();
+  return w8 * B * (c->g * ctw + L * n + 2 * (L + 1) * n + 2 * n + (L + 1) * L * n + 2 * ctw + c->h * ctw) +
+         giant_cap * (sizeof(MacTile) + sizeof(KsItem)) + B * (sizeof(CopyItem) + sizeof(KsItem));
+}
+
+// Serving admission charge of one request: the device memory it holds while
+// it is in the library (its ciphertext, its keys and its response chunks).
+uint64_t request_bytes(const wally_ctx* c, const wally_query& q) {
+  const uint64_t fold_keys = c->K ? (uint64_t)__builtin_ctz(c->fold[q.cluster]) : 0;
+  const uint64_t chunks = c->K ? c->chunks[q.cluster] : 1;
+  return 8 * (c->ctw() + (2 + fold_keys) * c->keyw() + chunks * c->ctw());
+}
+
 KsArgs base_args(const wally_ctx* c, const WaveWork& s) {
   KsArgs a{};
   a.log_n = c->log_n;
@@ -694,8 +713,9 @@ int validate_query(wally_ctx* c, const wally_query& q, uint64_t idx) {
   if (c->fold[q.cluster] > 1 && !q.key_fold)
     return set_err(c, WALLY_EINVAL, "query %llu: cluster %u is folded (fold %u) and needs its fold keys",
                    (unsigned long long)idx, q.cluster, c->fold[q.cluster]);
-  if (((uintptr_t)q.ct | (uintptr_t)q.out) & 15)
-    return set_err(c, WALLY_EINVAL, "query %llu: ct/out must be 16-byte aligned", (unsigned long long)idx);
+  // every row is moved in 16-byte accesses: ciphertext, keys and output alike
+  if (((uintptr_t)q.ct | (uintptr_t)q.out | (uintptr_t)q.key_baby | (uintptr_t)q.key_giant | (uintptr_t)q.key_fold) & 15)
+    return set_err(c, WALLY_EINVAL, "query %llu: ct, keys and out must be 16-byte aligned", (unsigned long long)idx);
   return WALLY_OK;
 }
 
@@ -729,7 +749,9 @@ int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
   if (desc->max_batch > (uint32_t)kMaxWaveQueries) return WALLY_EINVAL;
   if (desc->limb_bits < 30 || desc->limb_bits > 54) return WALLY_EINVAL;  // 27-bit halves in the sums
   if (desc->t_bits < 2 || desc->t_bits + 2 > desc->limb_bits) return WALLY_EINVAL;
-  if (desc->dim < 1) return WALLY_EINVAL;
+  // d_pad in 2..1024: the baby-step count g = 2^ceil(log2(d_pad)/2) is then
+  // 2..32, the counts the giant-step sum kernel is instantiated for
+  if (desc->dim < 2 || desc->dim > 1024) return WALLY_EINVAL;
   if (desc->layout != WALLY_LAYOUT_PER_CLUSTER && desc->layout != WALLY_LAYOUT_COPACK &&
       desc->layout != WALLY_LAYOUT_FOLDED)
     return WALLY_EINVAL;
@@ -886,6 +908,12 @@ int wally_params_query(const wally_ctx* c, wally_params_info* o) {
   o->compressed_widths[0] = c->comp.width[0];
   o->compressed_widths[1] = c->comp.width[1];
   o->compressed_chunk_bytes = c->comp.part_bytes[0] + c->comp.part_bytes[1];
+  o->hbm_budget = c->budget;
+  o->serve_request_bytes = 8 * (2 * c->ctw() + 2 * c->keyw());
+  // workspaces count as allocated once a session (or a scoring call) made them
+  const uint64_t ws = c->sets.empty() ? (uint64_t)c->n_sets * set_bytes(c) : 0;
+  const uint64_t used = c->allocated + ws;
+  o->serve_inflight_limit = used < c->budget ? (c->budget - used) / o->serve_request_bytes : 0;
   return WALLY_OK;
 }
 
@@ -1302,6 +1330,8 @@ int serve_pump(wally_ctx* c) {
       if (e != hipSuccess) return set_err(c, WALLY_EDEVICE, "serving wave failed: %s", hipGetErrorString(e));
       for (uint64_t t : s.tickets) c->finished.push_back(t);
       s.tickets.clear();
+      c->serve_bytes -= s.held_bytes;  // the requests' buffers are the caller's again
+      s.held_bytes = 0;
       s.busy = false;
     }
     if (!s.busy && !c->pending.empty()) {
@@ -1320,7 +1350,8 @@ int serve_pump(wally_ctx* c) {
       for (auto& r : taken) qs.push_back(&r.q);
       if ((rc = enqueue_wave(c, s, qs.data(), (int)qs.size()))) return rc;
       // descriptors are copied by the enqueue; the request copies may go
-      for (auto& r : taken) s.tickets.push_back(r.ticket);
+      s.held_bytes = 0;
+      for (auto& r : taken) s.tickets.push_back(r.ticket), s.held_bytes += r.bytes;
       s.busy = true;
     }
   }
@@ -1344,8 +1375,8 @@ int wally_serve_start(wally_ctx* c, void* hip_stream) {
   c->graph_pending = false;
   c->pending.clear();
   c->finished.clear();
-  // admission: in flight = one wave per set; waiting = the same again
-  c->max_pending = (uint64_t)c->B * c->sets.size();
+  c->serve_bytes = 0;
+  for (auto& s : c->sets) s.held_bytes = 0;
   c->serving = true;
   return WALLY_OK;
 }
@@ -1357,12 +1388,19 @@ int wally_serve_submit(wally_ctx* c, const wally_query* q, uint64_t* ticket) {
   if (!c->serving) return set_err(c, WALLY_ESTATE, "not serving");
   if (!q || !ticket) return set_err(c, WALLY_EINVAL, "null argument");
   if ((rc = validate_query(c, *q, 0))) return rc;
-  if (c->pending.size() >= c->max_pending) {
-    if ((rc = serve_pump(c))) return rc;
-    if (c->pending.size() >= c->max_pending) return WALLY_EAGAIN;
+  // admission by HBM: index, tables and workspaces (allocated) + the requests
+  // already admitted + this one must stay within the budget
+  const uint64_t rb = request_bytes(c, *q);
+  if (c->allocated + rb > c->budget)
+    return set_err(c, WALLY_ENOMEM, "request of %llu bytes can never be admitted: %llu of the %llu-byte budget are allocated",
+                   (unsigned long long)rb, (unsigned long long)c->allocated, (unsigned long long)c->budget);
+  if (c->allocated + c->serve_bytes + rb > c->budget) {
+    if ((rc = serve_pump(c))) return rc;  // retire finished waves first
+    if (c->allocated + c->serve_bytes + rb > c->budget) return WALLY_EAGAIN;
   }
   *ticket = c->next_ticket++;
-  c->pending.push_back(ServeReq{*q, *ticket});
+  c->serve_bytes += rb;
+  c->pending.push_back(ServeReq{*q, *ticket, rb});
   return serve_pump(c);
 }
 
@@ -1654,8 +1692,8 @@ int wally_pir_answer(wally_ctx* c, const wally_pir_query* q, uint64_t nq, void* 
   for (uint64_t i = 0; i < nq; ++i) {
     if (!q[i].ct || !q[i].keys || !q[i].out)
       return set_err(c, WALLY_EINVAL, "PIR query %llu: null pointer", (unsigned long long)i);
-    if (((uintptr_t)q[i].ct | (uintptr_t)q[i].out) & 15)
-      return set_err(c, WALLY_EINVAL, "PIR query %llu: ct/out must be 16-byte aligned", (unsigned long long)i);
+    if (((uintptr_t)q[i].ct | (uintptr_t)q[i].out | (uintptr_t)q[i].keys) & 15)
+      return set_err(c, WALLY_EINVAL, "PIR query %llu: ct, keys and out must be 16-byte aligned", (unsigned long long)i);
   }
   if ((rc = pir_ensure_work(c))) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
@@ -1708,6 +1746,35 @@ int wally_diag_rotate(wally_ctx* c, const uint64_t* in, const uint64_t* keys, ui
     a.out_sel = 1;
     HIP_OK(c, keyswitch(c, s.baby_dev, w, a, st));
   }
+  return WALLY_OK;
+}
+
+int wally_diag_bfly_rate(wally_ctx* c, int inverse, uint32_t blocks, uint32_t iters, uint64_t* out, double* ms,
+                         void* hip_stream) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  if (!out || !ms || blocks == 0 || iters == 0 || blocks > (1u << 20) || iters > (1u << 24))
+    return set_err(c, WALLY_EINVAL, "bad butterfly-rate arguments");
+  const uint64_t q = c->mods[0];
+  ulonglong2 w[4];
+  for (int s = 0; s < 4; ++s) {
+    const uint64_t v = powmod(c->psi[0], s + 1, q);
+    w[s] = make_ulonglong2(v, shoup_of(v, q));
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_OK(c, hipEventCreate(&a));
+  hipError_t e = hipEventCreate(&b);
+  if (e == hipSuccess) e = hipEventRecord(a, st);
+  if (e == hipSuccess) e = launch_bfly_rate(out, (int)blocks, inverse ? 1 : 0, w, q, (int)iters, st);
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float f = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&f, a, b);
+  (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (e != hipSuccess) return set_err(c, WALLY_EDEVICE, "butterfly-rate launch failed: %s", hipGetErrorString(e));
+  *ms = f;
   return WALLY_OK;
 }
 

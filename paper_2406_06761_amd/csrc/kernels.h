@@ -141,6 +141,9 @@ hipError_t launch_resp_intt(const uint64_t* in, uint64_t* out, int chunks, int l
 // coefficient rows [chunks][2][L][n] -> serialized responses [chunks][part_bytes[0] + part_bytes[1]]
 hipError_t launch_resp_pack(const uint64_t* coef, uint8_t* out, int chunks, const CompressArgs& a, const DevModuli& M,
                             hipStream_t st);
+// register-resident butterfly loop (diagnostic): out [blocks * 256][16]
+hipError_t launch_bfly_rate(uint64_t* out, int blocks, int inverse, const ulonglong2* w, uint64_t q, int iters,
+                            hipStream_t st);
 hipError_t launch_copy_ct(const CopyItem* items, int n_items, uint64_t words, hipStream_t st);
 hipError_t launch_encode(const EncodeJob* jobs, int n_jobs, const EncodeArgs& a, const DevModuli& M, hipStream_t st);
 hipError_t launch_ntt_rows(uint64_t* data, int rows, int log_n, int mi, int inverse, const DevModuli& M,

@@ -572,6 +572,40 @@ __global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_ntt_rows(uint64_t* d
 }
 
 // ---------------------------------------------------------------------------
+// diagnostics: register-resident butterfly rate.  Every thread keeps 16 words
+// in registers and runs `iters` radix-16 passes of the transforms' own
+// butterfly (ct_bfly forward, gs_bfly inverse) with four fixed twiddles, one
+// per stage: 32 butterflies per pass and no memory traffic inside the loop.
+// Forward words are never reduced, so they wrap mod 2^64 (the instruction
+// sequence does not depend on the values).  The final words are stored so
+// the loop is not removed and its arithmetic can be checked.
+// grid (blocks); block 256
+template <int INV>
+__global__ __launch_bounds__(256) void k_bfly_rate(uint64_t* __restrict__ out, ulonglong2 w0, ulonglong2 w1,
+                                                   ulonglong2 w2, ulonglong2 w3, uint64_t q, int iters) {
+  const uint64_t gid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t q4 = 4 * q;
+  uint64_t x[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) x[e] = (gid * 16 + e) * 0x9E3779B97F4A7C15ull % q;
+  const ulonglong2 W[4] = {w0, w1, w2, w3};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int half = 8 >> st;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        if (e & half) continue;
+        if (INV) gs_bfly(x[e], x[e + half], W[st], q, q4);
+        else ct_bfly(x[e], x[e + half], W[st], q, q4);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) out[gid * 16 + e] = x[e];
+}
+
+// ---------------------------------------------------------------------------
 // response compression (paper §7.1, "Reducing the response size")
 
 // one row per workgroup: row r of [chunks][2][L][n] is limb r mod L
@@ -807,6 +841,16 @@ hipError_t launch_ntt_rows(uint64_t* data, int rows, int log_n, int mi, int inve
     case 13: hipLaunchKernelGGL(k_ntt_rows<13>, dim3(rows), dim3(NttShape<13, 4>::T), 0, st, data, mi, inverse, M); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_bfly_rate(uint64_t* out, int blocks, int inverse, const ulonglong2* w, uint64_t q, int iters,
+                            hipStream_t st) {
+  if (blocks <= 0) return hipSuccess;
+  if (inverse)
+    hipLaunchKernelGGL(k_bfly_rate<1>, dim3(blocks), dim3(256), 0, st, out, w[0], w[1], w[2], w[3], q, iters);
+  else
+    hipLaunchKernelGGL(k_bfly_rate<0>, dim3(blocks), dim3(256), 0, st, out, w[0], w[1], w[2], w[3], q, iters);
   return hipGetLastError();
 }
 

@@ -43,7 +43,9 @@ class ParamsInfo(ctypes.Structure):
                 ("gal_baby", ctypes.c_uint64), ("gal_giant", ctypes.c_uint64), ("ct_words", ctypes.c_uint64),
                 ("key_words", ctypes.c_uint64), ("pt_chunk_words", ctypes.c_uint64),
                 ("bytes_allocated", ctypes.c_uint64), ("drop_bits", ctypes.c_uint32 * 2),
-                ("compressed_widths", ctypes.c_uint32 * 2), ("compressed_chunk_bytes", ctypes.c_uint64)]
+                ("compressed_widths", ctypes.c_uint32 * 2), ("compressed_chunk_bytes", ctypes.c_uint64),
+                ("hbm_budget", ctypes.c_uint64), ("serve_request_bytes", ctypes.c_uint64),
+                ("serve_inflight_limit", ctypes.c_uint64)]
 
 
 class Query(ctypes.Structure):
@@ -65,7 +67,7 @@ SYMBOLS = [
     "wally_pir_encode", "wally_pir_info", "wally_pir_answer",
     "wally_serve_start", "wally_serve_submit", "wally_serve_poll", "wally_serve_stop", "wally_strerror",
     "wally_last_error", "wally_destroy", "wally_diag_ntt", "wally_diag_rotate", "wally_diag_kernel_timing",
-    "wally_diag_kernel_stats",
+    "wally_diag_kernel_stats", "wally_diag_bfly_rate",
 ]
 
 KERNELS = ["ks_digits", "ks_extend", "ks_inner", "ks_pinv", "ks_moddown", "mac", "copy_ct"]
@@ -119,6 +121,7 @@ def load():
         "wally_diag_ntt": ([vp, u32, vp, u64, i32, vp], i32),
         "wally_diag_rotate": ([vp, vp, vp, vp, u64, i32, vp], i32),
         "wally_diag_kernel_timing": ([vp, i32], i32),
+        "wally_diag_bfly_rate": ([vp, i32, u32, u32, vp, ctypes.POINTER(ctypes.c_double), vp], i32),
         "wally_diag_kernel_stats": ([vp, ctypes.POINTER(KernelStat), u32], i32),
     }
     for name, (args, res) in sig.items():
@@ -293,6 +296,13 @@ class Context:
         count = ct.numel() // self.info.ct_words
         self._check(self.lib.wally_diag_rotate(self.h, _ptr(ct), _ptr(keys), _ptr(out), count, which,
                                                _stream_handle(stream)), "wally_diag_rotate")
+
+    def bfly_rate(self, inverse, blocks, iters, out, stream=None):
+        """wally_diag_bfly_rate: (butterflies, launch ms); out receives the final words."""
+        ms = ctypes.c_double()
+        self._check(self.lib.wally_diag_bfly_rate(self.h, 1 if inverse else 0, blocks, iters, _ptr(out),
+                                                  ctypes.byref(ms), _stream_handle(stream)), "wally_diag_bfly_rate")
+        return blocks * 256 * 32 * iters, ms.value
 
     def kernel_timing(self, enable=True):
         self._check(self.lib.wally_diag_kernel_timing(self.h, 1 if enable else 0), "wally_diag_kernel_timing")

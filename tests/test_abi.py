@@ -41,6 +41,34 @@ def test_struct_layouts_match_header():
     assert wally.ParamsInfo.q.offset == 24
 
 
+def test_struct_layouts_match_a_c_compiler(tmp_path):
+    """Every field offset and structure size of the binding equals what a C
+    compiler gives for include/wally.h."""
+    import subprocess
+
+    from paper_2406_06761_amd import wally
+
+    structs = {"wally_params_desc": wally.ParamsDesc, "wally_params_info": wally.ParamsInfo,
+               "wally_query": wally.Query, "wally_tune_entry": wally.TuneEntry}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "wally.h"', '#include "wally_diag.h"',
+             "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", str(ROOT / "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
 def test_error_strings_and_null_handling():
     from paper_2406_06761_amd import wally
 
@@ -61,6 +89,11 @@ def test_error_strings_and_null_handling():
     assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL
     d = wally.ParamsDesc(12, 3, 36, 20, 64, wally.LAYOUT_FOLDED, 0, 0, 0, 12, 0)  # not a power of two
     assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL
+    # dimensions whose baby-step count has no giant-step sum kernel (g = 1 and g = 64)
+    for dim in (1, 1025, 2048):
+        d = wally.ParamsDesc(13, 3, 36, 20, dim, 0, 0, 0, 0, 0, 0)
+        assert lib.wally_params_init(ctypes.byref(d), ctypes.byref(h)) == wally.EINVAL, dim
+        assert not h.value
 
 
 def test_library_is_newer_than_its_sources():

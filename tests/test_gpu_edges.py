@@ -51,10 +51,17 @@ def test_bad_queries_are_refused_before_any_work(ctx):
     q["key_giant"] = 0
     with pytest.raises(WallyError, match="null pointer"):
         ctx.score_batch(q)
-    q, keep = _one_query(ctx, 0)
-    q["out"] += 8  # not 16-byte aligned
-    with pytest.raises(WallyError, match="aligned"):
-        ctx.score_batch(q)
+    for field in ("out", "ct", "key_baby", "key_giant", "key_fold"):  # each pointer 16-byte aligned
+        q, keep = _one_query(ctx, 0)
+        q[field] = (q["ct"] if field == "key_fold" else q[field]) + 8
+        with pytest.raises(WallyError, match="aligned"):
+            ctx.score_batch(q)
+        with pytest.raises(WallyError, match="aligned"):
+            ctx.serve_start()
+            try:
+                ctx.serve_submit(0, *(int(q[f][0]) for f in ("ct", "key_baby", "key_giant", "out", "key_fold")))
+            finally:
+                ctx.serve_stop()
     torch.cuda.synchronize()
     assert (keep[2] == 7).all()  # nothing was enqueued
 

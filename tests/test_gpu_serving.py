@@ -2,8 +2,9 @@
 
 * a query's response is the same word for word whether it is served alone or
   inside a burst of other queries (and equal to the oracle's);
-* admission: with a small in-flight budget, submit returns EAGAIN (None in the
-  binding) and the refused requests go through after polling;
+* admission by HBM budget: with room for three requests beside the index and
+  workspaces, submit returns EAGAIN (None in the binding) and the refused
+  requests go through after polling; a request that can never fit is ENOMEM;
 * state errors: submit/poll/stop outside a session give ESTATE.
 """
 import time
@@ -83,16 +84,40 @@ def test_alone_equals_mix_equals_oracle(setup):
         c.close()
 
 
+def _budget_for(emb, offs, requests, **kw):
+    """hbm_budget that leaves room for `requests` one-chunk requests once the
+    index and the workspaces are allocated (measured on a probe context)."""
+    from paper_2406_06761_amd.wally import Context
+
+    c = Context.preset("tiny", **kw)
+    try:
+        c.encode_clusters(emb, offs)
+        c.serve_start()
+        info = c._query()
+        c.serve_stop()
+        return int(info.bytes_allocated) + requests * int(info.serve_request_bytes) + int(info.serve_request_bytes) // 2
+    finally:
+        c.close()
+
+
 def test_admission_refuses_then_drains(setup):
+    """Admission by HBM budget: room for exactly three one-chunk requests
+    beside the index and workspaces; a fourth submission is refused (EAGAIN)
+    until polling retires finished ones, and every response is exact."""
     from paper_2406_06761_amd.wally import Context, to_host
 
     o, w, emb, offs, dev, ref = setup
     nq = len(w.targets)
-    c = Context.preset("tiny", max_batch=1, wave_sets=2)  # 2 in flight + 2 waiting
+    budget = _budget_for(emb, offs, 3, max_batch=1, wave_sets=2)
+    c = Context.preset("tiny", max_batch=1, wave_sets=2, hbm_budget=budget)
     try:
         c.encode_clusters(emb, offs)
+        info = c._query()
+        assert info.hbm_budget == budget
+        assert info.serve_inflight_limit == 3  # workspaces not yet allocated are counted
         outs = torch.zeros((nq, 1, 2, o.L, o.n), dtype=torch.int64, device="cuda")
         c.serve_start()
+        assert c._query().serve_inflight_limit == 3
         refused = 0
         done = set()
         pending = list(range(nq))
@@ -113,9 +138,32 @@ def test_admission_refuses_then_drains(setup):
         c.serve_stop()
         torch.cuda.synchronize()
         assert refused > 0
+        assert c._query().serve_inflight_limit == 3  # every request's bytes were released
         got = to_host(outs)
         for i in range(nq):
             assert (got[i] == ref[i]).all(), i
+    finally:
+        c.close()
+
+
+def test_request_over_the_whole_budget_is_enomem(setup):
+    """A request that could never fit beside the index is refused with ENOMEM
+    (not EAGAIN, which would make the caller retry forever)."""
+    from paper_2406_06761_amd.wally import ENOMEM, Context, WallyError
+
+    o, w, emb, offs, dev, ref = setup
+    budget = _budget_for(emb, offs, 0, max_batch=1, wave_sets=1)
+    c = Context.preset("tiny", max_batch=1, wave_sets=1, hbm_budget=budget)
+    try:
+        c.encode_clusters(emb, offs)
+        c.serve_start()
+        assert c._query().serve_inflight_limit == 0
+        ct, kb, kg = dev[0]
+        out = torch.zeros((1, 2, o.L, o.n), dtype=torch.int64, device="cuda")
+        with pytest.raises(WallyError) as e:
+            c.serve_submit(int(w.targets[0]), ct.data_ptr(), kb.data_ptr(), kg.data_ptr(), out.data_ptr())
+        assert e.value.code == ENOMEM
+        c.serve_stop()
     finally:
         c.close()
 
