@@ -67,7 +67,7 @@ def inner_bytes(n, L):
 
 
 TRAFFIC_FILE = Path(__file__).resolve().parent / "profiles" / "hbm_traffic_paper.json"
-KERNEL_SOURCES = ["kernels.hip", "ntt.h", "arith.h", "kernels.h"]
+KERNEL_SOURCES = ["kernels.hip", "ntt.h", "arith.h", "kernels.h", "items.h"]
 
 
 def kernel_source_hash():

@@ -73,7 +73,7 @@ extern "C" {
 
 #define WALLY_PATH_BATCHED 0 /* queries of all clusters share launches        */
 #define WALLY_PATH_PLAIN 1   /* one launch sequence per cluster (baseline)     */
-#define WALLY_PATH_GRAPH 2   /* the batched launches captured in one hipGraph  */
+#define WALLY_PATH_GRAPH 2   /* the batched launches captured in hipGraphs      */
 
 typedef struct wally_ctx wally_ctx;
 
@@ -264,9 +264,10 @@ int wally_pir_answer(wally_ctx* ctx, const wally_pir_query* q, uint64_t nq, void
  * products combined by h-1 giant rotations.  q: host array of descriptors
  * with device pointers.  `path`: WALLY_PATH_BATCHED (waves of queries of all
  * clusters), WALLY_PATH_PLAIN (one launch sequence per cluster) or
- * WALLY_PATH_GRAPH (the batched launches of the whole batch captured once in
- * a hipGraph and replayed while the same query array and configuration are
- * passed again; at most 64 waves of max_batch queries, EINVAL beyond); all
+ * WALLY_PATH_GRAPH (the batched launches of the whole batch captured once, in
+ * segments of at most 48 waves of max_batch queries with a graph each, and
+ * replayed, segment after segment on hip_stream, while the same query array
+ * and configuration are passed again; any batch size); all
  * give identical words.  Work is enqueued on hip_stream (a
  * hipStream_t; NULL = default stream) and the call returns once it is
  * enqueued; output is independent of batch composition.  Validation errors

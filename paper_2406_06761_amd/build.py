@@ -11,7 +11,7 @@ ROOT = HERE.parent
 SRC = HERE / "csrc"
 LIB = HERE / "libwally.so"
 SOURCES = [SRC / "kernels.hip", SRC / "host.cpp"]
-HEADERS = [SRC / "arith.h", SRC / "ntt.h", SRC / "kernels.h", ROOT / "include" / "wally.h", ROOT / "include" / "wally_diag.h"]
+HEADERS = [SRC / "arith.h", SRC / "ntt.h", SRC / "kernels.h", SRC / "items.h", SRC / "plan.h", ROOT / "include" / "wally.h", ROOT / "include" / "wally_diag.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

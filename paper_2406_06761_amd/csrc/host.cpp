@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "plan.h"
 #include "wally.h"
 #include "wally_diag.h"
 
@@ -245,10 +246,10 @@ struct wally_ctx {
   int B = 0;
   int n_sets = 2;
   uint32_t tile_items = 8;  // giant items per plaintext-sharing tile of the sum kernel
-  // graph path: one captured graph of a whole batch, replayed while the batch
-  // (the query array) and the configuration stay the same
+  // graph path: the captured segments of a whole batch, replayed while the
+  // batch (the query array) and the configuration stay the same
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
+  std::vector<hipGraphExec_t> graph_execs;
   uint64_t graph_key = 0;
   void* graph_desc = nullptr;  // device descriptors of the captured batch
   bool capturing = false;
@@ -277,96 +278,6 @@ struct wally_ctx {
 };
 
 namespace {
-
-// Where each cluster's entries go.  Per cluster (paper §4.1 packing, Server
-// Initialization of §5): cluster c owns ceil(N_c / n) chunks, filled from slot
-// 0.  Co-packed: clusters of more than n entries keep chunks of their own (in
-// cluster order, first); the others go first-fit decreasing (size descending,
-// ties by index) into shared chunks at the chunk's fill level, so a query
-// needs one chunk and reads its scores from slot_base on.
-struct ChunkSeg {
-  uint32_t cluster;
-  uint64_t offset, count;  // entries [offset, offset + count) of the cluster
-};
-struct ChunkLayout {
-  std::vector<std::vector<ChunkSeg>> segs;  // per chunk, in slot order
-  std::vector<uint64_t> first;
-  std::vector<uint32_t> chunks, base, fold;
-};
-
-// Fold factor of a cluster in the folded layout (not in the paper): the
-// largest power of two B <= fold_max with B N_c <= n and d_pad / B >= 4.
-uint32_t fold_factor(uint64_t size, uint32_t n, uint32_t d_pad, uint32_t fold_max) {
-  uint32_t B = 1;
-  while (2 * B <= fold_max && 2 * B * size <= n && d_pad / (2 * B) >= 4) B *= 2;
-  return B;
-}
-
-// Baby/giant split of the d_pad / B diagonals of a fold class.
-struct FoldCls {
-  uint32_t B, g, h, gal_giant;
-};
-FoldCls fold_cls(const wally_ctx* c, uint32_t B) {
-  const uint32_t D = c->d_pad / B;
-  int lg = 0;
-  while ((1u << lg) < D) ++lg;
-  const uint32_t g = 1u << ((lg + 1) / 2);
-  return FoldCls{B, g, D / g, (uint32_t)powmod(3, g, 2ull * c->n)};
-}
-
-void plan_layout(uint32_t layout, const uint64_t* offsets, uint32_t k, uint32_t n, uint32_t d_pad, uint32_t fold_max,
-                 ChunkLayout& out) {
-  out.segs.clear();
-  out.first.assign(k, 0);
-  out.chunks.assign(k, 0);
-  out.base.assign(k, 0);
-  out.fold.assign(k, 1);
-  // chunks of cap = n / B entries each
-  auto own_chunks = [&](uint32_t c, uint32_t cap) {
-    const uint64_t sz = offsets[c + 1] - offsets[c];
-    out.first[c] = out.segs.size();
-    out.chunks[c] = (uint32_t)((sz + cap - 1) / cap);
-    for (uint64_t off = 0; off < sz; off += cap)
-      out.segs.push_back({ChunkSeg{c, off, std::min<uint64_t>(cap, sz - off)}});
-  };
-  if (layout == WALLY_LAYOUT_PER_CLUSTER) {
-    for (uint32_t c = 0; c < k; ++c) own_chunks(c, n);
-    return;
-  }
-  if (layout == WALLY_LAYOUT_FOLDED) {
-    for (uint32_t c = 0; c < k; ++c) {
-      out.fold[c] = fold_factor(offsets[c + 1] - offsets[c], n, d_pad, fold_max);
-      own_chunks(c, n / out.fold[c]);
-    }
-    return;
-  }
-  std::vector<uint32_t> small;
-  for (uint32_t c = 0; c < k; ++c) {
-    if (offsets[c + 1] - offsets[c] > n)
-      own_chunks(c, n);
-    else
-      small.push_back(c);
-  }
-  std::stable_sort(small.begin(), small.end(), [&](uint32_t a, uint32_t b) {
-    return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
-  });
-  const size_t shared0 = out.segs.size();
-  std::vector<uint32_t> fill;  // used slots of each shared chunk
-  for (uint32_t c : small) {
-    const uint32_t sz = (uint32_t)(offsets[c + 1] - offsets[c]);
-    size_t b = 0;
-    while (b < fill.size() && fill[b] + sz > n) ++b;
-    if (b == fill.size()) {
-      fill.push_back(0);
-      out.segs.emplace_back();
-    }
-    out.first[c] = shared0 + b;
-    out.chunks[c] = 1;
-    out.base[c] = fill[b];
-    out.segs[shared0 + b].push_back(ChunkSeg{c, 0, sz});
-    fill[b] += sz;
-  }
-}
 
 int set_err(wally_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
@@ -459,8 +370,8 @@ void drop_graph(wally_ctx* c) {
   // a replay still in flight reads the descriptors and workspaces freed here
   if (c->graph_pending) (void)hipEventSynchronize(c->graph_done);
   c->graph_pending = false;
-  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-  c->graph_exec = nullptr;
+  for (hipGraphExec_t ex : c->graph_execs) (void)hipGraphExecDestroy(ex);
+  c->graph_execs.clear();
   c->graph_key = 0;
   dfree(c, c->graph_desc);
   c->graph_desc = nullptr;
@@ -562,68 +473,6 @@ KsArgs base_args(const wally_ctx* c, const WaveWork& s) {
   return a;
 }
 
-// Enqueue the whole scoring of one wave (queries qs[0..w)) on set s.
-// All queries must already be validated.
-// Descriptors of one wave: copy and baby items per query, giant items per
-// (query, chunk) ordered by plaintext chunk, tiles of giant items sharing a
-// chunk, split in sub-waves of at most B giant items.
-struct WavePlan {
-  int w = 0;
-  FoldCls cls{1, 0, 0, 0};  // fold class shared by the wave's clusters
-  size_t ng = 0, nt = 0;
-  std::vector<std::pair<size_t, size_t>> sub_tiles;  // per sub-wave: [first tile, end tile)
-};
-
-void plan_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w, CopyItem* copy, KsItem* baby,
-               KsItem* giant, MacTile* tiles, WavePlan& p) {
-  const uint64_t ctw = c->ctw();
-  p.cls = fold_cls(c, c->fold[qs[0]->cluster]);  // the waves of make_waves and serving are of one class
-  const FoldCls& fc = p.cls;
-  std::vector<std::pair<uint64_t, uint32_t>> order;  // (global chunk index, item)
-  std::vector<std::pair<int, uint32_t>> gq;           // (query slot, chunk)
-  for (int k = 0; k < w; ++k) {
-    const wally_query& q = *qs[k];
-    uint64_t* ctp = s.ctp + (uint64_t)k * c->g * ctw;
-    copy[k] = CopyItem{q.ct, ctp};
-    baby[k] = KsItem{q.key_baby, ctp, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    for (uint32_t ch = 0; ch < c->chunks[q.cluster]; ++ch) {
-      order.push_back({c->chunk_base[q.cluster] + ch, (uint32_t)gq.size()});
-      gq.push_back({k, ch});
-    }
-  }
-  std::stable_sort(order.begin(), order.end(),
-                   [](const std::pair<uint64_t, uint32_t>& a, const std::pair<uint64_t, uint32_t>& b) {
-                     return a.first < b.first;
-                   });
-  p.w = w;
-  p.ng = order.size();
-  p.nt = 0;
-  p.sub_tiles.clear();
-  for (size_t g0 = 0; g0 < p.ng; g0 += c->B) {
-    const size_t g1 = std::min(p.ng, g0 + (size_t)c->B);
-    const size_t t0 = p.nt;
-    for (size_t k = g0; k < g1; ++k) {
-      const auto& gi = gq[order[k].second];
-      const wally_query& q = *qs[gi.first];
-      const size_t slot = k - g0;
-      KsItem it{};
-      it.key = q.key_giant;
-      it.key_fold = q.key_fold;
-      it.fin = q.out + (uint64_t)gi.second * ctw;
-      it.pt = c->pt + c->chunk_pt[order[k].first];
-      it.ctp = s.ctp + (uint64_t)gi.first * c->g * ctw;
-      it.buf0 = s.R0 + slot * ctw;
-      it.buf1 = s.R1 + slot * ctw;
-      it.acc = fc.h == 1 && fc.B == 1 ? it.fin : s.ACC + slot * c->h * ctw;
-      giant[k] = it;
-      const bool start = k == g0 || order[k].first != order[k - 1].first || tiles[p.nt - 1].count >= c->tile_items;
-      if (start) tiles[p.nt++] = MacTile{(uint32_t)(k - g0), 0};
-      tiles[p.nt - 1].count++;
-    }
-    p.sub_tiles.push_back({t0, p.nt});
-  }
-}
-
 // Enqueue the kernels of a planned wave on stream st, reading the
 // descriptors from device memory.
 int launch_wave(wally_ctx* c, WaveWork& s, const WavePlan& p, const CopyItem* copy, const KsItem* baby,
@@ -688,12 +537,14 @@ int launch_wave(wally_ctx* c, WaveWork& s, const WavePlan& p, const CopyItem* co
   return WALLY_OK;
 }
 
+WaveBufs wave_bufs(const WaveWork& s) { return WaveBufs{s.ctp, s.R0, s.R1, s.ACC}; }
+
 // Eager path: plan into the set's pinned buffers, copy, launch on its stream.
 int enqueue_wave(wally_ctx* c, WaveWork& s, const wally_query* const* qs, int w) {
   // host descriptors may be rewritten only after the previous copy landed
   HIP_OK(c, hipEventSynchronize(s.staged));
   WavePlan p;
-  plan_wave(c, s, qs, w, s.copy_host, s.baby_host, s.giant_host, s.tile_host, p);
+  plan_wave(c, wave_bufs(s), qs, w, s.copy_host, s.baby_host, s.giant_host, s.tile_host, p);
   HIP_OK(c, hipMemcpyAsync(s.copy_dev, s.copy_host, w * sizeof(CopyItem), hipMemcpyHostToDevice, s.stream));
   HIP_OK(c, hipMemcpyAsync(s.baby_dev, s.baby_host, w * sizeof(KsItem), hipMemcpyHostToDevice, s.stream));
   HIP_OK(c, hipMemcpyAsync(s.giant_dev, s.giant_host, p.ng * sizeof(KsItem), hipMemcpyHostToDevice, s.stream));
@@ -1084,80 +935,30 @@ uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) 
   return h;
 }
 
-// Queries ordered by chunk (so a wave touches few plaintext chunks) and cut
-// into waves: up to B queries, of one cluster only on the plain path.
-void make_waves(wally_ctx* c, const wally_query* q, uint64_t nq, int path, std::vector<const wally_query*>& ord,
-                std::vector<std::pair<uint64_t, uint64_t>>& waves) {
-  ord.resize(nq);
-  for (uint64_t i = 0; i < nq; ++i) ord[i] = &q[i];
-  // by fold class (a wave runs one baby/giant split), then first chunk, then
-  // cluster: clusters that share a chunk land in the same waves and tiles
-  const std::vector<uint64_t>& fc = c->chunk_base;
-  const std::vector<uint32_t>& fo = c->fold;
-  std::stable_sort(ord.begin(), ord.end(), [&fc, &fo](const wally_query* a, const wally_query* b) {
-    if (fo[a->cluster] != fo[b->cluster]) return fo[a->cluster] < fo[b->cluster];
-    return fc[a->cluster] != fc[b->cluster] ? fc[a->cluster] < fc[b->cluster] : a->cluster < b->cluster;
-  });
-  waves.clear();
-  for (uint64_t i = 0; i < nq;) {
-    uint64_t j = i;
-    while (j < nq && j - i < (uint64_t)c->B && fo[ord[j]->cluster] == fo[ord[i]->cluster] &&
-           (path != WALLY_PATH_PLAIN || ord[j]->cluster == ord[i]->cluster))
-      ++j;
-    waves.push_back({i, j});
-    i = j;
-  }
-}
+// Graph path: the batch's waves cut into segments of at most kGraphSegWaves
+// waves; each segment (fork, its waves on the set streams, join) is captured
+// into a graph of its own that reads its descriptors from its part of one
+// device block, and a replay launches the segments in order on the caller's
+// stream.  A capture of about 1,000 waves in one graph (some 150k kernel
+// nodes, two chains of 75k) ended the process inside the capture; segments
+// keep every graph within the size of the graphs that run.
+constexpr size_t kGraphSegWaves = 48;
 
-// Graph path: descriptors of every wave in one device block, the whole batch
-// (fork, waves on the set streams, join) captured into one graph.
-int build_graph(wally_ctx* c, const std::vector<const wally_query*>& ord,
-                const std::vector<std::pair<uint64_t, uint64_t>>& waves) {
-  drop_graph(c);
-  const size_t nw = waves.size();
-  std::vector<WavePlan> plans(nw);
-  // sizes: copy/baby per query, giant/tile per (query, chunk)
-  size_t nq = ord.size(), ng = 0;
-  for (const wally_query* q : ord) ng += c->chunks[q->cluster];
-  const size_t bytes = nq * sizeof(CopyItem) + nq * sizeof(KsItem) + ng * sizeof(KsItem) + ng * sizeof(MacTile) + 256;
-  std::vector<unsigned char> host(bytes);
-  CopyItem* copy_h = (CopyItem*)host.data();
-  KsItem* baby_h = (KsItem*)(copy_h + nq);
-  KsItem* giant_h = baby_h + nq;
-  MacTile* tile_h = (MacTile*)(giant_h + ng);
-  int rc = dalloc(c, bytes, &c->graph_desc);
-  if (rc) return rc;
-  unsigned char* dbase = (unsigned char*)c->graph_desc;
-  std::vector<size_t> qoff(nw), goff(nw), toff(nw);
-  size_t qo = 0, go = 0, to = 0;
-  for (size_t wv = 0; wv < nw; ++wv) {
-    WaveWork& s = c->sets[wv % c->sets.size()];
-    const int w = (int)(waves[wv].second - waves[wv].first);
-    qoff[wv] = qo;
-    goff[wv] = go;
-    toff[wv] = to;
-    plan_wave(c, s, ord.data() + waves[wv].first, w, copy_h + qo, baby_h + qo, giant_h + go, tile_h + to, plans[wv]);
-    qo += w;
-    go += plans[wv].ng;
-    to += plans[wv].nt;
-  }
-  HIP_OK(c, hipMemcpy(dbase, host.data(), bytes, hipMemcpyHostToDevice));
-  const CopyItem* copy_d = (const CopyItem*)dbase;
-  const KsItem* baby_d = (const KsItem*)(copy_d + nq);
-  const KsItem* giant_d = baby_d + nq;
-  const MacTile* tile_d = (const MacTile*)(giant_d + ng);
-  if (!c->cap_stream) HIP_OK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-  HIP_OK(c, hipStreamSynchronize(c->cap_stream));
-  for (auto& s : c->sets) HIP_OK(c, hipStreamSynchronize(s.stream));
+int capture_segment(wally_ctx* c, const SegmentPlan& sp, const unsigned char* dbase, size_t w0,
+                    hipGraphExec_t* exec) {
+  const CopyItem* copy_d = (const CopyItem*)(dbase + sp.copy_at);
+  const KsItem* baby_d = (const KsItem*)(dbase + sp.baby_at);
+  const KsItem* giant_d = (const KsItem*)(dbase + sp.giant_at);
+  const MacTile* tile_d = (const MacTile*)(dbase + sp.tile_at);
   HIP_OK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
   c->capturing = true;
-  rc = WALLY_OK;
+  int rc = WALLY_OK;
   hipError_t e = hipEventRecord(c->fork, c->cap_stream);
   for (size_t k = 0; e == hipSuccess && k < c->sets.size(); ++k) e = hipStreamWaitEvent(c->sets[k].stream, c->fork, 0);
-  for (size_t wv = 0; e == hipSuccess && !rc && wv < nw; ++wv) {
-    WaveWork& s = c->sets[wv % c->sets.size()];
-    rc = launch_wave(c, s, plans[wv], copy_d + qoff[wv], baby_d + qoff[wv], giant_d + goff[wv], tile_d + toff[wv],
-                     s.stream);
+  for (size_t k = 0; e == hipSuccess && !rc && k < sp.plans.size(); ++k) {
+    WaveWork& s = c->sets[(w0 + k) % c->sets.size()];
+    rc = launch_wave(c, s, sp.plans[k], copy_d + sp.qoff[k], baby_d + sp.qoff[k], giant_d + sp.goff[k],
+                     tile_d + sp.toff[k], s.stream);
   }
   for (size_t k = 0; e == hipSuccess && !rc && k < c->sets.size(); ++k) {
     e = hipEventRecord(c->sets[k].done, c->sets[k].stream);
@@ -1174,16 +975,41 @@ int build_graph(wally_ctx* c, const std::vector<const wally_query*>& ord,
     if (graph) (void)hipGraphDestroy(graph);
     return set_err(c, WALLY_EDEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
   }
-  e = hipGraphInstantiate(&c->graph_exec, graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return set_err(c, WALLY_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
   return WALLY_OK;
 }
 
-// Largest batch the graph path captures, in waves (about 150 kernel nodes
-// each).  Captures of about 1,000 waves ended the process inside the score
-// call; the limit keeps the graph within the sizes that have run.
-constexpr int kMaxGraphWaves = 64;
+int build_graph(wally_ctx* c, const std::vector<const wally_query*>& ord,
+                const std::vector<std::pair<uint64_t, uint64_t>>& waves) {
+  drop_graph(c);
+  const auto segs = graph_segments(waves.size(), kGraphSegWaves);
+  auto bufs = [c](size_t wv) { return wave_bufs(c->sets[wv % c->sets.size()]); };
+  std::vector<SegmentPlan> plans(segs.size());
+  std::vector<std::vector<unsigned char>> blocks(segs.size());
+  std::vector<size_t> at(segs.size());
+  size_t total = 0;
+  for (size_t k = 0; k < segs.size(); ++k) {
+    plan_segment(c, ord, waves, segs[k].first, segs[k].second, bufs, blocks[k], plans[k]);
+    at[k] = total;
+    total += (plans[k].bytes + 255) / 256 * 256;
+  }
+  int rc = dalloc(c, std::max<size_t>(total, 256), &c->graph_desc);
+  if (rc) return rc;
+  unsigned char* dbase = (unsigned char*)c->graph_desc;
+  for (size_t k = 0; k < segs.size(); ++k)
+    HIP_OK(c, hipMemcpy(dbase + at[k], blocks[k].data(), plans[k].bytes, hipMemcpyHostToDevice));
+  if (!c->cap_stream) HIP_OK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIP_OK(c, hipStreamSynchronize(c->cap_stream));
+  for (auto& s : c->sets) HIP_OK(c, hipStreamSynchronize(s.stream));
+  for (size_t k = 0; k < segs.size(); ++k) {
+    hipGraphExec_t ex = nullptr;
+    if ((rc = capture_segment(c, plans[k], dbase + at[k], segs[k].first, &ex))) return rc;
+    c->graph_execs.push_back(ex);
+  }
+  return WALLY_OK;
+}
 
 int score_locked(wally_ctx* c, const wally_query* q, uint64_t nq, int path, hipStream_t user) {
   int rc;
@@ -1195,21 +1021,19 @@ int score_locked(wally_ctx* c, const wally_query* q, uint64_t nq, int path, hipS
     key = fnv1a(&c->B, sizeof c->B, key);
     key = fnv1a(&c->tile_items, sizeof c->tile_items, key);
     key ^= (uint64_t)c->sets.size() << 56;
-    if (!c->graph_exec || c->graph_key != key) {
+    if (c->graph_execs.empty() || c->graph_key != key) {
       std::vector<const wally_query*> ord;
       std::vector<std::pair<uint64_t, uint64_t>> waves;
       make_waves(c, q, nq, WALLY_PATH_BATCHED, ord, waves);
-      if (waves.size() > kMaxGraphWaves)
-        return set_err(c, WALLY_EINVAL,
-                       "graph path: the batch needs %zu waves of %d queries, at most %d are captured in one graph "
-                       "(split the batch or use the batched path)",
-                       waves.size(), c->B, kMaxGraphWaves);
-      if ((rc = build_graph(c, ord, waves))) return rc;
+      if ((rc = build_graph(c, ord, waves))) {
+        drop_graph(c);
+        return rc;
+      }
       c->graph_key = key;
     }
     // earlier eager work on the set streams shares the workspaces
     for (auto& s : c->sets) HIP_OK(c, hipStreamWaitEvent(user, s.done, 0));
-    HIP_OK(c, hipGraphLaunch(c->graph_exec, user));
+    for (hipGraphExec_t ex : c->graph_execs) HIP_OK(c, hipGraphLaunch(ex, user));
     // later eager work may come on another stream: it waits for this event
     if (!c->graph_done) HIP_OK(c, hipEventCreateWithFlags(&c->graph_done, hipEventDisableTiming));
     HIP_OK(c, hipEventRecord(c->graph_done, user));

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "items.h"
+
 namespace wally {
 
 constexpr int kMaxLimbs = 8;
@@ -26,24 +28,6 @@ struct DevModuli {
   const ulonglong2* inv[kMaxMod];          // (psi^-brv(k), Shoup)
 };
 
-// One key switch (CtRotate) work item.  Input and output are chosen by the
-// launch (KsArgs::in_sel / out_sel): 0 = buf0 + off, 1 = buf1 + off, 2 = fin + off.
-struct KsItem {
-  const uint64_t* key;   // [L][2][L+1][n]
-  uint64_t* buf0;
-  uint64_t* buf1;
-  uint64_t* fin;
-  const uint64_t* pt;    // plaintexts of the chunk [d_pad][L][n] (giant steps)
-  const uint64_t* ctp;   // rotated query copies [g][2][L][n] (giant steps)
-  uint64_t* acc;         // giant-step sums [h][2][L][n] (giant steps); sel 3 reads it
-  const uint64_t* key_fold;  // fold keys [log2 B][L][2][L+1][n] (folded layout)
-};
-
-// A tile of giant items that share one plaintext chunk (consecutive items).
-struct MacTile {
-  uint32_t first, count;
-};
-
 struct KsArgs {
   int log_n, L;
   uint32_t gal;
@@ -60,10 +44,6 @@ struct KsArgs {
   uint64_t* D;  // scratch [items][L+1][L][n]: extended digits
 };
 
-struct CopyItem {
-  const uint64_t* src;
-  uint64_t* dst;
-};
 
 struct EncodeJob {
   const void* emb;      // first entry of the chunk, row-major [.][d], int8 or int16 (EncodeArgs::wide)

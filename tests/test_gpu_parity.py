@@ -341,19 +341,31 @@ def test_graph_then_eager_on_another_stream(tiny_workload):
         c.close()
 
 
-def test_graph_refuses_batches_over_the_wave_limit(tiny_workload):
-    """More than 64 waves in one graph is refused before anything is captured."""
-    from paper_2406_06761_amd.wally import EINVAL, PATH_GRAPH, WallyError, query_array
+def test_graph_in_segments_matches_oracle(tiny_workload):
+    """A batch of 100 one-query waves is captured as three graphs (at most 48
+    waves each) and replayed segment after segment; every replay, with eager
+    work between them, gives the oracle's words for every query."""
+    from paper_2406_06761_amd.wally import PATH_BATCHED, PATH_GRAPH, query_array, to_host
 
     o, w, emb, offs, qv, packets, ref = tiny_workload
-    c = _ctx("tiny", max_batch=1, wave_sets=1)
+    c = _ctx("tiny", max_batch=1, wave_sets=2)
     try:
         c.encode_clusters(emb, offs)
         q, outs, keep = _tiny_queries(o, w, packets)
-        big = np.concatenate([q] * 5)[:65]  # 65 one-query waves
-        with pytest.raises(WallyError) as e:
-            c.score_batch(big, path=PATH_GRAPH)
-        assert e.value.code == EINVAL and "64" in str(e.value)
+        nq, m = 100, len(w.targets)
+        big_out = torch.zeros((nq, 1, 2, o.L, o.n), dtype=torch.int64, device="cuda")
+        big = query_array(np.resize(w.targets, nq), [int(q[i % m]["ct"]) for i in range(nq)],
+                          [int(q[i % m]["key_baby"]) for i in range(nq)],
+                          [int(q[i % m]["key_giant"]) for i in range(nq)],
+                          [big_out[i].data_ptr() for i in range(nq)])
+        for rep in range(3):
+            big_out.zero_()
+            torch.cuda.synchronize()
+            c.score_batch(big, path=PATH_GRAPH if rep < 2 else PATH_BATCHED)
+            torch.cuda.synchronize()
+            got = to_host(big_out)
+            for i in range(nq):
+                assert (got[i] == ref[i % m]).all(), (rep, i)
     finally:
         c.close()
 
