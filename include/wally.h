@@ -274,6 +274,26 @@ int wally_pir_answer(wally_ctx* ctx, const wally_pir_query* q, uint64_t nq, void
  * are reported before anything is enqueued (EINVAL); ESTATE while serving. */
 int wally_score_batch(wally_ctx* ctx, const wally_query* q, uint64_t nq, int path, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the batched
+ * path of wally_score_batch with every workspace row and descriptor table in
+ * one static device array of WALLY_STATIC_SCRATCH_BYTES, which each GPU the
+ * library runs on holds from the first context on it until the process ends.
+ * The call allocates nothing (no device memory, no host memory; the pinned
+ * descriptor staging and events it uses are made by wally_params_init).
+ * Queries run in waves of as many as the array holds, one after another on
+ * hip_stream (at n = 8192, L = 4, d_pad = 256 a query needs about 19 MiB, so
+ * waves hold 13); the words equal wally_score_batch's.  The caller passes the
+ * queries and their output buffers as for wally_score_batch.
+ * The array keeps the last call's contents and is shared by every context on
+ * the GPU: a call of one context is ordered after that context's previous
+ * static call (whatever its stream), but calls of different contexts on one
+ * GPU that overlap in time race.  Returns once enqueued.  EINVAL for invalid
+ * queries, or when one query's workspace does not fit in the array at these
+ * parameters (nothing is enqueued); ESTATE before an encode or while serving. */
+#define WALLY_STATIC_SCRATCH_BYTES (256ull << 20)
+int wally_score_batch_static(wally_ctx* ctx, const wally_query* q, uint64_t nq, void* hip_stream);
+
 /* One configuration timed by wally_tune. */
 typedef struct {
   uint32_t max_batch;  /* queries per wave                                  */

@@ -242,6 +242,13 @@ struct wally_ctx {
   uint64_t* comp_scratch = nullptr;
   uint64_t comp_scratch_chunks = 0;
   hipEvent_t comp_done = nullptr;  // recorded after each compression call
+  // wally_score_batch_static: the device's static scratch, pinned host
+  // staging for the descriptors of two waves, and their events
+  unsigned char* static_scratch = nullptr;
+  unsigned char* static_host[2] = {};
+  hipEvent_t static_staged[2] = {};
+  hipEvent_t static_done = nullptr;  // after each static call; the next one waits for it
+  bool static_pending = false;
   // waves
   int B = 0;
   int n_sets = 2;
@@ -362,6 +369,40 @@ hipError_t keyswitch(wally_ctx* c, const KsItem* items, int n, const KsArgs& a, 
     e = timed(c, st, WALLY_KERNEL_MODDOWN, n, [&] { return launch_ks_moddown(items, n, a, c->M, st); });
   return e;
 }
+
+// Scratch of wally_score_batch_static, for callers that cannot allocate:
+// every workspace row and descriptor table of its waves.  Each GPU holds its
+// own copy for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress gives on that device (static_scratch_of).
+static __device__ __align__(256) unsigned char scratch[WALLY_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+// The device address of `scratch` on device dev (current), looked up once per device.
+hipError_t static_scratch_of(int dev, unsigned char** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = (unsigned char*)p;
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+
+// Descriptor capacity of one static wave (pinned host staging and device
+// table alike): copy and baby items per query, giant items and tiles.
+constexpr uint64_t kStaticQueries = 1024, kStaticItems = 4096;
+constexpr uint64_t kStaticCopyAt = 0, kStaticBabyAt = kStaticCopyAt + kStaticQueries * sizeof(CopyItem),
+                   kStaticGiantAt = kStaticBabyAt + kStaticQueries * sizeof(KsItem),
+                   kStaticTileAt = kStaticGiantAt + kStaticItems * sizeof(KsItem),
+                   kStaticDescBytes = (kStaticTileAt + kStaticItems * sizeof(MacTile) + 255) / 256 * 256;
+static_assert(kStaticDescBytes < WALLY_STATIC_SCRATCH_BYTES / 8, "descriptor tables take a small part of the scratch");
 
 constexpr int kMaxWaveQueries = 1 << 15;
 constexpr size_t kMaxWaveItems = (size_t)1 << 15;
@@ -725,6 +766,18 @@ int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
     wally_destroy(c);
     return WALLY_EDEVICE;
   }
+  // the static scratch of this device, and what its entry point needs on the host
+  if (static_scratch_of(c->device, &c->static_scratch) != hipSuccess ||
+      hipEventCreateWithFlags(&c->static_done, hipEventDisableTiming) != hipSuccess) {
+    wally_destroy(c);
+    return WALLY_EDEVICE;
+  }
+  for (int k = 0; k < 2; ++k)
+    if (hipHostMalloc((void**)&c->static_host[k], kStaticDescBytes, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->static_staged[k], hipEventDisableTiming) != hipSuccess) {
+      wally_destroy(c);
+      return WALLY_EDEVICE;
+    }
   for (int m = 0; m < nm; ++m) {
     const ulonglong2* base = reinterpret_cast<const ulonglong2*>((uint64_t*)c->tables + (size_t)m * 4 * c->n);
     c->M.fwd[m] = base;
@@ -1080,6 +1133,108 @@ int wally_score_batch(wally_ctx* c, const wally_query* q, uint64_t nq, int path,
   return score_locked(c, q, nq, path, (hipStream_t)hip_stream);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Waves of queries scored in the static scratch: descriptor tables first,
+// then one wave's workspace rows for `bs` queries.  c->B is bs while this runs.
+int score_static_waves(wally_ctx* c, const wally_query* q, uint64_t nq, uint64_t bs, hipStream_t st) {
+  const uint64_t n = c->n, L = c->L, ctw = c->ctw(), w8 = 8;
+  unsigned char* at = c->static_scratch + kStaticDescBytes;
+  auto carve = [&at](uint64_t bytes) {
+    unsigned char* p = at;
+    at += (bytes + 255) / 256 * 256;
+    return (uint64_t*)p;
+  };
+  WaveWork ws;
+  ws.ctp = carve(w8 * bs * c->g * ctw);
+  ws.X = carve(w8 * bs * L * n);
+  ws.U = carve(w8 * bs * 2 * (L + 1) * n);
+  ws.Y = carve(w8 * bs * 2 * n);
+  ws.D = carve(w8 * bs * (L + 1) * L * n);
+  ws.R0 = carve(w8 * bs * ctw);
+  ws.R1 = carve(w8 * bs * ctw);
+  ws.ACC = carve(w8 * bs * c->h * ctw);
+  if (at > c->static_scratch + WALLY_STATIC_SCRATCH_BYTES)
+    return set_err(c, WALLY_EINVAL, "static scratch overrun (%llu queries per wave)", (unsigned long long)bs);
+  unsigned char* dd = c->static_scratch;
+  const CopyItem* copy_d = (const CopyItem*)(dd + kStaticCopyAt);
+  const KsItem* baby_d = (const KsItem*)(dd + kStaticBabyAt);
+  const KsItem* giant_d = (const KsItem*)(dd + kStaticGiantAt);
+  const MacTile* tile_d = (const MacTile*)(dd + kStaticTileAt);
+  // the previous static call of this context (whatever its stream) is done with the scratch
+  if (c->static_pending) HIP_OK(c, hipStreamWaitEvent(st, c->static_done, 0));
+  std::vector<const wally_query*> ord;
+  std::vector<std::pair<uint64_t, uint64_t>> waves;
+  make_waves(c, q, nq, WALLY_PATH_BATCHED, ord, waves);
+  for (size_t wv = 0; wv < waves.size(); ++wv) {
+    const int w = (int)(waves[wv].second - waves[wv].first);
+    const int hb = (int)(wv & 1);
+    unsigned char* hh = c->static_host[hb];
+    // this staging half was last read by the copy of wave wv - 2
+    HIP_OK(c, hipEventSynchronize(c->static_staged[hb]));
+    WavePlan p;
+    const wally_query* const* qs = ord.data() + waves[wv].first;
+    if (wave_giant_items(c, qs, w) > kStaticItems)
+      return set_err(c, WALLY_EINVAL, "static wave of %d queries has more than %llu giant items", w,
+                     (unsigned long long)kStaticItems);
+    plan_wave(c, wave_bufs(ws), qs, w, (CopyItem*)(hh + kStaticCopyAt), (KsItem*)(hh + kStaticBabyAt),
+              (KsItem*)(hh + kStaticGiantAt), (MacTile*)(hh + kStaticTileAt), p);
+    // same stream: these copies land after the previous wave's kernels read the tables
+    HIP_OK(c, hipMemcpyAsync(dd + kStaticCopyAt, hh + kStaticCopyAt, w * sizeof(CopyItem), hipMemcpyHostToDevice, st));
+    HIP_OK(c, hipMemcpyAsync(dd + kStaticBabyAt, hh + kStaticBabyAt, w * sizeof(KsItem), hipMemcpyHostToDevice, st));
+    HIP_OK(c, hipMemcpyAsync(dd + kStaticGiantAt, hh + kStaticGiantAt, p.ng * sizeof(KsItem), hipMemcpyHostToDevice,
+                             st));
+    HIP_OK(c, hipMemcpyAsync(dd + kStaticTileAt, hh + kStaticTileAt, p.nt * sizeof(MacTile), hipMemcpyHostToDevice,
+                             st));
+    HIP_OK(c, hipEventRecord(c->static_staged[hb], st));
+    int rc = launch_wave(c, ws, p, copy_d, baby_d, giant_d, tile_d, st);
+    if (rc) return rc;
+  }
+  HIP_OK(c, hipEventRecord(c->static_done, st));
+  c->static_pending = true;
+  return WALLY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wally_score_batch_static(wally_ctx* c, const wally_query* q, uint64_t nq, void* hip_stream) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->K == 0) return set_err(c, WALLY_ESTATE, "no clusters encoded");
+  if (c->serving) return set_err(c, WALLY_ESTATE, "a serving session owns the device queues");
+  if (nq == 0) return WALLY_OK;
+  if (!q) return set_err(c, WALLY_EINVAL, "null query array");
+  if (!c->static_scratch) return set_err(c, WALLY_ESTATE, "no static scratch on device %d", c->device);
+  for (uint64_t i = 0; i < nq; ++i)
+    if ((rc = validate_query(c, q[i], i))) return rc;
+  // queries per wave: as many workspaces as the scratch holds beside the tables
+  const uint64_t n = c->n, L = c->L, ctw = c->ctw(), w8 = 8, align = 8 * 256;
+  const uint64_t per_query =
+      w8 * (c->g * ctw + L * n + 2 * (L + 1) * n + 2 * n + (L + 1) * L * n + 2 * ctw + c->h * ctw);
+  const uint64_t room = WALLY_STATIC_SCRATCH_BYTES - kStaticDescBytes - align;
+  const uint64_t max_chunks = std::max<uint32_t>(1, c->max_chunks);
+  const uint64_t bs = std::min({room / per_query, kStaticQueries, kStaticItems / max_chunks});
+  if (bs == 0)
+    return set_err(c, WALLY_EINVAL,
+                   "the static scratch (%llu bytes) cannot hold one query: its workspace needs %llu bytes and its "
+                   "%llu chunks %llu giant items (at most %llu)",
+                   (unsigned long long)WALLY_STATIC_SCRATCH_BYTES, (unsigned long long)per_query,
+                   (unsigned long long)max_chunks, (unsigned long long)max_chunks, (unsigned long long)kStaticItems);
+  const int saved_b = c->B;
+  const bool saved_timing = c->timing;
+  c->B = (int)bs;
+  c->timing = false;
+  rc = score_static_waves(c, q, nq, bs, (hipStream_t)hip_stream);
+  c->B = saved_b;
+  c->timing = saved_timing;
+  return rc;
+}
+
 int wally_tune(wally_ctx* c, const wally_query* q, uint64_t nq, const uint32_t* batches, const uint32_t* sets,
                const uint32_t* tiles, wally_tune_entry* out, uint32_t max_out, uint32_t* n_out) {
   int rc = check_live(c);
@@ -1277,6 +1432,11 @@ void wally_destroy(wally_ctx* c) {
   if (c->graph_done) (void)hipEventDestroy(c->graph_done);
   if (c->comp_done) (void)hipEventDestroy(c->comp_done);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (int k = 0; k < 2; ++k) {
+    if (c->static_host[k]) (void)hipHostFree(c->static_host[k]);
+    if (c->static_staged[k]) (void)hipEventDestroy(c->static_staged[k]);
+  }
+  if (c->static_done) (void)hipEventDestroy(c->static_done);
   for (auto& t : c->timers) c->ev_pool.push_back(t.a), c->ev_pool.push_back(t.b);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;

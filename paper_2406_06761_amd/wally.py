@@ -58,11 +58,12 @@ assert ctypes.sizeof(Query) == QUERY_DTYPE.itemsize
 
 PIR_QUERY_DTYPE = np.dtype([("ct", "<u8"), ("keys", "<u8"), ("out", "<u8")])
 PIR_PAPER_KEYS = 0xFFFFFFFF  # first_key_level: the paper's choice
+STATIC_SCRATCH_BYTES = 256 << 20  # WALLY_STATIC_SCRATCH_BYTES
 
 # every symbol declared in include/wally.h and include/wally_diag.h
 SYMBOLS = [
     "wally_params_init", "wally_params_query", "wally_encode_clusters", "wally_cluster_info", "wally_cluster_fold",
-    "wally_score_batch",
+    "wally_score_batch", "wally_score_batch_static",
     "wally_tune", "wally_compress_responses", "wally_encode_clusters_i16",
     "wally_pir_encode", "wally_pir_info", "wally_pir_answer",
     "wally_serve_start", "wally_serve_submit", "wally_serve_poll", "wally_serve_stop", "wally_strerror",
@@ -106,6 +107,7 @@ def load():
         "wally_cluster_fold": ([vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32),
                                 ctypes.POINTER(u64), ctypes.POINTER(u64)], i32),
         "wally_score_batch": ([vp, vp, u64, i32, vp], i32),
+        "wally_score_batch_static": ([vp, vp, u64, vp], i32),
         "wally_pir_encode": ([vp, vp, u32, u32, u32], i32),
         "wally_pir_info": ([vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64)], i32),
         "wally_pir_answer": ([vp, vp, u64, vp], i32),
@@ -247,6 +249,13 @@ class Context:
         queries = np.ascontiguousarray(queries, dtype=QUERY_DTYPE)
         self._check(self.lib.wally_score_batch(self.h, queries.ctypes.data, len(queries), path,
                                                _stream_handle(stream)), "wally_score_batch")
+
+    def score_batch_static(self, queries: np.ndarray, stream=None):
+        """wally_score_batch_static: the batched path in the library's static
+        scratch (no allocation)."""
+        queries = np.ascontiguousarray(queries, dtype=QUERY_DTYPE)
+        self._check(self.lib.wally_score_batch_static(self.h, queries.ctypes.data, len(queries),
+                                                      _stream_handle(stream)), "wally_score_batch_static")
 
     def tune(self, queries: np.ndarray, batches=(), sets=(), tiles=()):
         """Autotune the batched schedule on these queries; returns the timings
