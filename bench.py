@@ -33,31 +33,62 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 39.3e12 lane-instructions/s
-INSTR_PER_MODMUL = 20                       # VALU instructions of one compiled 54-bit Shoup butterfly
+# VALU instructions per unit of work in the compiled kernels (gfx950 assembly
+# of kernels.hip): a forward lazy butterfly 17 (its register-resident loop:
+# 544 per 32 butterflies), an inverse one 21 (671 per 32), a Shoup scaling 13,
+# a giant-step multiply-accumulate with 27-bit split operands 9.25 (296 per 32
+# products, the per-output fold included), a key inner-product step with a
+# 128-bit sum 31 (the straight-line kernel body: 497 per 16 products,
+# reductions and addressing included).
+INSTR = {"bfly_fwd": 17.0, "bfly_inv": 21.0, "scale": 13.0, "mac27": 9.25, "mac128": 31.0}
+INSTR_PER_MODMUL = INSTR["bfly_fwd"]        # the dominant kernel's unit: a forward butterfly
 HBM_PEAK = 8.0e12
+EPOCH_S = 10.0  # shortest epoch of the paper's serving table: every query must finish within it
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def per_item_work(kernel, n, L, g, h):
-    """Algorithmic modular multiply(-accumulate)s per work item of each kernel.
-    One NTT = (n/2) log2 n butterflies; an inverse NTT adds n scalings."""
+def per_item_units(kernel, n, L, g, h):
+    """Algorithmic units per work item of each kernel, by kind.  One NTT is
+    (n/2) log2 n butterflies; an inverse NTT adds n scalings."""
     bf = n // 2 * int(math.log2(n))
-    if kernel == "ks_digits":
-        return L * (bf + n)
-    if kernel == "ks_extend":
-        return L * L * bf
-    if kernel == "ks_inner":
-        return 2 * L * (L + 1) * n
-    if kernel == "ks_pinv":
-        return 2 * (bf + n)
-    if kernel == "ks_moddown":
-        return 2 * L * bf + 2 * L * n
-    if kernel == "mac":
-        return 2 * g * L * n * h
-    return 0
+    return {
+        "ks_digits": {"bfly_inv": L * bf, "scale": L * n},
+        "ks_extend": {"bfly_fwd": L * L * bf},
+        "ks_inner": {"mac128": 2 * L * (L + 1) * n},
+        "ks_pinv": {"bfly_inv": 2 * bf, "scale": 2 * n},
+        "ks_moddown": {"bfly_fwd": 2 * L * bf, "scale": 2 * L * n},
+        "mac": {"mac27": 2 * g * L * n * h},
+    }.get(kernel, {})
+
+
+def per_item_work(kernel, n, L, g, h):
+    """Algorithmic modular multiply(-accumulate)s per work item of each kernel."""
+    return sum(per_item_units(kernel, n, L, g, h).values())
+
+
+def per_item_instr(kernel, n, L, g, h):
+    """VALU lane-instructions per work item at the compiled cost of each unit."""
+    return sum(v * INSTR[k] for k, v in per_item_units(kernel, n, L, g, h).items())
+
+
+def host_cpu():
+    """CPU model and the CPUs this process may run on."""
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        visible = len(os.sched_getaffinity(0))
+    except AttributeError:
+        visible = os.cpu_count() or 1
+    return model, visible
 
 
 def inner_bytes(n, L):
@@ -206,7 +237,9 @@ def serve_rates(ctx, w, chunks, cts, kbs, kgs, pool, rates, duration, log_every=
              "p50_ms": float(np.percentile(lat_ms, 50)) if len(lat) else None,
              "p99_ms": float(np.percentile(lat_ms, 99)) if len(lat) else None,
              "sustained_scores_per_s": scores_done / elapsed, "sustained_qps": len(lat) / elapsed,
-             "deferred_arrivals": len(deferred), "admission_refusals": refused, "wall_s": elapsed}
+             "deferred_arrivals": len(deferred), "admission_refusals": refused, "wall_s": elapsed,
+             "p99_within_epoch": bool(len(lat) and np.percentile(lat_ms, 99) < EPOCH_S * 1e3),
+             "over_capacity": bool(len(lat) and len(lat) / elapsed < 0.98 * rate)}
         log(f"serve {rate:.0f} QPS: p50 {r['p50_ms']:.1f} ms p99 {r['p99_ms']:.1f} ms, "
             f"{r['sustained_qps']:.0f} QPS sustained, {len(deferred)} arrivals deferred by admission")
         results.append(r)
@@ -502,9 +535,14 @@ def main():
     ap.add_argument("--fold-only", action="store_true", help="with --folded: skip the other layout's leg")
     ap.add_argument("--pir", action="store_true", help="index PIR (metadata fetch, paper 4.2) instead")
     ap.add_argument("--pir-queries", type=int, default=1024)
+    ap.add_argument("--batch500k-steps", type=int, default=1,
+                    help="paper workload: timed steps (after one warm-up) of the 500k-query batch on the same index, "
+                         "batched path (0 = skip)")
+    ap.add_argument("--batch500k-graph", action="store_true",
+                    help="also time the 500k batch on the graph path (captured in segments)")
     ap.add_argument("--fold-steps", type=int, default=2,
                     help="timed steps of the folded layout after the paper layout's legs (0 = skip)")
-    ap.add_argument("--fold-serve-rates", default="20000",
+    ap.add_argument("--fold-serve-rates", default="20000,50000",
                     help="Poisson rates (QPS) served on the folded layout when serving is measured ('' = skip)")
     args = ap.parse_args()
     if args.serve_rates is None:
@@ -644,7 +682,7 @@ def main():
         avg_ms = total_ms / max(launches, 1)
         items_per_launch = items / max(launches, 1)
         peak = PEAK_VALU_LANE_OPS / INSTR_PER_MODMUL
-        step_work = sum(kstats[k][1] * work[k] for k in kstats) / args.steps
+        step_instr = sum(kstats[k][1] * per_item_instr(k, n, L, info.g, info.h) for k in kstats) / args.steps
         if dom == "ks_inner":  # streams the key: HBM bound
             achieved = inner_bytes(n, L) * items_per_launch / (avg_ms * 1e-3)
             roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
@@ -653,10 +691,15 @@ def main():
         else:
             achieved = work[dom] * items_per_launch / (avg_ms * 1e-3)
             roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e9, "peak": peak / 1e9,
-                        "unit": "Gmodmul/s", "frac": achieved / peak, "traffic": None, "work_per_item": work[dom]}
+                        "unit": "Gbutterfly/s", "frac": achieved / peak, "traffic": None, "work_per_item": work[dom],
+                        "peak_derivation": "256 CU x 64 lanes x 2.4 GHz / 17 VALU instructions per compiled "
+                                           "forward butterfly"}
         roofline.update({"avg_launch_ms": avg_ms, "items_per_launch": items_per_launch,
-                         "path_gmodmul_per_s": step_work / (ms_per_step * 1e-3) / 1e9,
-                         "path_frac": step_work / (ms_per_step * 1e-3) / peak})
+                         "path_frac": step_instr / (ms_per_step * 1e-3) / PEAK_VALU_LANE_OPS,
+                         "path_frac_method": "VALU lane-instructions of the path's algorithmic work (butterflies, "
+                                             "scalings, 27-bit-split and 128-bit multiply-accumulates at their "
+                                             "compiled instruction counts) per step / (step time x 39.3e12)",
+                         "instr_per_unit": INSTR})
         for k, (nl, it, ms) in kstats.items():
             log(f"  {k:11s} launches {nl:7d} items {it:9d} total {ms:9.1f} ms avg {ms / max(nl, 1):.3f} ms")
 
@@ -698,7 +741,6 @@ def main():
             ctx.diag_rotate(cts[:cnt], kbs[:cnt], out_i, r & 1)
         ist = ctx.kernel_stats()
         ctx.kernel_timing(False)
-        peak = PEAK_VALU_LANE_OPS / INSTR_PER_MODMUL
         isolated = {}
         for k, (nl, it, ms) in ist.items():
             if not nl:
@@ -709,12 +751,29 @@ def main():
                          frac=inner_bytes(n, L) * it / (ms * 1e-3) / HBM_PEAK)
             else:
                 w_ = per_item_work(k, n, L, info.g, info.h)
-                e.update(bound="alu", achieved_gmodmul=w_ * it / (ms * 1e-3) / 1e9, frac=w_ * it / (ms * 1e-3) / peak)
+                ins = per_item_instr(k, n, L, info.g, info.h)
+                e.update(bound="alu", achieved_gunits=w_ * it / (ms * 1e-3) / 1e9,
+                         frac=ins * it / (ms * 1e-3) / PEAK_VALU_LANE_OPS)
             isolated[k] = e
             log(f"  isolated {k:11s} {e['ms_per_launch']:.3f} ms per launch of {e['items_per_launch']:.0f} items, "
                 f"frac {e['frac']:.3f}")
+        # the measured peak of the transforms' arithmetic: the register-resident
+        # butterfly loop (wally_diag_bfly_rate) forward and inverse
+        bout = torch.empty(4096 * 256 * 16, dtype=torch.int64, device="cuda")
+        measured = {}
+        for inv in (0, 1):
+            ctx.bfly_rate(inv, 4096, 50, bout)
+            bf, bms = ctx.bfly_rate(inv, 4096, 400, bout)
+            measured["inverse" if inv else "forward"] = bf / (bms * 1e-3)
+        del bout
+        log(f"butterfly rate, register-resident: forward {measured['forward']:.4g}/s, "
+            f"inverse {measured['inverse']:.4g}/s")
         if roofline is not None:
             roofline["isolated"] = isolated
+            if roofline["bound"] == "alu":
+                roofline["peak_measured"] = measured["forward"] / 1e9
+                roofline["frac_of_measured_peak"] = roofline["achieved"] * 1e9 / measured["forward"]
+            roofline["bfly_rate_measured"] = measured
             traffic = stored_traffic(roofline["kernel"], preset_name)
             if traffic is not None:
                 roofline["traffic"] = traffic * roofline["items_per_launch"]
@@ -731,20 +790,10 @@ def main():
                     "frac": ks_bytes / (ms_per_step * 1e-3) / HBM_PEAK}
 
     graph = None
-    graph_b = None
-    b_now = tuned["chosen"]["max_batch"] if tuned else (args.max_batch or 512)
+    graph_b = tuned["chosen"]["max_batch"] if tuned else (args.max_batch or 512)
     run_graph = args.graph_steps > 0
-    if run_graph and -(-nq // b_now) > 64:
-        # the library captures at most 64 waves per graph: larger waves for this leg
-        graph_b = 1 << max(0, (-(-nq // 64) - 1).bit_length())
-        if graph_b > 2048:  # workspaces of such waves would not fit beside the index
-            log(f"graph path skipped: {nq} queries need waves of {graph_b}")
-            run_graph, graph_b = False, None
-        else:
-            sets_now = tuned["chosen"]["wave_sets"] if tuned else (args.wave_sets or 2)
-            tile_now = tuned["chosen"]["tile_items"] if tuned else 8
-            ctx.tune(q[: min(2048, nq)], batches=(graph_b,), sets=(sets_now,), tiles=(tile_now,))
-            log(f"graph path: waves of {graph_b} queries ({-(-nq // graph_b)} waves)")
+    if run_graph:
+        log(f"graph path: waves of {graph_b} queries ({-(-nq // graph_b)} waves, captured in segments of at most 48)")
     if run_graph:
         t0 = time.perf_counter()
         ctx.score_batch(q, path=PATH_GRAPH)  # capture + first replay
@@ -773,6 +822,54 @@ def main():
     if args.serve_rates:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         serving = serve_rates(ctx, w, chunks, cts, kbs, kgs, pool, rates, args.serve_seconds)
+
+    # The 500k-query batch (503,710 with the fakes) on the same resident index:
+    # one warm-up and the timed steps on the batched path.  Its responses
+    # (~258 GB) do not fit beside the index, so queries share a ring of
+    # response chunk slots.
+    batch500k = None
+    if args.workload == "paper" and args.batch500k_steps > 0:
+        w5 = synth.paper_workload(n_real=500_000, name="batch500k")
+        nq5 = len(w5.targets)
+        qc5 = chunks[w5.targets].astype(np.int64)
+        ring5 = 16384
+        off5 = np.zeros(nq5, dtype=np.int64)
+        off5[1:] = np.cumsum(qc5)[:-1]
+        off5 %= ring5 - int(chunks.max())
+        outs5 = torch.empty(ring5 * ctw, dtype=torch.int64, device="cuda")
+        pidx5 = np.arange(nq5) % pool
+        q5 = query_array(w5.targets, cts.data_ptr() + pidx5 * cts[0].numel() * 8,
+                         kbs.data_ptr() + pidx5 * kbs[0].numel() * 8, kgs.data_ptr() + pidx5 * kgs[0].numel() * 8,
+                         outs5.data_ptr() + off5 * ctw * 8)
+        scores5 = int(w5.sizes[w5.targets].sum())
+        t0 = time.perf_counter()
+        ctx.score_batch(q5, path=PATH_BATCHED)
+        torch.cuda.synchronize()
+        log(f"batch500k: warm-up {time.perf_counter() - t0:.1f} s ({nq5} queries)")
+        t0 = time.perf_counter()
+        for i in range(args.batch500k_steps):
+            ctx.score_batch(q5, path=PATH_BATCHED)
+            torch.cuda.synchronize()
+            log(f"batch500k: step {i} done at {time.perf_counter() - t0:.1f} s")
+        dt5 = (time.perf_counter() - t0) / args.batch500k_steps
+        batch500k = {"queries": nq5, "real_queries": w5.n_real, "scores_per_step": scores5,
+                     "steps": args.batch500k_steps, "ms_per_step": dt5 * 1e3, "scores_per_s": scores5 / dt5,
+                     "queries_per_s": nq5 / dt5, "response_ring_slots": ring5, "graph_path": None}
+        if args.batch500k_graph:
+            t0 = time.perf_counter()
+            ctx.score_batch(q5, path=PATH_GRAPH)  # capture in segments + first replay
+            torch.cuda.synchronize()
+            cap = time.perf_counter() - t0
+            log(f"batch500k graph: capture + first replay {cap:.1f} s")
+            t0 = time.perf_counter()
+            ctx.score_batch(q5, path=PATH_GRAPH)
+            torch.cuda.synchronize()
+            g5 = time.perf_counter() - t0
+            batch500k["graph_path"] = {"capture_and_first_replay_s": cap, "ms_per_step": g5 * 1e3,
+                                       "scores_per_s": scores5 / g5}
+            log(f"batch500k graph: {g5:.1f} s per replay")
+        log(f"batch500k: {dt5 * 1e3:.0f} ms per batch, {scores5 / dt5:.4g} scores/s")
+        del outs5, q5
 
     # Folded small-cluster layout (not in the paper) on the same batch: the
     # per-cluster index is dropped first, the folded one encoded, and the same
@@ -836,9 +933,12 @@ def main():
 
     cpu = None
     if not args.no_cpu and args.cpu_sample > 0:
-        threads = min(16, os.cpu_count() or 1)
+        model, visible = host_cpu()
+        # every host CPU this process may use, up to the 16 a one-GPU share of the box grants
+        threads = min(16, visible)
         cpu = cpu_baseline(w, args.cpu_sample if args.workload != "tiny" else min(16, nq), threads, preset_name)
-        log(f"cpu oracle: {cpu['value']:.4g} scores/s on {threads} threads")
+        cpu.update({"cpu_model": model, "cpus_visible": visible})
+        log(f"cpu oracle: {cpu['value']:.4g} scores/s on {threads} threads ({model}, {visible} CPUs visible)")
 
     line = {
         "metric": "encrypted query-entry scores/sec (batched path)",
@@ -870,6 +970,9 @@ def main():
         "tuned": tuned,
         "response_compression": compress,
         "serving": serving,
+        "serving_capacity_qps": max((r["sustained_qps"] for r in serving), default=None) if serving else None,
+        "epoch_s": EPOCH_S,
+        "batch500k": batch500k,
         "roofline": roofline,
         "kernels_ms": {k: v[2] for k, v in kstats.items()},
         "folded_layout": folded,

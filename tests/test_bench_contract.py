@@ -32,3 +32,21 @@ def test_work_per_item_and_inner_bytes():
     assert ks == 30 * bf + (L + 2) * n + 2 * L * (L + 1) * n + 2 * L * n == 2_039_808
     # key 2.5 MiB + extended digits 1.25 MiB in, inner products 640 KiB out
     assert bench.inner_bytes(n, L) == 4.375 * 2**20
+
+
+def test_instruction_weighted_work():
+    """The path fraction counts each unit at its compiled VALU instruction
+    cost: a forward butterfly 17, an inverse one 21, a scaling 13, a
+    27-bit-split product 9.25, a 128-bit-sum product 31."""
+    sys.path.insert(0, str(ROOT))
+    import bench
+
+    n, L, g, h = 8192, 4, 16, 16
+    bf = n // 2 * 13
+    assert bench.per_item_instr("ks_extend", n, L, g, h) == 17 * L * L * bf
+    assert bench.per_item_instr("ks_digits", n, L, g, h) == 21 * L * bf + 13 * L * n
+    assert bench.per_item_instr("ks_pinv", n, L, g, h) == 21 * 2 * bf + 13 * 2 * n
+    assert bench.per_item_instr("ks_moddown", n, L, g, h) == 17 * 2 * L * bf + 13 * 2 * L * n
+    assert bench.per_item_instr("ks_inner", n, L, g, h) == 31 * 2 * L * (L + 1) * n
+    assert bench.per_item_instr("mac", n, L, g, h) == 9.25 * 2 * g * L * n * h
+    assert bench.per_item_instr("copy_ct", n, L, g, h) == 0
