@@ -76,6 +76,7 @@ def _load():
             "or_lift_plain": [P, u64p, u64p],
             "or_encrypt": [P, i64p, u64p, u64p, i64p, u64p],
             "or_galois_key": [P, i64p, ctypes.c_uint64, u64p, i64p, u64p],
+            "or_switch_key": [P, i64p, i64p, u64p, i64p, u64p],
             "or_phase": [P, i64p, u64p, u64p],
             "or_rotate": [P, u64p, u64p, ctypes.c_uint64, u64p],
             "or_ptct_mul": [P, u64p, u64p, u64p],
@@ -232,6 +233,25 @@ class Oracle:
         s, ps = _i64(s)
         key = np.empty((self.L, 2, self.L + 1, self.n), dtype=np.uint64)
         self.lib.or_galois_key(self._ps, ps, gal, pa, pe, key.ctypes.data_as(u64p))
+        return key
+
+    def negacyclic_square(self, s):
+        """s^2 in Z[X]/(X^n + 1), exact (ternary s: coefficients of magnitude <= n)."""
+        s = np.asarray(s, dtype=np.int64)
+        full = np.convolve(s, s)  # degree 2n - 2
+        out = full[: self.n].copy()
+        out[: self.n - 1] -= full[self.n :]
+        return out
+
+    def relin_key(self, s, rng):
+        """Relinearization key [L][2][L+1][n]: switches the s^2 part of a
+        ciphertext product back to s (same layout and digits as a Galois key)."""
+        a, pa = _u64(self.uniform(rng, self.p.moduli, count=self.L))
+        e, pe = _i64(self.error(rng, count=self.L))
+        w, pw = _i64(self.negacyclic_square(s))
+        s, ps = _i64(s)
+        key = np.empty((self.L, 2, self.L + 1, self.n), dtype=np.uint64)
+        self.lib.or_switch_key(self._ps, ps, pw, pa, pe, key.ctypes.data_as(u64p))
         return key
 
     def phase(self, s, ct):

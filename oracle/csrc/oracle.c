@@ -274,6 +274,50 @@ void or_galois_key(const or_params* p, const int64_t* s, uint64_t gal, const uin
   free(en);
 }
 
+/* Key-switching key from a target polynomial w (signed coefficients) back to
+ * s, in the layout of the Galois keys: for digit i and modulus m (m = L is P)
+ *   key[i][1][m] = a_i[m]
+ *   key[i][0][m] = -a_i[m]*s + e_i + [m == i] * (P mod q_i) * w.
+ * With w = s^2 (the negacyclic square of s) this is the relinearization key
+ * that CtCtMult needs (paper 2.1, "Evaluation keys"; hybrid RNS key
+ * switching, paper 7.1).  a: [L][L+1][n] uniform in NTT form; e: [L][n]
+ * signed; key: [L][2][L+1][n]. */
+void or_switch_key(const or_params* p, const int64_t* s, const int64_t* w, const uint64_t* a, const int64_t* e,
+                   uint64_t* key) {
+  const uint32_t n = 1u << p->log_n;
+  const int L = p->L, M = L + 1;
+  const uint64_t P = p->q[L];
+  uint64_t* sn = (uint64_t*)malloc(sizeof(uint64_t) * n);
+  uint64_t* wn = (uint64_t*)malloc(sizeof(uint64_t) * n);
+  uint64_t* en = (uint64_t*)malloc(sizeof(uint64_t) * n);
+  for (int i = 0; i < L; ++i) {
+    for (int m = 0; m < M; ++m) {
+      const uint64_t q = p->q[m];
+      for (uint32_t k = 0; k < n; ++k) {
+        sn[k] = smod(s[k], q);
+        wn[k] = smod(w[k], q);
+        en[k] = smod(e[(size_t)i * n + k], q);
+      }
+      or_ntt(sn, p->log_n, q, p->psi[m]);
+      or_ntt(wn, p->log_n, q, p->psi[m]);
+      or_ntt(en, p->log_n, q, p->psi[m]);
+      const uint64_t* am = a + ((size_t)i * M + m) * n;
+      uint64_t* b = key + (((size_t)i * 2 + 0) * M + m) * n;
+      uint64_t* ka = key + (((size_t)i * 2 + 1) * M + m) * n;
+      const uint64_t gadget = (m == i) ? P % q : 0;
+      for (uint32_t k = 0; k < n; ++k) {
+        uint64_t v = submod(en[k], mulmod(am[k], sn[k], q), q);
+        v = addmod(v, mulmod(gadget, wn[k], q), q);
+        b[k] = v;
+        ka[k] = am[k];
+      }
+    }
+  }
+  free(sn);
+  free(wn);
+  free(en);
+}
+
 /* Coefficient form of c0 + c1*s in each limb (the decryption phase; the
  * CRT and the scaling by t/Q are done with Python integers). out: [L][n] */
 void or_phase(const or_params* p, const int64_t* s, const uint64_t* ct, uint64_t* out) {
