@@ -232,8 +232,8 @@ int wally_cluster_fold(const wally_ctx* ctx, uint32_t c, uint32_t* fold, uint32_
  * encryption of PT[k][i].  Key reduction: the client sends keys for levels
  * a0 .. c-1 only; a level a < a0 applies Subs(., g_a0) 2^(a0 - a) times
  * (g_a0^(2^(a0-a)) = g_a mod 2n holds for a0 <= floor((log2 n - 1)/2)).
- * The second dimension (ciphertext products) is not provided: the answer is
- * the d2 columns. */
+ * wally_pir_answer returns the d2 columns; wally_pir_answer2 (below) adds the
+ * second dimension and returns one ciphertext. */
 typedef struct {
   const uint64_t* ct;   /* [2][L][n] query                                     */
   const uint64_t* keys; /* [c - a0][L][2][L+1][n] Galois keys of g_a0 .. g_(c-1) */
@@ -250,6 +250,44 @@ int wally_pir_encode(wally_ctx* ctx, const uint32_t* coeffs, uint32_t d1, uint32
  * query carries (gal_keys[k] = g_(a0+k), room for c - a0 <= 11 entries).  Any
  * output pointer may be NULL.  EINVAL without a PIR database. */
 int wally_pir_info(const wally_ctx* ctx, uint32_t* levels, uint32_t* first_key_level, uint64_t* gal_keys);
+
+/* Both dimensions of MulPIR (paper §4.2, "Overview of MulPIR": one query
+ * ciphertext expanded into the two indicator vectors, the first dimension,
+ * then d2 ciphertext products and their sum).  The query for entry (row i,
+ * column j) is Enc(2^-c (X^i + X^(d1 + j))) with c = ceil(log2(d1 + d2))
+ * (wally_pir_info2); its expansion gives the row indicator in entries 0 ..
+ * d1-1 and the column indicator in entries d1 .. d1+d2-1.  Column k of the
+ * first dimension times indicator entry d1 + k, summed over k, encrypts
+ * PT[j][i].  Each BFV product of (a0, a1) and (b0, b1) is taken on the
+ * centred integer lifts of the coefficients as (a0 b0, a0 b1 + a1 b0,
+ * a1 b1); the d2 products are summed as integers in an extended basis of the
+ * L ciphertext primes and auxiliary primes (the NTT-friendly primes of the
+ * same size after P, as many as make their product exceed t d2 n Q + 2),
+ * scaled once, c = round(t X / Q) mod Q (§7.1: the scaling is skipped between
+ * the products), and the three-part result (c0, c1, c2) is relinearized once,
+ * (c0, c1) + KeySwitch_{s^2 -> s}(c2), with the query's relinearization key.
+ * The answer is bit-exact with that definition. */
+typedef struct {
+  const uint64_t* ct;        /* [2][L][n] query                                     */
+  const uint64_t* keys;      /* [c - a0][L][2][L+1][n] Galois keys of g_a0 .. g_(c-1) (wally_pir_info2) */
+  const uint64_t* relin_key; /* [L][2][L+1][n]: digit i, modulus m: (-a s + e + [m == i] (P mod q_i) s^2, a) */
+  uint64_t* out;             /* [2][L][n] answer: an encryption of PT[j][i]          */
+} wally_pir_query2;
+
+/* Expansion depth c = ceil(log2(d1 + d2)), first key level a0 (the paper's
+ * choice min(c - 1, floor((log2 n - 1)/2)) unless wally_pir_encode was given
+ * one) and Galois elements of the keys of a two-index query (room for 11),
+ * and the number of auxiliary primes.  Any output may be NULL.  EINVAL
+ * without a PIR database or when d1 + d2 > 2048. */
+int wally_pir_info2(const wally_ctx* ctx, uint32_t* levels, uint32_t* first_key_level, uint64_t* gal_keys,
+                    uint32_t* aux_primes);
+
+/* Answer nq two-index queries (device pointers) on hip_stream: expansion,
+ * first and second dimension, up to 64 queries at a time (fewer when their
+ * buffers would exceed 8 GiB).  Same ordering and ownership rules as
+ * wally_pir_answer, whose workspace it shares.  EINVAL (null or misaligned
+ * pointers, d1 + d2 > 2048), ESTATE. */
+int wally_pir_answer2(wally_ctx* ctx, const wally_pir_query2* q, uint64_t nq, void* hip_stream);
 
 /* Answer nq PIR queries (device pointers) on hip_stream: expansion and first
  * dimension, up to 64 queries at a time (fewer for deep expansions, so that a

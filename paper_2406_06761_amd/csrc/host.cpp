@@ -237,6 +237,15 @@ struct wally_ctx {
   uint64_t** pir_out_host = nullptr;
   hipEvent_t pir_staged = nullptr;
   hipEvent_t pir_done = nullptr;  // after the last answer's work; the next call (any stream) and frees wait for it
+  uint64_t pir_work_S = 0;        // expansion size the workspace was made for
+  bool pir_work_two = false;      // ... and whether it has the second dimension's buffers
+  // second dimension: depth and first key level of two-index queries (0
+  // levels: not available), the auxiliary primes, constants of the extended
+  // basis (device) and the auxiliary transform tables; buffers of one wave
+  uint32_t pir_c2 = 0, pir_a02 = 0, pir_Lb = 0, pir2_kc = 0;
+  Pir2Consts* pir2_K = nullptr;
+  ulonglong2* pir2_tables = nullptr;
+  uint64_t *pir2_col = nullptr, *pir2_cf = nullptr, *pir2_ext = nullptr, *pir2_x3 = nullptr, *pir2_c3 = nullptr;
   // response compression: constants and a coefficient-form scratch
   CompressArgs comp{};
   uint64_t* comp_scratch = nullptr;
@@ -1444,14 +1453,31 @@ void wally_destroy(wally_ctx* c) {
 
 // ---------------------------------------------------------------------------
 // Index PIR for metadata fetch (paper §4.2, MulPIR): oblivious expansion of
-// the query ciphertext by substitutions, with the paper's key reduction, and
-// the first dimension (plaintext products summed over the expanded rows).
+// the query ciphertext by substitutions, with the paper's key reduction, the
+// first dimension (plaintext products summed over the expanded rows) and the
+// second dimension (ciphertext products with the second indicator, summed in
+// an extended basis, scaled once and relinearized).
 
 namespace {
 constexpr uint32_t kPirWaveMax = 64;    // queries expanded together, at most
-constexpr uint64_t kPirWaveBytes = 8ull << 30;  // expansion buffers of one wave, at most
+constexpr uint64_t kPirWaveBytes = 8ull << 30;  // expansion and product buffers of one wave, at most
 constexpr int kPirKsItems = 1024;       // key-switch items per launch (scratch size)
-constexpr uint32_t kPirMaxLevels = 11;  // d1 <= 2048
+constexpr uint32_t kPirMaxLevels = 11;  // 2^c <= 2048 expanded entries
+constexpr uint32_t kPir2Cols = 16;      // columns of the second dimension per pass
+
+// One query of either kind: rk is the relinearization key of a two-index query.
+struct PirQ {
+  const uint64_t* ct;
+  const uint64_t* keys;
+  const uint64_t* rk;
+  uint64_t* out;
+};
+
+// Expansion depth, first key level and whether the second dimension runs.
+struct PirMode {
+  uint32_t c, a0;
+  bool two;
+};
 
 void pir_free_work(wally_ctx* c) {
   if (c->pir_done) (void)hipEventSynchronize(c->pir_done);  // answers in flight read the workspace
@@ -1461,14 +1487,14 @@ void pir_free_work(wally_ctx* c) {
     dfree(c, c->pir_y[k]);
     c->pir_lev[k] = c->pir_y[k] = nullptr;
   }
-  dfree(c, c->pir_X);
-  dfree(c, c->pir_U);
-  dfree(c, c->pir_Y);
-  dfree(c, c->pir_D);
+  for (uint64_t** p : {&c->pir_X, &c->pir_U, &c->pir_Y, &c->pir_D, &c->pir2_col, &c->pir2_cf, &c->pir2_ext,
+                       &c->pir2_x3, &c->pir2_c3}) {
+    dfree(c, *p);
+    *p = nullptr;
+  }
   dfree(c, c->pir_items_dev);
   dfree(c, c->pir_copy_dev);
   dfree(c, c->pir_out_dev);
-  c->pir_X = c->pir_U = c->pir_Y = c->pir_D = nullptr;
   c->pir_items_dev = nullptr;
   c->pir_copy_dev = nullptr;
   c->pir_out_dev = nullptr;
@@ -1478,25 +1504,27 @@ void pir_free_work(wally_ctx* c) {
   c->pir_items_host = nullptr;
   c->pir_copy_host = nullptr;
   c->pir_out_host = nullptr;
+  c->pir_work_S = 0;
+  c->pir_work_two = false;
 }
 
-int pir_alloc_work(wally_ctx* c);
-
-// The PIR workspace, all or nothing: a failed allocation frees what was taken.
-int pir_ensure_work(wally_ctx* c) {
-  if (c->pir_lev[0]) return WALLY_OK;
-  const int rc = pir_alloc_work(c);
-  if (rc) pir_free_work(c);
-  return rc;
+// Device bytes per query of a wave: the two expansion lists and the two
+// substitution buffers (3 S ciphertexts), and for the second dimension the
+// columns, one pass's coefficient and auxiliary rows, the tensor sums and the
+// scaled product.
+uint64_t pir_query_bytes(const wally_ctx* c, uint64_t S, bool two, uint32_t kc) {
+  const uint64_t ctw = c->ctw(), n = c->n, L = c->L, Lb = c->pir_Lb;
+  uint64_t w = 3 * S * ctw;
+  if (two) w += (uint64_t)c->pir_d2 * ctw + kc * 2 * ctw + kc * 4 * Lb * n + 3 * (L + Lb) * n + 4 * L * n;
+  return 8 * w;
 }
 
-int pir_alloc_work(wally_ctx* c) {
-  const size_t w8 = 8, ctw = c->ctw(), S = 1ull << c->pir_c, n = c->n, L = c->L;
-  // queries per wave: the two expansion lists and the two substitution
-  // buffers (3 S ciphertexts per query) within kPirWaveBytes
-  c->pir_wq = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kPirWaveMax, kPirWaveBytes / (3 * S * ctw * w8)));
+int pir_alloc_work(wally_ctx* c, uint64_t S, bool two) {
+  const size_t w8 = 8, ctw = c->ctw(), n = c->n, L = c->L, Lb = c->pir_Lb;
+  const uint32_t kc = two ? std::min(c->pir_d2, kPir2Cols) : 0;
+  c->pir_wq = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kPirWaveMax, kPirWaveBytes / pir_query_bytes(c, S, two, kc)));
   const size_t W = c->pir_wq;
-  const size_t items = W * (S - 1);
+  const size_t items = W * S;  // substitutions (S - 1 per query) and one relinearization
   int rc;
   for (int k = 0; k < 2; ++k) {
     if ((rc = dalloc(c, W * S * ctw * w8, (void**)&c->pir_lev[k]))) return rc;
@@ -1506,6 +1534,14 @@ int pir_alloc_work(wally_ctx* c) {
   if ((rc = dalloc(c, kPirKsItems * 2 * (L + 1) * n * w8, (void**)&c->pir_U))) return rc;
   if ((rc = dalloc(c, kPirKsItems * 2 * n * w8, (void**)&c->pir_Y))) return rc;
   if ((rc = dalloc(c, kPirKsItems * (L + 1) * L * n * w8, (void**)&c->pir_D))) return rc;
+  if (two) {
+    if ((rc = dalloc(c, W * c->pir_d2 * ctw * w8, (void**)&c->pir2_col))) return rc;
+    if ((rc = dalloc(c, W * kc * 2 * ctw * w8, (void**)&c->pir2_cf))) return rc;
+    if ((rc = dalloc(c, W * kc * 4 * Lb * n * w8, (void**)&c->pir2_ext))) return rc;
+    if ((rc = dalloc(c, W * 3 * (L + Lb) * n * w8, (void**)&c->pir2_x3))) return rc;
+    if ((rc = dalloc(c, W * 4 * L * n * w8, (void**)&c->pir2_c3))) return rc;
+    c->pir2_kc = kc;
+  }
   if ((rc = dalloc(c, items * sizeof(KsItem), (void**)&c->pir_items_dev))) return rc;
   if ((rc = dalloc(c, W * sizeof(CopyItem), (void**)&c->pir_copy_dev))) return rc;
   if ((rc = dalloc(c, W * sizeof(uint64_t*), (void**)&c->pir_out_dev))) return rc;
@@ -1513,59 +1549,92 @@ int pir_alloc_work(wally_ctx* c) {
   HIP_OK(c, hipHostMalloc((void**)&c->pir_copy_host, W * sizeof(CopyItem), hipHostMallocDefault));
   HIP_OK(c, hipHostMalloc((void**)&c->pir_out_host, W * sizeof(uint64_t*), hipHostMallocDefault));
   if (!c->pir_staged) HIP_OK(c, hipEventCreateWithFlags(&c->pir_staged, hipEventDisableTiming));
+  c->pir_work_S = S;
+  c->pir_work_two = two;
   return WALLY_OK;
 }
 
-// Expansion and first dimension of up to pir_wq queries on stream st.
-int pir_wave(wally_ctx* c, const wally_pir_query* q, uint32_t w, hipStream_t st) {
-  const uint64_t ctw = c->ctw(), S = 1ull << c->pir_c, keyw = c->keyw();
+// The PIR workspace for a mode, all or nothing: a workspace made for another
+// expansion size or without the second dimension's buffers is replaced (after
+// the answers in flight), and a failed allocation frees what was taken.
+int pir_ensure_work(wally_ctx* c, const PirMode& md) {
+  const uint64_t S = 1ull << md.c;
+  if (c->pir_lev[0] && c->pir_work_S == S && (c->pir_work_two || !md.two)) return WALLY_OK;
+  pir_free_work(c);
+  const int rc = pir_alloc_work(c, S, md.two);
+  if (rc) pir_free_work(c);
+  return rc;
+}
+
+// Expansion of up to pir_wq queries on stream st, then the first dimension
+// (into the callers' outputs, or the column buffer for two-index queries),
+// then, for two-index queries, the second dimension into the outputs.
+int pir_wave(wally_ctx* c, const PirMode& md, const PirQ* q, uint32_t w, hipStream_t st) {
+  const uint64_t ctw = c->ctw(), S = 1ull << md.c, keyw = c->keyw();
   HIP_OK(c, hipEventSynchronize(c->pir_staged));  // host descriptors of the last wave were copied
-  // descriptors: copies, substitution items of every level, outputs
+  // descriptors: copies, substitution items of every level, relinearization items, outputs
   size_t base = 0;
-  std::vector<size_t> lev_base(c->pir_c);
-  for (uint32_t a = 0; a < c->pir_c; ++a) {
+  std::vector<size_t> lev_base(md.c);
+  for (uint32_t a = 0; a < md.c; ++a) {
     lev_base[a] = base;
     const uint64_t half = 1ull << a;
-    const uint32_t ka = std::max(a, c->pir_a0);
+    const uint32_t ka = std::max(a, md.a0);
     uint64_t* cur = c->pir_lev[a & 1];
     for (uint32_t i = 0; i < w; ++i)
       for (uint64_t b = 0; b < half; ++b) {
         KsItem it{};
-        it.key = q[i].keys + (uint64_t)(ka - c->pir_a0) * keyw;
+        it.key = q[i].keys + (uint64_t)(ka - md.a0) * keyw;
         it.buf0 = cur + (i * S + b) * ctw;
         it.buf1 = c->pir_y[0] + (i * (S / 2) + b) * ctw;
         it.fin = c->pir_y[1] + (i * (S / 2) + b) * ctw;
         c->pir_items_host[base++] = it;
       }
   }
+  const size_t relin_base = base;
+  const uint64_t c3w = 4ull * c->L * c->n;  // words of one scaled product (c0, c2, 0, c1)
+  if (md.two)
+    for (uint32_t i = 0; i < w; ++i) {
+      // key switch of (c0, c2) with the identity automorphism, + (0, c1): (c0, c1) + KS(c2)
+      KsItem it{};
+      it.key = q[i].rk;
+      it.buf0 = c->pir2_c3 + i * c3w;
+      it.acc = c->pir2_c3 + i * c3w + c3w / 2;
+      it.fin = q[i].out;
+      c->pir_items_host[base++] = it;
+    }
   for (uint32_t i = 0; i < w; ++i) {
     c->pir_copy_host[i] = CopyItem{q[i].ct, c->pir_lev[0] + i * S * ctw};
-    c->pir_out_host[i] = q[i].out;
+    c->pir_out_host[i] = md.two ? c->pir2_col + (uint64_t)i * c->pir_d2 * ctw : q[i].out;
   }
   HIP_OK(c, hipMemcpyAsync(c->pir_items_dev, c->pir_items_host, base * sizeof(KsItem), hipMemcpyHostToDevice, st));
   HIP_OK(c, hipMemcpyAsync(c->pir_copy_dev, c->pir_copy_host, w * sizeof(CopyItem), hipMemcpyHostToDevice, st));
   HIP_OK(c, hipMemcpyAsync(c->pir_out_dev, c->pir_out_host, w * sizeof(uint64_t*), hipMemcpyHostToDevice, st));
   HIP_OK(c, hipEventRecord(c->pir_staged, st));
   HIP_OK(c, timed(c, st, WALLY_KERNEL_COPY, w, [&] { return launch_copy_ct(c->pir_copy_dev, (int)w, ctw, st); }));
-  for (uint32_t a = 0; a < c->pir_c; ++a) {
+  auto ks_args = [c](uint32_t gal, int in_sel, int out_sel) {
+    KsArgs k{};
+    k.log_n = c->log_n;
+    k.L = c->L;
+    k.gal = gal;
+    k.in_sel = in_sel;
+    k.out_sel = out_sel;
+    k.giant = -1;
+    k.g = c->g;
+    k.X = c->pir_X;
+    k.U = c->pir_U;
+    k.Y = c->pir_Y;
+    k.D = c->pir_D;
+    return k;
+  };
+  for (uint32_t a = 0; a < md.c; ++a) {
     const uint64_t half = 1ull << a;
-    const uint32_t ka = std::max(a, c->pir_a0);
+    const uint32_t ka = std::max(a, md.a0);
     const uint32_t reps = 1u << (ka - a);  // Subs(., g_ka) applied 2^(ka - a) times is Subs(., g_a)
     const int n_items = (int)(w * half);
     int last_out = 1;
     for (uint32_t r = 0; r < reps; ++r) {
-      KsArgs ka_args{};
-      ka_args.log_n = c->log_n;
-      ka_args.L = c->L;
-      ka_args.gal = c->n / (1u << ka) + 1;
-      ka_args.in_sel = r == 0 ? 0 : (r % 2 == 1 ? 1 : 2);  // x, then alternately y0, y1
-      ka_args.out_sel = r % 2 == 0 ? 1 : 2;
-      ka_args.giant = -1;
-      ka_args.g = c->g;
-      ka_args.X = c->pir_X;
-      ka_args.U = c->pir_U;
-      ka_args.Y = c->pir_Y;
-      ka_args.D = c->pir_D;
+      // x, then alternately y0, y1
+      const KsArgs ka_args = ks_args(c->n / (1u << ka) + 1, r == 0 ? 0 : (r % 2 == 1 ? 1 : 2), r % 2 == 0 ? 1 : 2);
       for (int i0 = 0; i0 < n_items; i0 += kPirKsItems)
         HIP_OK(c, keyswitch(c, c->pir_items_dev + lev_base[a] + i0, std::min(kPirKsItems, n_items - i0), ka_args, st));
       last_out = ka_args.out_sel;
@@ -1582,8 +1651,9 @@ int pir_wave(wally_ctx* c, const wally_pir_query* q, uint32_t w, hipStream_t st)
     sa.L = c->L;
     HIP_OK(c, launch_pir_split(sa, n_items, c->M, st));
   }
+  const uint64_t* E = c->pir_lev[md.c & 1];
   PirDotArgs da{};
-  da.E = c->pir_lev[c->pir_c & 1];
+  da.E = E;
   da.pt = c->pir_pt;
   da.out = c->pir_out_dev;
   da.stride = (uint32_t)S;
@@ -1593,6 +1663,191 @@ int pir_wave(wally_ctx* c, const wally_pir_query* q, uint32_t w, hipStream_t st)
   da.log_n = c->log_n;
   da.L = c->L;
   HIP_OK(c, timed(c, st, WALLY_KERNEL_MAC, w, [&] { return launch_pir_dot(da, c->M, st); }));
+  if (!md.two) return WALLY_OK;
+  // second dimension, columns in passes of pir2_kc
+  Pir2Args pa{};
+  pa.K = c->pir2_K;
+  pa.col = c->pir2_col;
+  pa.E = E;
+  pa.cf = c->pir2_cf;
+  pa.ext = c->pir2_ext;
+  pa.x3 = c->pir2_x3;
+  pa.c3 = c->pir2_c3;
+  pa.stride = (uint32_t)S;
+  pa.d1 = c->pir_d1;
+  pa.d2 = c->pir_d2;
+  pa.nq = w;
+  pa.log_n = c->log_n;
+  pa.L = c->L;
+  pa.Lb = (int)c->pir_Lb;
+  for (uint32_t k0 = 0; k0 < c->pir_d2; k0 += c->pir2_kc) {
+    pa.k0 = k0;
+    pa.kc = std::min(c->pir2_kc, c->pir_d2 - k0);
+    pa.accumulate = k0 > 0;
+    HIP_OK(c, launch_pir2_coef(pa, c->M, st));
+    HIP_OK(c, launch_pir2_extend(pa, st));
+    HIP_OK(c, launch_rows_ntt(c->pir2_ext, (int)(w * pa.kc * 4 * c->pir_Lb), c->log_n, c->pir2_K, c->L,
+                              (int)c->pir_Lb, 0, st));
+    HIP_OK(c, launch_pir2_tensor(pa, st));
+  }
+  const int MB = c->L + (int)c->pir_Lb;
+  HIP_OK(c, launch_rows_ntt(c->pir2_x3, (int)(w * 3 * MB), c->log_n, c->pir2_K, 0, MB, 1, st));
+  HIP_OK(c, launch_pir2_scale(pa, st));
+  HIP_OK(c, launch_rows_ntt(c->pir2_c3, (int)(w * 4 * c->L), c->log_n, c->pir2_K, 0, c->L, 0, st));
+  KsArgs rl = ks_args(1, 0, 2);
+  rl.giant = 0;  // + acc = (0, c1)
+  HIP_OK(c, keyswitch(c, c->pir_items_dev + relin_base, (int)w, rl, st));
+  return WALLY_OK;
+}
+
+// little-endian multi-word integers (host)
+std::vector<uint64_t> mw_prod(const uint64_t* p, int count, int skip = -1) {
+  std::vector<uint64_t> x{1};
+  for (int i = 0; i < count; ++i)
+    if (i != skip) mw_mul_small(x, p[i]);
+  return x;
+}
+int mw_cmp(const std::vector<uint64_t>& a, const std::vector<uint64_t>& b) {
+  for (size_t k = std::max(a.size(), b.size()); k-- > 0;) {
+    const uint64_t x = k < a.size() ? a[k] : 0, y = k < b.size() ? b[k] : 0;
+    if (x != y) return x < y ? -1 : 1;
+  }
+  return 0;
+}
+void mw_add_small(std::vector<uint64_t>& x, uint64_t v) {
+  for (uint64_t& w : x) {
+    const uint64_t s = w + v;
+    v = s < w;
+    w = s;
+    if (!v) return;
+  }
+  if (v) x.push_back(v);
+}
+
+// Constants of the exact conversion from the primes src[0..ns) to tgt[0..nt).
+bool make_conv(const uint64_t* src, int ns, const uint64_t* tgt, int nt, BaseConv& C) {
+  C = BaseConv{};
+  C.ns = (uint32_t)ns;
+  C.nt = (uint32_t)nt;
+  const std::vector<uint64_t> S = mw_prod(src, ns);
+  // the multi-word sums stay below ns S
+  std::vector<uint64_t> bound = S;
+  mw_mul_small(bound, (uint64_t)ns);
+  if (bound.size() > (size_t)kMaxConvWords) return false;
+  for (size_t w = 0; w < S.size(); ++w) C.S[w] = S[w];
+  for (size_t w = 0; w < S.size(); ++w) C.half[w] = (S[w] >> 1) | (w + 1 < S.size() ? S[w + 1] << 63 : 0);
+  for (int i = 0; i < ns; ++i) {
+    const uint64_t si = src[i];
+    C.s[i] = si;
+    const std::vector<uint64_t> hat = mw_prod(src, ns, i);
+    for (size_t w = 0; w < hat.size(); ++w) C.hat[i][w] = hat[w];
+    C.inv[i] = powmod(mw_mod_small(hat, si), si - 2, si);
+    C.invp[i] = shoup_of(C.inv[i], si);
+    for (int j = 0; j < nt; ++j) {
+      C.hat_t[i][j] = mw_mod_small(hat, tgt[j]);
+      C.hat_tp[i][j] = shoup_of(C.hat_t[i][j], tgt[j]);
+    }
+  }
+  for (int j = 0; j < nt; ++j) {
+    C.t[j] = tgt[j];
+    C.S_t[j] = mw_mod_small(S, tgt[j]);
+    C.S_tp[j] = shoup_of(C.S_t[j], tgt[j]);
+  }
+  return true;
+}
+
+// The extended basis of the second dimension for a table with d2 columns:
+// auxiliary primes (the NTT-friendly primes of the ciphertext primes' size
+// that come after P, descending) until their product B exceeds t d2 n Q + 2,
+// their transform tables, and every conversion and scaling constant.
+int pir2_setup(wally_ctx* c, uint32_t d2) {
+  dfree(c, c->pir2_K);
+  dfree(c, c->pir2_tables);
+  c->pir2_K = nullptr;
+  c->pir2_tables = nullptr;
+  c->pir_Lb = 0;
+  const uint64_t two_n = 2ull * c->n, t = c->mods[c->L + 1];
+  std::vector<uint64_t> need = mw_prod(c->mods, c->L);  // Q
+  mw_mul_small(need, t);
+  mw_mul_small(need, d2);
+  mw_mul_small(need, (uint64_t)c->n);
+  mw_add_small(need, 2);
+  std::vector<uint64_t> aux, B{1};
+  for (uint64_t cand = c->mods[c->L] - two_n; mw_cmp(B, need) <= 0; cand -= two_n) {
+    if (cand <= two_n || aux.size() >= (size_t)kMaxAux)
+      return set_err(c, WALLY_EINVAL, "no auxiliary basis of at most %d primes for %u columns", kMaxAux, d2);
+    if (!is_prime(cand) || cand == t) continue;
+    aux.push_back(cand);
+    mw_mul_small(B, cand);
+  }
+  const int L = c->L, Lb = (int)aux.size(), n = c->n;
+  Pir2Consts K{};
+  K.L = (uint32_t)L;
+  K.Lb = (uint32_t)Lb;
+  // transform tables of the auxiliary primes, [Lb][fwd n | inv n]
+  std::vector<ulonglong2> tab((size_t)Lb * 2 * n);
+  for (int b = 0; b < Lb; ++b) {
+    const uint64_t q = aux[b], ps = min_root(q, two_n), pinv = powmod(ps, q - 2, q);
+    uint64_t p1 = 1, p2 = 1;
+    for (int k = 0; k < n; ++k) {
+      const uint32_t r = bitrev(k, c->log_n);
+      tab[(size_t)b * 2 * n + r] = make_ulonglong2(p1, shoup_of(p1, q));
+      tab[(size_t)b * 2 * n + n + r] = make_ulonglong2(p2, shoup_of(p2, q));
+      p1 = mulmod(p1, ps, q);
+      p2 = mulmod(p2, pinv, q);
+    }
+  }
+  int rc = dalloc(c, tab.size() * sizeof(ulonglong2), (void**)&c->pir2_tables);
+  if (rc) return rc;
+  HIP_OK(c, hipMemcpy(c->pir2_tables, tab.data(), tab.size() * sizeof(ulonglong2), hipMemcpyHostToDevice));
+  std::vector<uint64_t> base(c->mods, c->mods + L);
+  base.insert(base.end(), aux.begin(), aux.end());
+  for (int m = 0; m < L + Lb; ++m) {
+    RowMod& r = K.mod[m];
+    const uint64_t q = base[m];
+    r.q = q;
+    r.ninv = powmod(c->n % q, q - 2, q);
+    r.ninvp = shoup_of(r.ninv, q);
+    r.onep = (uint64_t)((((u128)1) << 64) / q);
+    r.r64 = (uint64_t)(((u128)1 << 64) % q);
+    r.r64p = shoup_of(r.r64, q);
+    if (m < L) {
+      r.fwd = c->M.fwd[m];
+      r.inv = c->M.inv[m];
+    } else {
+      r.fwd = c->pir2_tables + (size_t)(m - L) * 2 * n;
+      r.inv = r.fwd + n;
+    }
+    K.t_m[m] = t % q;
+    K.t_mp[m] = shoup_of(K.t_m[m], q);
+  }
+  const std::vector<uint64_t> Q = mw_prod(c->mods, L);
+  std::vector<uint64_t> hq(Q.size());
+  for (size_t w = 0; w < Q.size(); ++w) hq[w] = (Q[w] >> 1) | (w + 1 < Q.size() ? Q[w + 1] << 63 : 0);
+  for (int m = 0; m < L + Lb; ++m) K.h_m[m] = mw_mod_small(hq, base[m]);
+  for (int b = 0; b < Lb; ++b) {
+    K.qinv_b[b] = powmod(mw_mod_small(Q, aux[b]), aux[b] - 2, aux[b]);
+    K.qinv_bp[b] = shoup_of(K.qinv_b[b], aux[b]);
+  }
+  K.t = t;
+  if (!make_conv(c->mods, L, aux.data(), Lb, K.q_to_b) || !make_conv(aux.data(), Lb, c->mods, L, K.b_to_q))
+    return set_err(c, WALLY_EINVAL, "extended basis beyond the conversion word limit");
+  if ((rc = dalloc(c, sizeof(Pir2Consts), (void**)&c->pir2_K))) return rc;
+  HIP_OK(c, hipMemcpy(c->pir2_K, &K, sizeof(Pir2Consts), hipMemcpyHostToDevice));
+  c->pir_Lb = (uint32_t)Lb;
+  return WALLY_OK;
+}
+
+// Validation of a batch and the workspace, then the waves (one or two dimensions).
+int pir_answer_any(wally_ctx* c, const PirMode& md, const std::vector<PirQ>& qs, hipStream_t st) {
+  int rc;
+  if ((rc = pir_ensure_work(c, md))) return rc;
+  // the workspace is shared: this call's work follows the last call's, whatever stream that was on
+  if (c->pir_done) HIP_OK(c, hipStreamWaitEvent(st, c->pir_done, 0));
+  else HIP_OK(c, hipEventCreateWithFlags(&c->pir_done, hipEventDisableTiming));
+  for (uint64_t i0 = 0; i0 < qs.size(); i0 += c->pir_wq)
+    if ((rc = pir_wave(c, md, qs.data() + i0, (uint32_t)std::min<uint64_t>(c->pir_wq, qs.size() - i0), st))) return rc;
+  HIP_OK(c, hipEventRecord(c->pir_done, st));
   return WALLY_OK;
 }
 }  // namespace
@@ -1614,6 +1869,10 @@ int wally_pir_encode(wally_ctx* c, const uint32_t* coeffs, uint32_t d1, uint32_t
   if (a0 > std::min(levels - 1, top))
     return set_err(c, WALLY_EINVAL, "first key level %u above %u (levels %u, squaring holds up to %u)", a0,
                    std::min(levels - 1, top), levels, top);
+  // two-index queries expand to d1 + d2 entries (none when that is beyond 2^11)
+  uint32_t levels2 = 1;
+  while ((1u << levels2) < d1 + d2) ++levels2;
+  if (levels2 > kPirMaxLevels) levels2 = 0;
   const uint64_t n_pt = (uint64_t)d1 * d2, t = c->mods[c->L + 1];
   for (uint64_t i = 0; i < n_pt * c->n; ++i)
     if (coeffs[i] >= t) return set_err(c, WALLY_EINVAL, "PIR coefficient %llu is not below t", (unsigned long long)i);
@@ -1624,10 +1883,11 @@ int wally_pir_encode(wally_ctx* c, const uint32_t* coeffs, uint32_t d1, uint32_t
   c->pir_w = nullptr;
   c->pir_d1 = c->pir_d2 = 0;
   if ((rc = dalloc(c, n_pt * c->ptw() / c->d_pad * 8, (void**)&c->pir_pt))) return rc;
-  // X^-(2^a) at NTT entry i of limb l: psi_l^(-(2 brv(i) + 1) 2^a)
+  // X^-(2^a) at NTT entry i of limb l: psi_l^(-(2 brv(i) + 1) 2^a), for the deeper of the two expansions
+  const uint32_t lev_max = std::max(levels, levels2);
   const uint64_t two_n = 2ull * c->n;
-  std::vector<ulonglong2> w((size_t)levels * c->L * c->n);
-  for (uint32_t a = 0; a < levels; ++a)
+  std::vector<ulonglong2> w((size_t)lev_max * c->L * c->n);
+  for (uint32_t a = 0; a < lev_max; ++a)
     for (int l = 0; l < c->L; ++l) {
       const uint64_t q = c->mods[l];
       for (int i = 0; i < c->n; ++i) {
@@ -1650,10 +1910,14 @@ int wally_pir_encode(wally_ctx* c, const uint32_t* coeffs, uint32_t d1, uint32_t
   }
   dfree(c, dco);
   if (e != hipSuccess) return set_err(c, WALLY_EDEVICE, "PIR encode failed: %s", hipGetErrorString(e));
+  c->pir_c2 = 0;
+  if (levels2 && (rc = pir2_setup(c, d2))) return rc;
   c->pir_d1 = d1;
   c->pir_d2 = d2;
   c->pir_c = levels;
   c->pir_a0 = a0;
+  c->pir_c2 = levels2;
+  c->pir_a02 = first_key_level == UINT32_MAX ? std::min(levels2 - 1, top) : a0;
   return WALLY_OK;
 }
 
@@ -1666,28 +1930,66 @@ int wally_pir_info(const wally_ctx* c, uint32_t* levels, uint32_t* first_key_lev
   return WALLY_OK;
 }
 
+int wally_pir_info2(const wally_ctx* c, uint32_t* levels, uint32_t* first_key_level, uint64_t* gal_keys,
+                    uint32_t* aux_primes) {
+  if (!c || !c->pir_d1 || !c->pir_c2) return WALLY_EINVAL;
+  if (levels) *levels = c->pir_c2;
+  if (first_key_level) *first_key_level = c->pir_a02;
+  if (gal_keys)
+    for (uint32_t a = c->pir_a02; a < c->pir_c2; ++a) gal_keys[a - c->pir_a02] = c->n / (1u << a) + 1;
+  if (aux_primes) *aux_primes = c->pir_Lb;
+  return WALLY_OK;
+}
+
+}  // extern "C"
+
+namespace {
+int pir_check(wally_ctx* c, const void* q, uint64_t nq) {
+  if (c->serving) return set_err(c, WALLY_ESTATE, "a serving session owns the device queues");
+  if (!c->pir_d1) return set_err(c, WALLY_ESTATE, "no PIR database encoded");
+  if (nq && !q) return set_err(c, WALLY_EINVAL, "null query array");
+  return WALLY_OK;
+}
+}  // namespace
+
+extern "C" {
+
 int wally_pir_answer(wally_ctx* c, const wally_pir_query* q, uint64_t nq, void* hip_stream) {
   int rc = check_live(c);
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(c->mu);
-  if (c->serving) return set_err(c, WALLY_ESTATE, "a serving session owns the device queues");
-  if (!c->pir_d1) return set_err(c, WALLY_ESTATE, "no PIR database encoded");
-  if (nq && !q) return set_err(c, WALLY_EINVAL, "null query array");
+  if ((rc = pir_check(c, q, nq))) return rc;
+  std::vector<PirQ> qs(nq);
   for (uint64_t i = 0; i < nq; ++i) {
     if (!q[i].ct || !q[i].keys || !q[i].out)
       return set_err(c, WALLY_EINVAL, "PIR query %llu: null pointer", (unsigned long long)i);
     if (((uintptr_t)q[i].ct | (uintptr_t)q[i].out | (uintptr_t)q[i].keys) & 15)
       return set_err(c, WALLY_EINVAL, "PIR query %llu: ct, keys and out must be 16-byte aligned", (unsigned long long)i);
+    qs[i] = PirQ{q[i].ct, q[i].keys, nullptr, q[i].out};
   }
-  if ((rc = pir_ensure_work(c))) return rc;
-  hipStream_t st = (hipStream_t)hip_stream;
-  // the workspace is shared: this call's work follows the last call's, whatever stream that was on
-  if (c->pir_done) HIP_OK(c, hipStreamWaitEvent(st, c->pir_done, 0));
-  else HIP_OK(c, hipEventCreateWithFlags(&c->pir_done, hipEventDisableTiming));
-  for (uint64_t i0 = 0; i0 < nq; i0 += c->pir_wq)
-    if ((rc = pir_wave(c, q + i0, (uint32_t)std::min<uint64_t>(c->pir_wq, nq - i0), st))) return rc;
-  HIP_OK(c, hipEventRecord(c->pir_done, st));
-  return WALLY_OK;
+  if (nq == 0) return WALLY_OK;
+  return pir_answer_any(c, PirMode{c->pir_c, c->pir_a0, false}, qs, (hipStream_t)hip_stream);
+}
+
+int wally_pir_answer2(wally_ctx* c, const wally_pir_query2* q, uint64_t nq, void* hip_stream) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if ((rc = pir_check(c, q, nq))) return rc;
+  if (!c->pir_c2)
+    return set_err(c, WALLY_EINVAL, "two-index queries need d1 + d2 <= %u (database %u x %u)", 1u << kPirMaxLevels,
+                   c->pir_d1, c->pir_d2);
+  std::vector<PirQ> qs(nq);
+  for (uint64_t i = 0; i < nq; ++i) {
+    if (!q[i].ct || !q[i].keys || !q[i].relin_key || !q[i].out)
+      return set_err(c, WALLY_EINVAL, "PIR query %llu: null pointer", (unsigned long long)i);
+    if (((uintptr_t)q[i].ct | (uintptr_t)q[i].out | (uintptr_t)q[i].keys | (uintptr_t)q[i].relin_key) & 15)
+      return set_err(c, WALLY_EINVAL, "PIR query %llu: ct, keys, relin_key and out must be 16-byte aligned",
+                     (unsigned long long)i);
+    qs[i] = PirQ{q[i].ct, q[i].keys, q[i].relin_key, q[i].out};
+  }
+  if (nq == 0) return WALLY_OK;
+  return pir_answer_any(c, PirMode{c->pir_c2, c->pir_a02, true}, qs, (hipStream_t)hip_stream);
 }
 
 }  // extern "C"

@@ -102,6 +102,68 @@ struct PirDotArgs {
   uint32_t stride, d1, d2, nq;
   int log_n, L;
 };
+// Index PIR, second dimension (paper §4.2 "Overview of MulPIR", step 3; the
+// products computed in a larger basis and scaled once, §7.1 "Reducing the
+// computation of BFV operations").  The extended basis is the L ciphertext
+// primes followed by Lb auxiliary primes whose product B exceeds
+// t d2 n Q + 2, so that both the tensor sums (below d2 n Q^2 / 2 in
+// magnitude) and their scaled values (below t d2 n Q / 2 + 1) are exact.
+constexpr int kMaxAux = 12;
+constexpr int kMaxBase = kMaxLimbs + kMaxAux;
+constexpr int kMaxConvWords = 12;  // 64-bit words of the multi-word sums of a conversion
+
+// One modulus of the extended basis (index < L: q_index; then the auxiliary primes).
+struct RowMod {
+  uint64_t q, ninv, ninvp, onep, r64, r64p;
+  const ulonglong2* fwd;  // (psi^brv(k), Shoup) for k < n
+  const ulonglong2* inv;  // (psi^-brv(k), Shoup)
+};
+
+// Exact conversion of residues r_i modulo the ns source primes s_i (product S)
+// to residues modulo the nt target primes: with y_i = r_i (S/s_i)^-1 mod s_i,
+// the integer v = sum_i y_i (S/s_i) - alpha S lies in [0, S) for
+// alpha = floor(sum_i y_i (S/s_i) / S), found exactly by multi-word compares
+// (one more S is taken off for the centred lift when v > floor(S/2)); its
+// residue mod t_j is sum_i y_i [S/s_i]_{t_j} - alpha [S]_{t_j}.
+struct BaseConv {
+  uint32_t ns, nt;
+  uint64_t s[kMaxBase], inv[kMaxBase], invp[kMaxBase];  // source primes, (S/s_i)^-1 mod s_i, Shoup
+  uint64_t hat[kMaxBase][kMaxConvWords];                // S / s_i, little-endian words (zero padded)
+  uint64_t S[kMaxConvWords], half[kMaxConvWords];       // S and floor(S / 2)
+  uint64_t t[kMaxBase];                                 // target primes
+  uint64_t hat_t[kMaxBase][kMaxBase], hat_tp[kMaxBase][kMaxBase];  // [i][j]: (S/s_i) mod t_j, Shoup
+  uint64_t S_t[kMaxBase], S_tp[kMaxBase];               // S mod t_j, Shoup
+};
+
+struct Pir2Consts {
+  uint32_t L, Lb;
+  RowMod mod[kMaxBase];
+  BaseConv q_to_b, b_to_q;
+  uint64_t t;
+  uint64_t t_m[kMaxBase], t_mp[kMaxBase];  // t mod each modulus of the extended basis, Shoup
+  uint64_t h_m[kMaxBase];                  // floor(Q / 2) mod each modulus
+  uint64_t qinv_b[kMaxAux], qinv_bp[kMaxAux];  // Q^-1 mod each auxiliary prime, Shoup
+};
+
+struct Pir2Args {
+  const Pir2Consts* K;   // device copy
+  const uint64_t* col;   // first-dimension columns [nq][d2][2][L][n]
+  const uint64_t* E;     // expanded ciphertexts [nq][stride][2][L][n]; the second indicator at d1 + k
+  uint64_t* cf;          // coefficient form [nq][kc][2 (column, indicator)][2][L][n]
+  uint64_t* ext;         // auxiliary residues, then their NTT [nq][kc][2][2][Lb][n]
+  uint64_t* x3;          // tensor sums [nq][3][L + Lb][n]
+  uint64_t* c3;          // scaled product [nq][4][L][n]: c0, c2, zero, c1 (NTT form once transformed)
+  uint32_t stride, d1, d2, k0, kc, nq;  // columns [k0, k0 + kc) in this pass
+  int log_n, L, Lb, accumulate;         // accumulate: add to the tensor sums of earlier passes
+};
+hipError_t launch_pir2_coef(const Pir2Args& a, const DevModuli& M, hipStream_t st);
+hipError_t launch_pir2_extend(const Pir2Args& a, hipStream_t st);
+hipError_t launch_pir2_tensor(const Pir2Args& a, hipStream_t st);
+hipError_t launch_pir2_scale(const Pir2Args& a, hipStream_t st);
+// in-place NTT of `rows` rows of n words, row r modulo K->mod[m0 + r % period]
+hipError_t launch_rows_ntt(uint64_t* data, int rows, int log_n, const Pir2Consts* K, int m0, int period, int inverse,
+                           hipStream_t st);
+
 hipError_t launch_pir_encode(const uint32_t* coeffs, uint64_t* out, int n_pt, int log_n, int L, const DevModuli& M,
                              hipStream_t st);
 hipError_t launch_pir_split(const PirSplitArgs& a, int items, const DevModuli& M, hipStream_t st);

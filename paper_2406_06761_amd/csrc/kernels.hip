@@ -572,6 +572,266 @@ __global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_ntt_rows(uint64_t* d
 }
 
 // ---------------------------------------------------------------------------
+// Index PIR, second dimension (paper §4.2, step 3): the sum over columns k of
+// the BFV products of column k with the second indicator entry d1 + k, the
+// tensor products summed as integers in the extended basis and scaled once
+// (§7.1), then relinearized by the key-switching kernels.
+
+// acc (kMaxConvWords words) += y * m (m zero padded to kMaxConvWords words)
+__device__ __forceinline__ void mw_mac_full(uint64_t (&acc)[kMaxConvWords], uint64_t y, const uint64_t* m) {
+  uint64_t carry = 0;
+#pragma unroll
+  for (int w = 0; w < kMaxConvWords; ++w) {
+    const uint64_t mw = m[w];
+    const uint64_t lo = y * mw, hi = __umul64hi(y, mw);
+    uint64_t s = acc[w] + lo;
+    uint64_t c = s < lo;
+    s += carry;
+    c += s < carry;
+    acc[w] = s;
+    carry = hi + c;
+  }
+}
+
+// acc >= m (multi-word)
+__device__ __forceinline__ bool mw_geq(const uint64_t (&acc)[kMaxConvWords], const uint64_t* m) {
+  bool gt = false, lt = false;
+#pragma unroll
+  for (int w = kMaxConvWords - 1; w >= 0; --w) {
+    const uint64_t mw = m[w];
+    const bool undecided = !gt && !lt;
+    gt = gt || (undecided && acc[w] > mw);
+    lt = lt || (undecided && acc[w] < mw);
+  }
+  return !lt;
+}
+
+__device__ __forceinline__ void mw_sub(uint64_t (&acc)[kMaxConvWords], const uint64_t* m) {
+  uint64_t borrow = 0;
+#pragma unroll
+  for (int w = 0; w < kMaxConvWords; ++w) {
+    const uint64_t mw = m[w];
+    const uint64_t d = acc[w] - mw;
+    const uint64_t b1 = acc[w] < mw;
+    const uint64_t d2 = d - borrow;
+    const uint64_t b2 = d < borrow;
+    acc[w] = d2;
+    borrow = b1 | b2;
+  }
+}
+
+// out[j] = v mod t_j for the integer v with residues r[i] modulo the source
+// primes: v in [0, S), or its centred lift in (-S/2, S/2] (see BaseConv).
+// The multi-word sum has at most ns S < 2^(64 kMaxConvWords).
+__device__ void base_conv(const BaseConv* __restrict__ C, const uint64_t* r, uint64_t* out, bool centred) {
+  const uint32_t ns = C->ns, nt = C->nt;
+  uint64_t y[kMaxBase];
+  uint64_t acc[kMaxConvWords];
+#pragma unroll
+  for (int w = 0; w < kMaxConvWords; ++w) acc[w] = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxBase; ++i) {
+    if ((uint32_t)i < ns) {
+      const uint64_t si = C->s[i];
+      y[i] = csub(shoup(r[i], C->inv[i], C->invp[i], si), si);
+      mw_mac_full(acc, y[i], C->hat[i]);
+    } else {
+      y[i] = 0;
+    }
+  }
+  uint32_t alpha = 0;
+  for (uint32_t it = 0; it < ns; ++it) {  // the sum is below ns S
+    if (!mw_geq(acc, C->S)) break;
+    mw_sub(acc, C->S);
+    ++alpha;
+  }
+  if (centred) {
+    // v > floor(S/2): the centred lift is v - S
+    uint64_t h1[kMaxConvWords];
+#pragma unroll
+    for (int w = 0; w < kMaxConvWords; ++w) h1[w] = C->half[w];
+    // acc > half  <=>  acc >= half + 1
+    uint64_t carry = 1;
+#pragma unroll
+    for (int w = 0; w < kMaxConvWords; ++w) {
+      const uint64_t v = h1[w] + carry;
+      carry = v < carry;
+      h1[w] = v;
+    }
+    if (mw_geq(acc, h1)) ++alpha;
+  }
+  for (uint32_t j = 0; j < nt; ++j) {
+    const uint64_t tj = C->t[j];
+    uint64_t sum = 0;  // ns terms below 2 t_j each (t_j < 2^55, ns <= 20): below 2^61
+#pragma unroll
+    for (int i = 0; i < kMaxBase; ++i)
+      if ((uint32_t)i < ns) sum += shoup(y[i], C->hat_t[i][j], C->hat_tp[i][j], tj);
+    sum = sum % tj;
+    const uint64_t sub = csub(shoup((uint64_t)alpha, C->S_t[j], C->S_tp[j], tj), tj);
+    out[j] = submod(sum, sub, tj);
+  }
+}
+
+// INTT of the column and indicator rows of the pass: one row per workgroup,
+// row r = (((q kc + k) 2 + which) 2 + part) L + limb; output in [0, q_limb).
+template <int LOGN>
+__global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_pir2_coef(Pir2Args a, DevModuli M) {
+  using S = NttShape<LOGN, 4>;
+  using FM = FirstMap<LOGN, 4>;
+  __shared__ uint64_t lds[S::LDS_WORDS];
+  const int tid = threadIdx.x;
+  const uint32_t L = (uint32_t)a.L;
+  uint32_t r = blockIdx.x;
+  const uint32_t limb = r % L;
+  r /= L;
+  const uint32_t part = r & 1;
+  r >>= 1;
+  const uint32_t which = r & 1;
+  r >>= 1;
+  const uint32_t k = r % a.kc, qq = r / a.kc;
+  const uint64_t ctw = 2ull * L * S::N;
+  const uint64_t* src = which ? a.E + ((uint64_t)qq * a.stride + a.d1 + a.k0 + k) * ctw
+                              : a.col + ((uint64_t)qq * a.d2 + a.k0 + k) * ctw;
+  src += ((uint64_t)part * L + limb) * S::N;
+  const uint64_t q = M.q[limb];
+  uint64_t x[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) x[e] = gmem(src)[FM::idx(tid, e)];
+  ntt_inv_nat<LOGN, 4>(x, lds, M.inv[limb], q, tid);
+  WALLY_GLOBAL uint64_t* dst = gmem(a.cf) + (uint64_t)blockIdx.x * S::N;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) dst[FM::idx(tid, e)] = csub(shoup(x[e], M.ninv[limb], M.ninvp[limb], q), q);
+}
+
+// centred lift of every coefficient of the pass's rows (mod Q) to the
+// auxiliary primes: grid (n / 256, polys = nq kc 4); block 256
+__global__ __launch_bounds__(256) void k_pir2_extend(Pir2Args a) {
+  const uint64_t n = 1ull << a.log_n;
+  const uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t p = blockIdx.y;
+  const Pir2Consts* K = a.K;
+  uint64_t r[kMaxBase], v[kMaxBase];
+#pragma unroll
+  for (int i = 0; i < kMaxBase; ++i) r[i] = i < a.L ? gmem(a.cf)[(p * a.L + i) * n + x] : 0;
+  base_conv(&K->q_to_b, r, v, true);
+  for (int b = 0; b < a.Lb; ++b) gmem(a.ext)[(p * a.Lb + b) * n + x] = v[b];
+}
+
+// in-place transform of rows modulo K->mod[m0 + r % period]; natural order
+// in and out, results in [0, m)
+template <int LOGN>
+__global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_rows_ntt(uint64_t* data, const Pir2Consts* K, int m0,
+                                                                  int period, int inverse) {
+  using S = NttShape<LOGN, 4>;
+  using FM = FirstMap<LOGN, 4>;
+  __shared__ uint64_t lds[S::LDS_WORDS];
+  const int tid = threadIdx.x;
+  const RowMod md = K->mod[m0 + (int)(blockIdx.x % (uint32_t)period)];
+  WALLY_GLOBAL uint64_t* row = gmem(data) + (uint64_t)blockIdx.x * S::N;
+  uint64_t x[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) x[e] = row[FM::idx(tid, e)];
+  if (inverse) {
+    ntt_inv_nat<LOGN, 4>(x, lds, md.inv, md.q, tid);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) row[FM::idx(tid, e)] = csub(shoup(x[e], md.ninv, md.ninvp, md.q), md.q);
+  } else {
+    ntt_fwd_nat<LOGN, 4>(x, lds, md.fwd, md.q, tid);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) row[FM::idx(tid, e)] = reduce_lazy(x[e], md.q, md.onep);
+  }
+}
+
+// tensor sums of the pass's columns in every modulus of the extended basis
+// (NTT form): X0 = sum a0 b0, X1 = sum (a0 b1 + a1 b0), X2 = sum a1 b1 with
+// 128-bit lazy sums (2 kc <= 32 products below 2^108).  Ciphertext primes read
+// the NTT-form rows themselves, auxiliary primes the extended rows.
+// grid (n / 256, L + Lb, nq); block 256
+__global__ __launch_bounds__(256) void k_pir2_tensor(Pir2Args a) {
+  const uint64_t n = 1ull << a.log_n;
+  const uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const int m = blockIdx.y;
+  const uint64_t qq = blockIdx.z;
+  const RowMod md = a.K->mod[m];
+  const uint64_t ctw = 2ull * a.L * n;
+  const int MB = a.L + a.Lb;
+  u128w s0{0, 0}, s1{0, 0}, s2{0, 0};
+  for (uint32_t k = 0; k < a.kc; ++k) {
+    uint64_t av[2], bv[2];
+    if (m < a.L) {
+      WALLY_GLOBAL const uint64_t* ca = gmem(a.col) + (qq * a.d2 + a.k0 + k) * ctw + (uint64_t)m * n + x;
+      WALLY_GLOBAL const uint64_t* cb = gmem(a.E) + (qq * a.stride + a.d1 + a.k0 + k) * ctw + (uint64_t)m * n + x;
+      av[0] = ca[0];
+      av[1] = ca[(uint64_t)a.L * n];
+      bv[0] = cb[0];
+      bv[1] = cb[(uint64_t)a.L * n];
+    } else {
+      const uint64_t base = ((qq * a.kc + k) * 4) * a.Lb + (uint64_t)(m - a.L);
+      WALLY_GLOBAL const uint64_t* e = gmem(a.ext) + base * n + x;
+      const uint64_t stride = (uint64_t)a.Lb * n;  // next part; two parts per ciphertext
+      av[0] = e[0];
+      av[1] = e[stride];
+      bv[0] = e[2 * stride];
+      bv[1] = e[3 * stride];
+    }
+    mac128(s0, av[0], bv[0]);
+    mac128(s1, av[0], bv[1]);
+    mac128(s1, av[1], bv[0]);
+    mac128(s2, av[1], bv[1]);
+  }
+  WALLY_GLOBAL uint64_t* o = gmem(a.x3) + (qq * 3 * MB + m) * n + x;
+  const u128w sums[3] = {s0, s1, s2};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    uint64_t v = reduce128(sums[c], md.q, md.r64, md.r64p, md.onep);
+    if (a.accumulate) v = addmod(v, o[(uint64_t)c * MB * n], md.q);
+    o[(uint64_t)c * MB * n] = v;
+  }
+}
+
+// scaling: per coefficient of each tensor sum x (residues in the extended
+// basis, coefficient form), y = round(t x / Q) = (t x + floor(Q/2) - r) / Q
+// with r = (t x + floor(Q/2)) mod Q: r is carried from Q to the auxiliary
+// primes exactly, y is formed there (|y| < B / 2) and carried back to the
+// ciphertext primes with its centred lift.  Output slots (c0, c2, 0, c1).
+// grid (n / 256, 3, nq); block 256
+__global__ __launch_bounds__(256) void k_pir2_scale(Pir2Args a) {
+  const uint64_t n = 1ull << a.log_n;
+  const uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  const uint64_t qq = blockIdx.z;
+  const Pir2Consts* K = a.K;
+  const int L = a.L, Lb = a.Lb, MB = L + Lb;
+  WALLY_GLOBAL const uint64_t* xin = gmem(a.x3) + (qq * 3 + c) * MB * n + x;
+  uint64_t r[kMaxBase], rb[kMaxBase], yb[kMaxBase], yq[kMaxBase];
+#pragma unroll
+  for (int i = 0; i < kMaxBase; ++i) {
+    r[i] = 0;
+    yb[i] = 0;
+    if (i < L) {
+      const uint64_t qi = K->mod[i].q;
+      const uint64_t tx = csub(shoup(xin[(uint64_t)i * n], K->t_m[i], K->t_mp[i], qi), qi);
+      r[i] = addmod(tx, K->h_m[i], qi);
+    }
+  }
+  base_conv(&K->q_to_b, r, rb, false);
+  for (int b = 0; b < Lb; ++b) {
+    const uint64_t bq = K->mod[L + b].q;
+    const uint64_t tx = csub(shoup(xin[(uint64_t)(L + b) * n], K->t_m[L + b], K->t_mp[L + b], bq), bq);
+    const uint64_t num = submod(addmod(tx, K->h_m[L + b], bq), rb[b], bq);
+    yb[b] = csub(shoup(num, K->qinv_b[b], K->qinv_bp[b], bq), bq);
+  }
+  base_conv(&K->b_to_q, yb, yq, true);
+  const int slot = c == 0 ? 0 : (c == 1 ? 3 : 1);
+  WALLY_GLOBAL uint64_t* o = gmem(a.c3) + (qq * 4 + slot) * L * n + x;
+  for (int j = 0; j < L; ++j) o[(uint64_t)j * n] = yq[j];
+  if (c == 0) {
+    WALLY_GLOBAL uint64_t* z = gmem(a.c3) + (qq * 4 + 2) * L * n + x;
+    for (int j = 0; j < L; ++j) z[(uint64_t)j * n] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // diagnostics: register-resident butterfly rate.  Every thread keeps 16 words
 // in registers and runs `iters` radix-16 passes of the transforms' own
 // butterfly (ct_bfly forward, gs_bfly inverse) with four fixed twiddles, one
@@ -839,6 +1099,51 @@ hipError_t launch_ntt_rows(uint64_t* data, int rows, int log_n, int mi, int inve
   switch (log_n) {
     case 12: hipLaunchKernelGGL(k_ntt_rows<12>, dim3(rows), dim3(NttShape<12, 4>::T), 0, st, data, mi, inverse, M); break;
     case 13: hipLaunchKernelGGL(k_ntt_rows<13>, dim3(rows), dim3(NttShape<13, 4>::T), 0, st, data, mi, inverse, M); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pir2_coef(const Pir2Args& a, const DevModuli& M, hipStream_t st) {
+  const uint32_t rows = a.nq * a.kc * 4 * (uint32_t)a.L;
+  if (rows == 0) return hipSuccess;
+  switch (a.log_n) {
+    case 12: hipLaunchKernelGGL(k_pir2_coef<12>, dim3(rows), dim3(NttShape<12, 4>::T), 0, st, a, M); break;
+    case 13: hipLaunchKernelGGL(k_pir2_coef<13>, dim3(rows), dim3(NttShape<13, 4>::T), 0, st, a, M); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pir2_extend(const Pir2Args& a, hipStream_t st) {
+  const uint32_t polys = a.nq * a.kc * 4;
+  if (polys == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pir2_extend, dim3((1u << a.log_n) / 256, polys), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pir2_tensor(const Pir2Args& a, hipStream_t st) {
+  if (a.nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pir2_tensor, dim3((1u << a.log_n) / 256, a.L + a.Lb, a.nq), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pir2_scale(const Pir2Args& a, hipStream_t st) {
+  if (a.nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pir2_scale, dim3((1u << a.log_n) / 256, 3, a.nq), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_ntt(uint64_t* data, int rows, int log_n, const Pir2Consts* K, int m0, int period, int inverse,
+                           hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  switch (log_n) {
+    case 12:
+      hipLaunchKernelGGL(k_rows_ntt<12>, dim3(rows), dim3(NttShape<12, 4>::T), 0, st, data, K, m0, period, inverse);
+      break;
+    case 13:
+      hipLaunchKernelGGL(k_rows_ntt<13>, dim3(rows), dim3(NttShape<13, 4>::T), 0, st, data, K, m0, period, inverse);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -57,6 +57,7 @@ class Query(ctypes.Structure):
 assert ctypes.sizeof(Query) == QUERY_DTYPE.itemsize
 
 PIR_QUERY_DTYPE = np.dtype([("ct", "<u8"), ("keys", "<u8"), ("out", "<u8")])
+PIR_QUERY2_DTYPE = np.dtype([("ct", "<u8"), ("keys", "<u8"), ("relin_key", "<u8"), ("out", "<u8")])
 PIR_PAPER_KEYS = 0xFFFFFFFF  # first_key_level: the paper's choice
 STATIC_SCRATCH_BYTES = 256 << 20  # WALLY_STATIC_SCRATCH_BYTES
 
@@ -65,7 +66,7 @@ SYMBOLS = [
     "wally_params_init", "wally_params_query", "wally_encode_clusters", "wally_cluster_info", "wally_cluster_fold",
     "wally_score_batch", "wally_score_batch_static",
     "wally_tune", "wally_compress_responses", "wally_encode_clusters_i16",
-    "wally_pir_encode", "wally_pir_info", "wally_pir_answer",
+    "wally_pir_encode", "wally_pir_info", "wally_pir_answer", "wally_pir_info2", "wally_pir_answer2",
     "wally_serve_start", "wally_serve_submit", "wally_serve_poll", "wally_serve_stop", "wally_strerror",
     "wally_last_error", "wally_destroy", "wally_diag_ntt", "wally_diag_rotate", "wally_diag_kernel_timing",
     "wally_diag_kernel_stats", "wally_diag_bfly_rate",
@@ -111,6 +112,9 @@ def load():
         "wally_pir_encode": ([vp, vp, u32, u32, u32], i32),
         "wally_pir_info": ([vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64)], i32),
         "wally_pir_answer": ([vp, vp, u64, vp], i32),
+        "wally_pir_info2": ([vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u32)],
+                            i32),
+        "wally_pir_answer2": ([vp, vp, u64, vp], i32),
         "wally_compress_responses": ([vp, vp, u64, vp, vp], i32),
         "wally_tune": ([vp, vp, u64, vp, vp, vp, ctypes.POINTER(TuneEntry), u32, ctypes.POINTER(u32)], i32),
         "wally_serve_start": ([vp, vp], i32),
@@ -234,6 +238,20 @@ class Context:
         queries = np.ascontiguousarray(queries, dtype=PIR_QUERY_DTYPE)
         self._check(self.lib.wally_pir_answer(self.h, queries.ctypes.data, len(queries), _stream_handle(stream)),
                     "wally_pir_answer")
+
+    def pir_info2(self):
+        """Two-index queries: (levels c, first key level a0, [Galois elements of the keys], auxiliary primes)."""
+        c, a0, lb = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        g = (ctypes.c_uint64 * 16)()
+        self._check(self.lib.wally_pir_info2(self.h, ctypes.byref(c), ctypes.byref(a0), g, ctypes.byref(lb)),
+                    "wally_pir_info2")
+        return c.value, a0.value, [g[k] for k in range(c.value - a0.value)], lb.value
+
+    def pir_answer2(self, queries: np.ndarray, stream=None):
+        """queries: numpy array of PIR_QUERY2_DTYPE (device pointers)."""
+        queries = np.ascontiguousarray(queries, dtype=PIR_QUERY2_DTYPE)
+        self._check(self.lib.wally_pir_answer2(self.h, queries.ctypes.data, len(queries), _stream_handle(stream)),
+                    "wally_pir_answer2")
 
     def compress_responses(self, responses, out, stream=None):
         """responses: device tensor of [chunks][2][L][n] words; out: device

@@ -56,6 +56,12 @@ def test_struct_layouts_match_a_c_compiler(tmp_path):
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
         for fname, _ in py._fields_:
             lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    dtypes = {"wally_query": wally.QUERY_DTYPE, "wally_pir_query": wally.PIR_QUERY_DTYPE,
+              "wally_pir_query2": wally.PIR_QUERY2_DTYPE}
+    for cname, dt in dtypes.items():
+        lines.append(f'printf("np_{cname} size %zu\\n", sizeof({cname}));')
+        for fname in dt.names:
+            lines.append(f'printf("np_{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
     lines.append("return 0; }")
     src = tmp_path / "layout.c"
     src.write_text("\n".join(lines))
@@ -67,6 +73,10 @@ def test_struct_layouts_match_a_c_compiler(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+    for cname, dt in dtypes.items():  # the numpy record layouts the binding passes as arrays
+        assert got[("np_" + cname, "size")] == dt.itemsize, cname
+        for fname in dt.names:
+            assert got[("np_" + cname, fname)] == dt.fields[fname][1], (cname, fname)
 
 
 def test_error_strings_and_null_handling():
