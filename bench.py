@@ -478,6 +478,35 @@ def pir_legs(nq, steps):
             log(f"pir {name}: a0={a0_}, {len(gals)} keys, {subs} substitutions per query, {dt * 1e3:.1f} ms for "
                 f"{nq} queries, {nq / dt:.0f} queries/s")
             del keys
+        # both dimensions (one answer ciphertext per query), the paper's key reduction
+        from paper_2406_06761_amd.wally import PIR_QUERY2_DTYPE
+
+        ctx.pir_encode(db, 0xFFFFFFFF)
+        c2, a02, gals2, n_aux = ctx.pir_info2()
+        keys = synth.uniform_residues(gen, (pool, len(gals2) * L, 2), qs + [info.P], n, device="cuda")
+        rks = synth.uniform_residues(gen, (pool, L, 2), qs + [info.P], n, device="cuda")
+        outs2 = torch.empty((nq, 2 * L * n), dtype=torch.int64, device="cuda")
+        pidx = np.arange(nq) % pool
+        q2 = np.zeros(nq, dtype=PIR_QUERY2_DTYPE)
+        q2["ct"] = cts.data_ptr() + pidx * cts[0].numel() * 8
+        q2["keys"] = keys.data_ptr() + pidx * keys[0].numel() * 8
+        q2["relin_key"] = rks.data_ptr() + pidx * rks[0].numel() * 8
+        q2["out"] = outs2.data_ptr() + np.arange(nq) * outs2[0].numel() * 8
+        ctx.pir_answer2(q2)  # warm-up (workspace)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.pir_answer2(q2)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        subs = sum((1 << a) * (1 << (max(a, a02) - a)) for a in range(c2))
+        legs["two_dimensions"] = {"first_key_level": a02, "keys_per_query": len(gals2) + 1,
+                                  "substitutions_per_query": subs, "ciphertext_products_per_query": d2,
+                                  "auxiliary_primes": n_aux, "ms_per_batch": dt * 1e3, "queries_per_s": nq / dt,
+                                  "answer_bytes_per_query": 2 * L * n * 8}
+        log(f"pir two dimensions: a0={a02}, {len(gals2)} Galois keys + relinearization key, {subs} substitutions "
+            f"and {d2} products per query, {dt * 1e3:.1f} ms for {nq} queries, {nq / dt:.0f} queries/s")
+        del keys, rks, outs2
     finally:
         ctx.close()
     return (d1, d2), legs
