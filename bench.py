@@ -672,12 +672,14 @@ def main():
     if not args.no_tune and args.workload != "tiny":
         t0 = time.perf_counter()
         sub = q[: min(8192, nq)]
-        res = ctx.tune(sub, batches=(512, 1024), sets=(2, 3), tiles=(8, 16))
-        best = min(res, key=lambda r: r[3])
+        res = ctx.tune(sub, batches=(512, 1024), sets=(2, 3), tiles=(8, 16), radices=(8, 16))
+        best = min(res, key=lambda r: r[4])
         tuned = {"sample_queries": len(sub), "candidates": [list(r) for r in res],
-                 "chosen": {"max_batch": best[0], "wave_sets": best[1], "tile_items": best[2]}}
+                 "candidate_fields": ["max_batch", "wave_sets", "tile_items", "ntt_radix", "ms"],
+                 "chosen": {"max_batch": best[0], "wave_sets": best[1], "tile_items": best[2],
+                            "ntt_radix": best[3]}}
         log(f"tuner: {len(res)} configs in {time.perf_counter() - t0:.1f} s, chose B={best[0]} "
-            f"sets={best[1]} tile={best[2]} ({best[3]:.1f} ms on {len(sub)} queries)")
+            f"sets={best[1]} tile={best[2]} radix={best[3]} ({best[4]:.1f} ms on {len(sub)} queries)")
 
     for i in range(args.warmup):
         t0 = time.perf_counter()

@@ -337,17 +337,22 @@ typedef struct {
   uint32_t max_batch;  /* queries per wave                                  */
   uint32_t wave_sets;  /* waves in flight (one stream each)                 */
   uint32_t tile_items; /* queries sharing one plaintext chunk per sum tile  */
+  uint32_t ntt_radix;  /* key-switch transforms: passes of radix 8 (n/8 threads
+                          per transform) or 16 (n/16 threads)              */
   double ms;           /* time of one batched call                          */
 } wally_tune_entry;
 
 /* Schedule autotuner: times wally_score_batch (batched path) on the caller's
  * queries for every combination of the candidate wave sizes, wave-stream
- * counts and plaintext-tile sizes (0-terminated lists; NULL or empty keeps
- * the current value), keeps the fastest for this context and writes every
- * timing to out[0..*n_out).  Synchronous; the outputs of the queries are
- * written (several times). */
+ * counts, plaintext-tile sizes and NTT radices of the key-switch transforms
+ * (8 or 16) (0-terminated lists; NULL or empty keeps the current value),
+ * keeps the fastest for this context and writes every timing to
+ * out[0..*n_out).  The words do not depend on the choice.  Synchronous; the
+ * outputs of the queries are written (several times).  EINVAL for a radix
+ * other than 8 or 16 or an invalid query. */
 int wally_tune(wally_ctx* ctx, const wally_query* q, uint64_t nq, const uint32_t* batches, const uint32_t* sets,
-               const uint32_t* tiles, wally_tune_entry* out, uint32_t max_out, uint32_t* n_out);
+               const uint32_t* tiles, const uint32_t* radices, wally_tune_entry* out, uint32_t max_out,
+               uint32_t* n_out);
 
 /* Serving (continuous batching).  The protocol runs in epochs and the server
  * must finish every query of an epoch before it ends (§3.1, "Epochs");

@@ -262,6 +262,7 @@ struct wally_ctx {
   int B = 0;
   int n_sets = 2;
   uint32_t tile_items = 8;  // giant items per plaintext-sharing tile of the sum kernel
+  int ks_loge = 4;          // key-switch transforms: 2^ks_loge words per thread (radix-8 or radix-16 passes)
   // graph path: the captured segments of a whole batch, replayed while the
   // batch (the query array) and the configuration stay the same
   hipStream_t cap_stream = nullptr;
@@ -514,6 +515,7 @@ KsArgs base_args(const wally_ctx* c, const WaveWork& s) {
   KsArgs a{};
   a.log_n = c->log_n;
   a.L = c->L;
+  a.loge = c->ks_loge;
   a.g = c->g;
   a.giant = -1;
   a.X = s.X;
@@ -1245,7 +1247,8 @@ int wally_score_batch_static(wally_ctx* c, const wally_query* q, uint64_t nq, vo
 }
 
 int wally_tune(wally_ctx* c, const wally_query* q, uint64_t nq, const uint32_t* batches, const uint32_t* sets,
-               const uint32_t* tiles, wally_tune_entry* out, uint32_t max_out, uint32_t* n_out) {
+               const uint32_t* tiles, const uint32_t* radices, wally_tune_entry* out, uint32_t max_out,
+               uint32_t* n_out) {
   int rc = check_live(c);
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(c->mu);
@@ -1253,10 +1256,16 @@ int wally_tune(wally_ctx* c, const wally_query* q, uint64_t nq, const uint32_t* 
   if (c->serving) return set_err(c, WALLY_ESTATE, "cannot tune while serving");
   if (!q || nq == 0) return set_err(c, WALLY_EINVAL, "empty query array");
   if (n_out) *n_out = 0;
-  const uint32_t cur_b[2] = {(uint32_t)c->B, 0}, cur_s[2] = {(uint32_t)c->n_sets, 0}, cur_t[2] = {c->tile_items, 0};
+  const uint32_t cur_b[2] = {(uint32_t)c->B, 0}, cur_s[2] = {(uint32_t)c->n_sets, 0}, cur_t[2] = {c->tile_items, 0},
+                 cur_r[2] = {1u << c->ks_loge, 0};
   if (!batches || !batches[0]) batches = cur_b;
   if (!sets || !sets[0]) sets = cur_s;
   if (!tiles || !tiles[0]) tiles = cur_t;
+  if (!radices || !radices[0]) radices = cur_r;
+  for (const uint32_t* pr = radices; *pr; ++pr)
+    if (*pr != 8 && *pr != 16) return set_err(c, WALLY_EINVAL, "NTT radix %u: 8 or 16", *pr);
+  for (uint64_t i = 0; i < nq; ++i)
+    if ((rc = validate_query(c, q[i], i))) return rc;
   hipStream_t st = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_OK(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -1265,33 +1274,36 @@ int wally_tune(wally_ctx* c, const wally_query* q, uint64_t nq, const uint32_t* 
   const bool timing = c->timing;
   c->timing = false;
   double best = 1e300;
-  uint32_t bb = c->B, bs = c->n_sets, bt = c->tile_items, k = 0;
+  uint32_t bb = c->B, bs = c->n_sets, bt = c->tile_items, br = 1u << c->ks_loge, k = 0;
   for (const uint32_t* pb = batches; *pb && !rc; ++pb)
     for (const uint32_t* ps = sets; *ps && !rc; ++ps)
-      for (const uint32_t* pt = tiles; *pt && !rc; ++pt) {
-        free_sets(c);
-        c->B = (int)*pb;
-        c->n_sets = (int)std::min<uint32_t>(*ps, 8);
-        c->tile_items = *pt;
-        // warm-up (allocates the workspaces), then one timed batch
-        if ((rc = score_locked(c, q, nq, WALLY_PATH_BATCHED, st))) break;
-        hipError_t e = hipEventRecord(e0, st);
-        if (e == hipSuccess) rc = score_locked(c, q, nq, WALLY_PATH_BATCHED, st);
-        if (!rc && e == hipSuccess) e = hipEventRecord(e1, st);
-        if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) rc = set_err(c, WALLY_EDEVICE, "tuning run failed: %s", hipGetErrorString(e));
-        if (rc) break;
-        if (out && k < max_out) out[k] = wally_tune_entry{*pb, (uint32_t)c->n_sets, *pt, (double)ms};
-        ++k;
-        if (ms < best) best = ms, bb = *pb, bs = (uint32_t)c->n_sets, bt = *pt;
-      }
+      for (const uint32_t* pt = tiles; *pt && !rc; ++pt)
+        for (const uint32_t* pr = radices; *pr && !rc; ++pr) {
+          free_sets(c);
+          c->B = (int)*pb;
+          c->n_sets = (int)std::min<uint32_t>(*ps, 8);
+          c->tile_items = *pt;
+          c->ks_loge = *pr == 8 ? 3 : 4;
+          // warm-up (allocates the workspaces), then one timed batch
+          if ((rc = score_locked(c, q, nq, WALLY_PATH_BATCHED, st))) break;
+          hipError_t e = hipEventRecord(e0, st);
+          if (e == hipSuccess) rc = score_locked(c, q, nq, WALLY_PATH_BATCHED, st);
+          if (!rc && e == hipSuccess) e = hipEventRecord(e1, st);
+          if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) rc = set_err(c, WALLY_EDEVICE, "tuning run failed: %s", hipGetErrorString(e));
+          if (rc) break;
+          if (out && k < max_out) out[k] = wally_tune_entry{*pb, (uint32_t)c->n_sets, *pt, *pr, (double)ms};
+          ++k;
+          if (ms < best) best = ms, bb = *pb, bs = (uint32_t)c->n_sets, bt = *pt, br = *pr;
+        }
   if (n_out) *n_out = std::min(k, max_out);
   free_sets(c);
   c->B = (int)bb;
   c->n_sets = (int)bs;
   c->tile_items = bt;
+  c->ks_loge = br == 8 ? 3 : 4;
   c->timing = timing;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1615,6 +1627,7 @@ int pir_wave(wally_ctx* c, const PirMode& md, const PirQ* q, uint32_t w, hipStre
     KsArgs k{};
     k.log_n = c->log_n;
     k.L = c->L;
+    k.loge = c->ks_loge;
     k.gal = gal;
     k.in_sel = in_sel;
     k.out_sel = out_sel;

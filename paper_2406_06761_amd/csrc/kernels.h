@@ -30,6 +30,7 @@ struct DevModuli {
 
 struct KsArgs {
   int log_n, L;
+  int loge;  // 2^loge words per thread in the transforms: 3 (radix-8 passes, n/8 threads) or 4 (radix 16, the default)
   uint32_t gal;
   int in_sel, out_sel;
   uint64_t in_off, out_off;

@@ -30,11 +30,6 @@
 #include "kernels.h"
 #include "ntt.h"
 
-// elements per thread (2^WALLY_KS_LOGE) of the key-switching transforms
-#ifndef WALLY_KS_LOGE
-#define WALLY_KS_LOGE 4
-#endif
-
 namespace wally {
 
 // Pointers read from descriptors in memory are generic to the compiler, which
@@ -993,15 +988,23 @@ __global__ __launch_bounds__(256) void k_resp_pack(const uint64_t* __restrict__ 
     default: return hipErrorInvalidValue;                                                                     \
   }
 
+// the key-switching kernels at the radix of KsArgs::loge (8 or 16 words per thread)
+#define WALLY_DISPATCH_KS(KERNEL, GRID, ...)                 \
+  if (a.loge == 3) {                                        \
+    WALLY_DISPATCH_LOGN(KERNEL, 3, GRID, __VA_ARGS__);      \
+  } else {                                                  \
+    WALLY_DISPATCH_LOGN(KERNEL, 4, GRID, __VA_ARGS__);      \
+  }
+
 hipError_t launch_ks_digits(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  WALLY_DISPATCH_LOGN(k_ks_digits, WALLY_KS_LOGE, dim3(n_items, a.L), items, a, M);
+  WALLY_DISPATCH_KS(k_ks_digits, dim3(n_items, a.L), items, a, M);
   return hipGetLastError();
 }
 
 hipError_t launch_ks_extend(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  WALLY_DISPATCH_LOGN(k_ks_extend, WALLY_KS_LOGE, dim3(xcd_blocks(n_items * a.L, a.L)), items, a, n_items, M);
+  WALLY_DISPATCH_KS(k_ks_extend, dim3(xcd_blocks(n_items * a.L, a.L)), items, a, n_items, M);
   return hipGetLastError();
 }
 
@@ -1024,13 +1027,13 @@ hipError_t launch_ks_inner(const KsItem* items, int n_items, const KsArgs& a, co
 
 hipError_t launch_ks_pinv(int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  WALLY_DISPATCH_LOGN(k_ks_pinv, WALLY_KS_LOGE, dim3(n_items, 2), a, M);
+  WALLY_DISPATCH_KS(k_ks_pinv, dim3(n_items, 2), a, M);
   return hipGetLastError();
 }
 
 hipError_t launch_ks_moddown(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  WALLY_DISPATCH_LOGN(k_ks_moddown, WALLY_KS_LOGE, dim3(xcd_blocks(n_items * 2, a.L)), items, a, n_items, M);
+  WALLY_DISPATCH_KS(k_ks_moddown, dim3(xcd_blocks(n_items * 2, a.L)), items, a, n_items, M);
   return hipGetLastError();
 }
 

@@ -77,7 +77,7 @@ KERNELS = ["ks_digits", "ks_extend", "ks_inner", "ks_pinv", "ks_moddown", "mac",
 
 class TuneEntry(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_uint32), ("wave_sets", ctypes.c_uint32), ("tile_items", ctypes.c_uint32),
-                ("ms", ctypes.c_double)]
+                ("ntt_radix", ctypes.c_uint32), ("ms", ctypes.c_double)]
 
 
 class KernelStat(ctypes.Structure):
@@ -116,7 +116,7 @@ def load():
                             i32),
         "wally_pir_answer2": ([vp, vp, u64, vp], i32),
         "wally_compress_responses": ([vp, vp, u64, vp, vp], i32),
-        "wally_tune": ([vp, vp, u64, vp, vp, vp, ctypes.POINTER(TuneEntry), u32, ctypes.POINTER(u32)], i32),
+        "wally_tune": ([vp, vp, u64, vp, vp, vp, vp, ctypes.POINTER(TuneEntry), u32, ctypes.POINTER(u32)], i32),
         "wally_serve_start": ([vp, vp], i32),
         "wally_serve_submit": ([vp, ctypes.POINTER(Query), ctypes.POINTER(u64)], i32),
         "wally_serve_poll": ([vp, ctypes.POINTER(u64), u32, ctypes.POINTER(u32)], i32),
@@ -275,22 +275,22 @@ class Context:
         self._check(self.lib.wally_score_batch_static(self.h, queries.ctypes.data, len(queries),
                                                       _stream_handle(stream)), "wally_score_batch_static")
 
-    def tune(self, queries: np.ndarray, batches=(), sets=(), tiles=()):
+    def tune(self, queries: np.ndarray, batches=(), sets=(), tiles=(), radices=()):
         """Autotune the batched schedule on these queries; returns the timings
-        [(max_batch, wave_sets, tile_items, ms)] (the fastest is kept)."""
+        [(max_batch, wave_sets, tile_items, ntt_radix, ms)] (the fastest is kept)."""
         queries = np.ascontiguousarray(queries, dtype=QUERY_DTYPE)
 
         def arr(v):
             a = (ctypes.c_uint32 * (len(v) + 1))(*v, 0)
             return ctypes.cast(a, ctypes.c_void_p), a
 
-        (pb, kb), (ps, ks), (pt, kt) = arr(batches), arr(sets), arr(tiles)
-        cap = max(1, len(batches)) * max(1, len(sets)) * max(1, len(tiles))
+        (pb, kb), (ps, ks), (pt, kt), (pr, kr) = arr(batches), arr(sets), arr(tiles), arr(radices)
+        cap = max(1, len(batches)) * max(1, len(sets)) * max(1, len(tiles)) * max(1, len(radices))
         out = (TuneEntry * cap)()
         n = ctypes.c_uint32()
-        self._check(self.lib.wally_tune(self.h, queries.ctypes.data, len(queries), pb, ps, pt, out, cap,
+        self._check(self.lib.wally_tune(self.h, queries.ctypes.data, len(queries), pb, ps, pt, pr, out, cap,
                                         ctypes.byref(n)), "wally_tune")
-        return [(e.max_batch, e.wave_sets, e.tile_items, e.ms) for e in out[: n.value]]
+        return [(e.max_batch, e.wave_sets, e.tile_items, e.ntt_radix, e.ms) for e in out[: n.value]]
 
     def serve_start(self, stream=None):
         self._check(self.lib.wally_serve_start(self.h, _stream_handle(stream)), "wally_serve_start")

@@ -202,8 +202,8 @@ def test_tuner_and_compression_on_folded(work):
     try:
         c.encode_clusters(work[1], work[2])
         q, outs, keep = _queries(o, work)
-        res = c.tune(q, batches=(3, 6), sets=(1, 2), tiles=(2, 8))
-        assert len(res) == 8
+        res = c.tune(q, batches=(3, 6), sets=(1, 2), tiles=(2, 8), radices=(8, 16))
+        assert len(res) == 16
         for t in outs:
             t.zero_()
         c.score_batch(q)

@@ -118,6 +118,16 @@ def test_small_end_to_end(pair):
     """Two clusters (one of two chunks) and three real queries at the preset's
     own parameters: response words equal the oracle's, decryption equals the
     integer dot products."""
+    _small_end_to_end(pair, None)
+
+
+def test_small_end_to_end_radix8(pair):
+    """The same with the key-switch transforms in radix-8 passes (n/8 threads
+    per transform), the tuner's other NTT radix."""
+    _small_end_to_end(pair, 8)
+
+
+def _small_end_to_end(pair, radix):
     from paper_2406_06761_amd.wally import query_array, to_device, to_host
 
     name, c, o = pair
@@ -135,6 +145,11 @@ def test_small_end_to_end(pair):
     dev = [(to_device(ct), to_device(kb), to_device(kg)) for ct, kb, kg, _ in packets]
     q = query_array(targets, [d[0].data_ptr() for d in dev], [d[1].data_ptr() for d in dev],
                     [d[2].data_ptr() for d in dev], [x.data_ptr() for x in outs])
+    if radix:
+        res = c.tune(q, radices=(radix,))  # one candidate: the context keeps it
+        assert [r[3] for r in res] == [radix]
+        for x in outs:
+            x.zero_()
     c.score_batch(q)
     torch.cuda.synchronize()
     pts = [o.encode_cluster(emb[int(offs[k]) : int(offs[k + 1])]) for k in range(2)]
@@ -378,8 +393,8 @@ def test_tuner_picks_a_config_and_stays_exact(tiny_workload):
     try:
         c.encode_clusters(emb, offs)
         q, outs, keep = _tiny_queries(o, w, packets)
-        res = c.tune(q, batches=(4, 16), sets=(1, 2), tiles=(4, 16))
-        assert len(res) == 8 and all(r[3] > 0 for r in res)
+        res = c.tune(q, batches=(4, 16), sets=(1, 2), tiles=(4, 16), radices=(8, 16))
+        assert len(res) == 16 and all(r[4] > 0 for r in res) and {r[3] for r in res} == {8, 16}
         outs.zero_()
         c.score_batch(q, path=PATH_BATCHED)
         torch.cuda.synchronize()
