@@ -748,9 +748,15 @@ def main():
         torch.cuda.synchronize()
         cdt = time.perf_counter() - t0
         in_b, out_b = chunks_out * ctw * 8, chunks_out * cb
+        # one fused kernel per response part: L inverse transforms, the exact
+        # rounding to q_0 and the packing; the transforms alone are 2 L inverse
+        # NTTs per response at the compiled instruction cost
+        bf = n // 2 * int(math.log2(n))
+        intt_instr = chunks_out * 2 * L * (bf * INSTR["bfly_inv"] + n * INSTR["scale"])
         compress = {"chunks": chunks_out, "ms": cdt * 1e3, "bytes_in": in_b, "bytes_out": out_b,
                     "ratio": in_b / out_b, "chunks_per_s": chunks_out / cdt,
                     "hbm_gbs": (in_b + out_b) / cdt / 1e9, "hbm_frac": (in_b + out_b) / cdt / HBM_PEAK,
+                    "bound": "alu", "alu_frac_transforms": intt_instr / cdt / PEAK_VALU_LANE_OPS,
                     "drop_bits": list(info.drop_bits), "widths": list(info.compressed_widths)}
         log(f"compress: {chunks_out} responses in {cdt * 1e3:.1f} ms, {in_b / out_b:.2f}x smaller, "
             f"{(in_b + out_b) / cdt / 1e9:.0f} GB/s of response bytes")

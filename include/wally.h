@@ -189,9 +189,10 @@ int wally_encode_clusters_i16(wally_ctx* ctx, const int16_t* emb, uint64_t n_ent
  * (value k in stream bits [k w, (k+1) w), stream bit b = bit b%8 of byte b/8).
  * `out` (device) receives [chunks][compressed_chunk_bytes]: part 0, then part
  * 1.  A client recovers c' ~ v 2^l mod q_0 and decrypts at modulus q_0.  Work
- * is enqueued on hip_stream; the context's scratch is shared, so a call runs
- * after the previous call's work, whatever stream that was on.  EINVAL for
- * null or misaligned pointers. */
+ * is enqueued on hip_stream and uses no workspace (calls on different streams
+ * are independent).  in: 8-byte aligned; out: 4-byte aligned (the packed
+ * stream is written in 32-bit words).  EINVAL for null or misaligned
+ * pointers. */
 int wally_compress_responses(wally_ctx* ctx, const uint64_t* in, uint64_t chunks, uint8_t* out, void* hip_stream);
 
 /* Where cluster c sits in the encoded index, so that a client can map

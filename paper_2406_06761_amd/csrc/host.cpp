@@ -89,9 +89,8 @@ uint64_t min_root(uint64_t q, uint64_t two_n) {
 
 uint64_t shoup_of(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
 
-// responses compressed per pass (the coefficient-form scratch is this many
-// ciphertexts: 512 MiB at n = 8192, L = 4)
-constexpr uint64_t kCompressBatch = 1024;
+// responses compressed per launch
+constexpr uint64_t kCompressBatch = 1u << 20;
 
 // little-endian multi-word integers for the compression constants
 void mw_mul_small(std::vector<uint64_t>& x, uint64_t m) {
@@ -135,6 +134,7 @@ bool compress_constants(const uint64_t* mods, int L, int log_n, uint64_t t, Comp
     a.mq0p[i] = shoup_of(a.mq0[i], q0);
   }
   a.qpq0 = mw_mod_small(qp, q0);
+  a.qpq0p = shoup_of(a.qpq0, q0);
   a.qpinv = powmod(a.qpq0, q0 - 2, q0);
   a.qpinvp = shoup_of(a.qpinv, q0);
   const double n = (double)(1u << log_n);
@@ -246,11 +246,8 @@ struct wally_ctx {
   Pir2Consts* pir2_K = nullptr;
   ulonglong2* pir2_tables = nullptr;
   uint64_t *pir2_col = nullptr, *pir2_cf = nullptr, *pir2_ext = nullptr, *pir2_x3 = nullptr, *pir2_c3 = nullptr;
-  // response compression: constants and a coefficient-form scratch
+  // response compression constants
   CompressArgs comp{};
-  uint64_t* comp_scratch = nullptr;
-  uint64_t comp_scratch_chunks = 0;
-  hipEvent_t comp_done = nullptr;  // recorded after each compression call
   // wally_score_batch_static: the device's static scratch, pinned host
   // staging for the descriptors of two waves, and their events
   unsigned char* static_scratch = nullptr;
@@ -944,26 +941,14 @@ int wally_compress_responses(wally_ctx* c, const uint64_t* in, uint64_t chunks, 
   if (chunks == 0) return WALLY_OK;
   if (!in || !out) return set_err(c, WALLY_EINVAL, "null response or output pointer");
   if ((uintptr_t)in & 7) return set_err(c, WALLY_EINVAL, "responses must be 8-byte aligned");
-  const uint64_t batch = std::min<uint64_t>(chunks, kCompressBatch);
-  if (c->comp_scratch_chunks < batch) {
-    if (c->comp_done) HIP_OK(c, hipEventSynchronize(c->comp_done));  // the last call may still read it
-    dfree(c, c->comp_scratch);
-    c->comp_scratch = nullptr;
-    c->comp_scratch_chunks = 0;
-    if ((rc = dalloc(c, batch * c->ctw() * 8, (void**)&c->comp_scratch))) return rc;
-    c->comp_scratch_chunks = batch;
-  }
+  if ((uintptr_t)out & 3) return set_err(c, WALLY_EINVAL, "the output must be 4-byte aligned");
   hipStream_t st = (hipStream_t)hip_stream;
-  // the scratch is shared: a call on another stream runs after the last one
-  if (c->comp_done) HIP_OK(c, hipStreamWaitEvent(st, c->comp_done, 0));
-  else HIP_OK(c, hipEventCreateWithFlags(&c->comp_done, hipEventDisableTiming));
   const uint64_t cbytes = c->comp.part_bytes[0] + c->comp.part_bytes[1];
-  for (uint64_t b0 = 0; b0 < chunks; b0 += batch) {
-    const int nb = (int)std::min(batch, chunks - b0);
-    HIP_OK(c, launch_resp_intt(in + b0 * c->ctw(), c->comp_scratch, nb, c->log_n, c->L, c->M, st));
-    HIP_OK(c, launch_resp_pack(c->comp_scratch, out + b0 * cbytes, nb, c->comp, c->M, st));
+  // two workgroups per response; launches of at most 2^30 workgroups
+  for (uint64_t b0 = 0; b0 < chunks; b0 += kCompressBatch) {
+    const int nb = (int)std::min(kCompressBatch, chunks - b0);
+    HIP_OK(c, launch_resp_compress(in + b0 * c->ctw(), out + b0 * cbytes, nb, c->comp, c->M, st));
   }
-  HIP_OK(c, hipEventRecord(c->comp_done, st));
   return WALLY_OK;
 }
 
@@ -1451,7 +1436,6 @@ void wally_destroy(wally_ctx* c) {
   while (!c->allocs.empty()) dfree(c, c->allocs.back().first);
   if (c->fork) (void)hipEventDestroy(c->fork);
   if (c->graph_done) (void)hipEventDestroy(c->graph_done);
-  if (c->comp_done) (void)hipEventDestroy(c->comp_done);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (int k = 0; k < 2; ++k) {
     if (c->static_host[k]) (void)hipHostFree(c->static_host[k]);

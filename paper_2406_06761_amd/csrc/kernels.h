@@ -76,7 +76,7 @@ struct CompressArgs {
   uint64_t m[kMaxMod][kMaxWords];      // Q'/q_i, i = 1 .. L-1
   uint64_t minv[kMaxMod], minvp[kMaxMod];  // (Q'/q_i)^-1 mod q_i and Shoup factor
   uint64_t mq0[kMaxMod], mq0p[kMaxMod];    // Q'/q_i mod q_0 and Shoup factor
-  uint64_t qpq0;                       // Q' mod q_0
+  uint64_t qpq0, qpq0p;                // Q' mod q_0 and Shoup factor
   uint64_t qpinv, qpinvp;              // Q'^-1 mod q_0 and Shoup factor
 };
 
@@ -178,12 +178,10 @@ hipError_t launch_ks_moddown(const KsItem* items, int n_items, const KsArgs& a, 
 // acc_i = sum_{j<g} PT[g i + j] * ct'_j for every giant index i of every item
 hipError_t launch_mac_tiles(const KsItem* items, const MacTile* tiles, int n_tiles, const KsArgs& a, int h,
                             const DevModuli& M, hipStream_t st);
-// rows [chunks][2][L][n], NTT form -> coefficient form in [0, q_i) (in to out)
-hipError_t launch_resp_intt(const uint64_t* in, uint64_t* out, int chunks, int log_n, int L, const DevModuli& M,
-                            hipStream_t st);
-// coefficient rows [chunks][2][L][n] -> serialized responses [chunks][part_bytes[0] + part_bytes[1]]
-hipError_t launch_resp_pack(const uint64_t* coef, uint8_t* out, int chunks, const CompressArgs& a, const DevModuli& M,
-                            hipStream_t st);
+// responses [chunks][2][L][n] (NTT form mod Q) -> serialized [chunks][part_bytes[0] + part_bytes[1]]
+// (out 4-byte aligned)
+hipError_t launch_resp_compress(const uint64_t* in, uint8_t* out, int chunks, const CompressArgs& a,
+                                const DevModuli& M, hipStream_t st);
 // register-resident butterfly loop (diagnostic): out [blocks * 256][16]
 hipError_t launch_bfly_rate(uint64_t* out, int blocks, int inverse, const ulonglong2* w, uint64_t q, int iters,
                             hipStream_t st);

@@ -863,117 +863,129 @@ __global__ __launch_bounds__(256) void k_bfly_rate(uint64_t* __restrict__ out, u
 // ---------------------------------------------------------------------------
 // response compression (paper §7.1, "Reducing the response size")
 
-// one row per workgroup: row r of [chunks][2][L][n] is limb r mod L
-template <int LOGN>
-__global__ __launch_bounds__((NttShape<LOGN, 4>::T)) void k_resp_intt(const uint64_t* __restrict__ in,
-                                                                      uint64_t* __restrict__ out, int L, DevModuli M) {
-  using S = NttShape<LOGN, 4>;
-  using FM = FirstMap<LOGN, 4>;
+// One workgroup per ciphertext part: the L limbs are transformed to
+// coefficient form one after another (each thread keeps its 16 coefficients
+// of every limb in registers, as r_0 and y_i = r_i (Q'/q_i)^-1 mod q_i), each
+// coefficient is switched to q_0 with exact rounding and its low bits dropped,
+// and the part's values are packed through LDS into coalesced 32-bit words of
+// the little-endian bit stream.  Input rows are read once; nothing goes back
+// to memory but the packed bytes.
+template <int LOGN, int L>
+__global__ __launch_bounds__((NttShape<LOGN, 3>::T)) void k_resp_compress(const uint64_t* __restrict__ in,
+                                                                          uint8_t* __restrict__ out, CompressArgs a,
+                                                                          DevModuli M) {
+  using S = NttShape<LOGN, 3>;  // 8 words per thread: the L limbs' coefficients stay in registers
+  using FM = FirstMap<LOGN, 3>;
+  constexpr int YL = L > 1 ? L - 1 : 1;
   __shared__ uint64_t lds[S::LDS_WORDS];
   const int tid = threadIdx.x;
-  const int mi = (int)(blockIdx.x % (uint32_t)L);
-  const uint64_t q = M.q[mi];
-  const uint64_t* src = in + (uint64_t)blockIdx.x * S::N;
-  uint64_t* dst = out + (uint64_t)blockIdx.x * S::N;
-  uint64_t x[16];
+  const uint64_t chunk = blockIdx.x >> 1;
+  const int part = (int)(blockIdx.x & 1);
+  WALLY_GLOBAL const uint64_t* src = gmem(in) + (chunk * 2 + part) * (uint64_t)L * S::N;
+  uint64_t r0[S::E], y[YL][S::E];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) x[e] = src[FM::idx(tid, e)];
-  ntt_inv_nat<LOGN, 4>(x, lds, M.inv[mi], q, tid);
+  for (int i = 0; i < L; ++i) {
+    const uint64_t q = M.q[i];
+    uint64_t x[S::E];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) dst[FM::idx(tid, e)] = csub(shoup(x[e], M.ninv[mi], M.ninvp[mi], q), q);
-}
-
-// a += y * m (multi-word, `words` words of m, a has words + 1)
-__device__ __forceinline__ void mw_mac(uint64_t* acc, uint64_t y, const uint64_t* m, int words) {
-  uint64_t carry = 0;
-  for (int w = 0; w < words; ++w) {
-    const uint64_t lo = y * m[w], hi = __umul64hi(y, m[w]);
-    uint64_t s = acc[w] + lo;
-    uint64_t c = s < lo;
-    s += carry;
-    c += s < carry;
-    acc[w] = s;
-    carry = hi + c;
+    for (int e = 0; e < S::E; ++e) x[e] = __builtin_nontemporal_load(&src[(uint64_t)i * S::N + FM::idx(tid, e)]);
+    ntt_inv_nat<LOGN, 3>(x, lds, M.inv[i], q, tid);
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) {
+      const uint64_t v = csub(shoup(x[e], M.ninv[i], M.ninvp[i], q), q);  // coefficient mod q_i
+      if (i == 0) r0[e] = v;
+      else y[(i + YL - 1) % YL][e] = csub(shoup(v, a.minv[i], a.minvp[i], q), q);
+    }
   }
-  acc[words] += carry;
-}
-
-// thread per (chunk, part, group of 8 coefficients); the group's 8 values of
-// width w are written as w consecutive bytes (little-endian bit stream)
-__global__ __launch_bounds__(256) void k_resp_pack(const uint64_t* __restrict__ coef, uint8_t* __restrict__ out,
-                                                   int chunks, CompressArgs a, DevModuli M) {
-  const uint64_t n = 1ull << a.log_n;
-  const uint64_t groups = n / 8;
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (uint64_t)chunks * 2 * groups) return;
-  const uint64_t g = gid % groups;
-  const int part = (int)((gid / groups) & 1);
-  const uint64_t chunk = gid / (2 * groups);
-  const int L = a.L, W = a.words;
   const uint64_t q0 = M.q[0];
   const ModConst mc0 = M.mc[0];
-  const uint64_t* rows = coef + ((chunk * 2 + part) * L) * n + g * 8;
   const uint32_t l = a.drop[part], w = a.width[part];
-  const uint64_t half = l ? (1ull << (l - 1)) : 0, mask = (w == 64) ? ~0ull : ((1ull << w) - 1);
-  uint8_t* o = out + chunk * (a.part_bytes[0] + a.part_bytes[1]) + (part ? a.part_bytes[0] : 0) + g * w;
-  uint64_t bits = 0;
-  uint32_t nb = 0;
-  for (int k = 0; k < 8; ++k) {
-    uint64_t S[kMaxWords + 1] = {0, 0, 0, 0, 0, 0, 0};
-    u128w rq{0, 0};  // sum_i y_i [Q'/q_i]_{q0}
+  const uint64_t half = l ? (1ull << (l - 1)) : 0, mask = (w >= 64) ? ~0ull : ((1ull << w) - 1);
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) {
+    // c' = round(c / Q') mod q_0 = (r_0 - [sum_i y_i Q'/q_i - k Q']_{q0}) Q'^-1 with
+    // k = round(sum_i y_i Q'/q_i / Q'), found exactly on the multi-word sum
+    uint64_t acc[kMaxWords + 1];
+#pragma unroll
+    for (int wd = 0; wd <= kMaxWords; ++wd) acc[wd] = 0;
+    u128w rq{0, 0};
+#pragma unroll
     for (int i = 1; i < L; ++i) {
-      const uint64_t qi = M.q[i];
-      const uint64_t y = csub(shoup(rows[(uint64_t)i * n + k], a.minv[i], a.minvp[i], qi), qi);
-      mw_mac(S, y, a.m[i], W);
-      mac128(rq, y, a.mq0[i]);
+      const uint64_t yi = y[i - 1][e];
+      uint64_t carry = 0;
+#pragma unroll
+      for (int wd = 0; wd < kMaxWords; ++wd) {
+        const uint64_t mw = a.m[i][wd];
+        const uint64_t lo = yi * mw, hi = __umul64hi(yi, mw);
+        uint64_t sm = acc[wd] + lo;
+        uint64_t cy = sm < lo;
+        sm += carry;
+        cy += sm < carry;
+        acc[wd] = sm;
+        carry = hi + cy;
+      }
+      acc[kMaxWords] += carry;
+      mac128(rq, yi, a.mq0[i]);
     }
-    // k = round(S / Q'): subtract Q' while S >= Q', then one more if 2 S > Q'
     uint32_t kc = 0;
-    for (;;) {
-      bool ge = true;  // S >= Q'
-      for (int wd = W; wd >= 0; --wd) {
-        const uint64_t qw = wd < W ? a.qp[wd] : 0;
-        if (S[wd] != qw) {
-          ge = S[wd] > qw;
-          break;
-        }
+    bool done = false;
+#pragma unroll
+    for (int it = 0; it < L; ++it) {  // the sum is below (L - 1) Q'
+      bool gt = false, lt = false;
+#pragma unroll
+      for (int wd = kMaxWords; wd >= 0; --wd) {
+        const uint64_t qw = wd < kMaxWords ? a.qp[wd] : 0;
+        const bool und = !gt && !lt;
+        gt = gt || (und && acc[wd] > qw);
+        lt = lt || (und && acc[wd] < qw);
       }
-      if (!ge) break;
+      done = done || lt;
       uint64_t br = 0;
-      for (int wd = 0; wd <= W; ++wd) {
-        const uint64_t qw = wd < W ? a.qp[wd] : 0;
-        const uint64_t d = S[wd] - qw - br;
-        br = (S[wd] < qw) || (S[wd] - qw < br);
-        S[wd] = d;
+#pragma unroll
+      for (int wd = 0; wd <= kMaxWords; ++wd) {
+        const uint64_t qw = done ? 0 : (wd < kMaxWords ? a.qp[wd] : 0);
+        const uint64_t d = acc[wd] - qw;
+        const uint64_t b1 = acc[wd] < qw;
+        const uint64_t d2 = d - br;
+        br = b1 | (d < br);
+        acc[wd] = d2;
       }
-      ++kc;
+      kc += done ? 0 : 1;
     }
-    {  // 2 S > Q'  (S < Q' here, so 2 S fits in W + 1 words)
-      bool gt = false;
-      for (int wd = W; wd >= 0; --wd) {
-        const uint64_t two = (S[wd] << 1) | (wd ? S[wd - 1] >> 63 : 0);
-        const uint64_t qw = wd < W ? a.qp[wd] : 0;
-        if (two != qw) {
-          gt = two > qw;
-          break;
-        }
+    {  // round up when 2 (remainder) > Q' (Q' is odd: no ties)
+      bool gt = false, lt = false;
+#pragma unroll
+      for (int wd = kMaxWords; wd >= 0; --wd) {
+        const uint64_t two = (acc[wd] << 1) | (wd ? acc[wd - 1] >> 63 : 0);
+        const uint64_t qw = wd < kMaxWords ? a.qp[wd] : 0;
+        const bool und = !gt && !lt;
+        gt = gt || (und && two > qw);
+        lt = lt || (und && two < qw);
       }
       kc += gt;
     }
     const uint64_t rmod = reduce128(rq, q0, mc0.r64, mc0.r64p, mc0.onep);
-    uint64_t kq = 0;  // k [Q']_{q0}, k <= L - 1
-    for (uint32_t r = 0; r < kc; ++r) kq = addmod(kq, a.qpq0, q0);
-    const uint64_t rc = submod(rmod, kq, q0);                  // [centred remainder]_{q0}
-    const uint64_t d = submod(rows[k], rc, q0);                 // r_0 - r_c
+    const uint64_t kq = csub(shoup((uint64_t)kc, a.qpq0, a.qpq0p, q0), q0);  // k [Q']_{q0}
+    const uint64_t rc = submod(rmod, kq, q0);
+    const uint64_t d = submod(r0[e], rc, q0);
     const uint64_t cp = csub(shoup(d, a.qpinv, a.qpinvp, q0), q0);  // c' in [0, q0)
-    const uint64_t v = ((cp + half) >> l) & mask;
-    bits |= v << nb;
-    nb += w;
-    while (nb >= 8) {
-      *o++ = (uint8_t)bits;
-      bits >>= 8;
-      nb -= 8;
+    lds[FM::idx(tid, e)] = ((cp + half) >> l) & mask;  // the last exchange ended with a barrier
+  }
+  __syncthreads();
+  const uint64_t nwords = (uint64_t)S::N * w / 32;
+  WALLY_GLOBAL uint32_t* o = (WALLY_GLOBAL uint32_t*)(gmem(out) + chunk * (a.part_bytes[0] + a.part_bytes[1]) +
+                                                      (part ? a.part_bytes[0] : 0));
+  for (uint64_t word = tid; word < nwords; word += S::T) {
+    const uint64_t b = word * 32;
+    uint64_t k = b / w;
+    const uint32_t off = (uint32_t)(b - k * w);
+    uint64_t v = lds[k] >> off;
+    uint32_t have = w - off;
+    for (++k; have < 32 && k < (uint64_t)S::N; ++k) {
+      v |= lds[k] << have;
+      have += w;
     }
+    o[word] = (uint32_t)v;
   }
 }
 
@@ -1162,24 +1174,30 @@ hipError_t launch_bfly_rate(uint64_t* out, int blocks, int inverse, const ulongl
   return hipGetLastError();
 }
 
-hipError_t launch_resp_intt(const uint64_t* in, uint64_t* out, int chunks, int log_n, int L, const DevModuli& M,
-                            hipStream_t st) {
+hipError_t launch_resp_compress(const uint64_t* in, uint8_t* out, int chunks, const CompressArgs& a,
+                                const DevModuli& M, hipStream_t st) {
   if (chunks <= 0) return hipSuccess;
-  const dim3 grid((uint32_t)chunks * 2 * (uint32_t)L);
-  switch (log_n) {
-    case 12: hipLaunchKernelGGL(k_resp_intt<12>, grid, dim3(NttShape<12, 4>::T), 0, st, in, out, L, M); break;
-    case 13: hipLaunchKernelGGL(k_resp_intt<13>, grid, dim3(NttShape<13, 4>::T), 0, st, in, out, L, M); break;
+  const dim3 grid((uint32_t)chunks * 2);
+#define WALLY_COMPRESS_L(LOGN)                                                                                \
+  switch (a.L) {                                                                                              \
+    case 1: hipLaunchKernelGGL((k_resp_compress<LOGN, 1>), grid, dim3(NttShape<LOGN, 3>::T), 0, st, in, out, a, M); break; \
+    case 2: hipLaunchKernelGGL((k_resp_compress<LOGN, 2>), grid, dim3(NttShape<LOGN, 3>::T), 0, st, in, out, a, M); break; \
+    case 3: hipLaunchKernelGGL((k_resp_compress<LOGN, 3>), grid, dim3(NttShape<LOGN, 3>::T), 0, st, in, out, a, M); break; \
+    case 4: hipLaunchKernelGGL((k_resp_compress<LOGN, 4>), grid, dim3(NttShape<LOGN, 3>::T), 0, st, in, out, a, M); break; \
+    case 5: hipLaunchKernelGGL((k_resp_compress<LOGN, 5>), grid, dim3(NttShape<LOGN, 3>::T), 0, st, in, out, a, M); break; \
+    case 6: hipLaunchKernelGGL((k_resp_compress<LOGN, 6>), grid, dim3(NttShape<LOGN, 3>::T), 0, st, in, out, a, M); break; \
+    case 7: hipLaunchKernelGGL((k_resp_compress<LOGN, 7>), grid, dim3(NttShape<LOGN, 3>::T), 0, st, in, out, a, M); break; \
+    case 8: hipLaunchKernelGGL((k_resp_compress<LOGN, 8>), grid, dim3(NttShape<LOGN, 3>::T), 0, st, in, out, a, M); break; \
+    default: return hipErrorInvalidValue;                                                                     \
+  }
+  switch (a.log_n) {
+    case 12: WALLY_COMPRESS_L(12) break;
+    case 13: WALLY_COMPRESS_L(13) break;
     default: return hipErrorInvalidValue;
   }
+#undef WALLY_COMPRESS_L
   return hipGetLastError();
 }
 
-hipError_t launch_resp_pack(const uint64_t* coef, uint8_t* out, int chunks, const CompressArgs& a, const DevModuli& M,
-                            hipStream_t st) {
-  if (chunks <= 0) return hipSuccess;
-  const uint64_t threads = (uint64_t)chunks * 2 * ((1ull << a.log_n) / 8);
-  hipLaunchKernelGGL(k_resp_pack, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, st, coef, out, chunks, a, M);
-  return hipGetLastError();
-}
 
 }  // namespace wally
