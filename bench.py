@@ -543,6 +543,8 @@ def main():
     ap.add_argument("--out-ring", type=int, default=0,
                     help="response chunk slots shared round robin (0 = a private response per query when it fits)")
     ap.add_argument("--max-batch", type=int, default=0)
+    ap.add_argument("--calls", type=int, default=1,
+                    help="score each step's batch in this many consecutive calls (progress lines on long batches)")
     ap.add_argument("--wave-sets", type=int, default=0)
     ap.add_argument("--pool", type=int, default=2048, help="distinct query packets resident on the device")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-cluster path (0 = skip)")
@@ -681,9 +683,20 @@ def main():
         log(f"tuner: {len(res)} configs in {time.perf_counter() - t0:.1f} s, chose B={best[0]} "
             f"sets={best[1]} tile={best[2]} radix={best[3]} ({best[4]:.1f} ms on {len(sub)} queries)")
 
+    # a step is one batch; --calls splits it into consecutive calls of equal
+    # query ranges (each call returns when its last waves are staged, so the
+    # log shows the batch's progress on long batches)
+    parts = [(int(p_[0]), int(p_[-1]) + 1) for p_ in np.array_split(np.arange(nq), max(1, args.calls))]
+
+    def score_step(tag, t0):
+        for k, (a_, b_) in enumerate(parts):
+            ctx.score_batch(q[a_:b_], path=PATH_BATCHED)
+            if len(parts) > 1:
+                log(f"{tag}: queries {a_}..{b_ - 1} enqueued at {time.perf_counter() - t0:.1f} s")
+
     for i in range(args.warmup):
         t0 = time.perf_counter()
-        ctx.score_batch(q, path=PATH_BATCHED)
+        score_step(f"warmup {i}", t0)
         torch.cuda.synchronize()
         log(f"warmup {i}: {time.perf_counter() - t0:.3f} s")
 
@@ -694,7 +707,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        ctx.score_batch(q, path=PATH_BATCHED)
+        score_step(f"step {i}", t0)
         log(f"step {i} enqueued at {time.perf_counter() - t0:.3f} s")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -995,7 +1008,7 @@ def main():
                    "params": f"n={n}, L={L} x {54 if n == 8192 else 36}-bit limbs, t={info.t}",
                    "queries": nq, "real_queries": w.n_real, "scores_per_step": scores,
                    "real_scores_per_step": real_scores, "pool_packets": pool,
-                   "max_batch": args.max_batch or 512, "wave_sets": args.wave_sets or 2,
+                   "max_batch": args.max_batch or 512, "wave_sets": args.wave_sets or 2, "calls_per_step": args.calls,
                    "schedule": (tuned or {}).get("chosen")},
         "real_scores_per_s": real_scores * args.steps / dt,
         "queries_per_s": nq * args.steps / dt,

@@ -20,7 +20,8 @@ paper §7.3 the centred lift mod t is the integer dot product).
   theirs);
 * large: 8M x 384 entries in 4,000 lognormal(1.0) clusters, t just above 2^23,
   (g, h) = (32, 16), co-packed layout (per cluster it would need ~518 GiB);
-  the first 8,192 logical queries of the 1M-query batch plus the samples.
+  the whole batch of 1,000,000 real queries + fakes (two calls of half the
+  batch), sampled from its end, responses through a ring of slots.
 """
 import numpy as np
 import pytest
@@ -40,7 +41,7 @@ def _query_vec(w, i):
     return synth.embeddings(1, w.dim, seed=synth.SEED_QUERIES, norm=w.norm, row_start=i)[0]
 
 
-def _sampled_parity(ctx, p, w, emb, lay, batch, picks, path, ring=0, pool=2048, compress=False):
+def _sampled_parity(ctx, p, w, emb, lay, batch, picks, path, ring=0, pool=2048, compress=False, calls=1):
     """Score logical queries `batch` of workload `w` (picks get real packets),
     then check picks and a few pool-packet queries against the oracle."""
     from paper_2406_06761_amd.wally import query_array, to_device, to_host
@@ -86,10 +87,11 @@ def _sampled_parity(ctx, p, w, emb, lay, batch, picks, path, ring=0, pool=2048, 
         keep.append((k, vec, ct, kb, kg, s, d))
         ct_ptr[k], kb_ptr[k], kg_ptr[k] = d[0].data_ptr(), d[1].data_ptr(), d[2].data_ptr()
     q = query_array(targets, ct_ptr, kb_ptr, kg_ptr, outs.data_ptr() + out_off * ctw * 8)
-    print(f"{w.name}: scoring {nq} queries (path {path})", flush=True)
-    ctx.score_batch(q, path=path)
-    torch.cuda.synchronize()
-    print(f"{w.name}: scored", flush=True)
+    print(f"{w.name}: scoring {nq} queries (path {path}, {calls} call(s))", flush=True)
+    for part in np.array_split(np.arange(nq), calls):
+        ctx.score_batch(q[part[0] : part[-1] + 1], path=path)
+        torch.cuda.synchronize()
+        print(f"{w.name}: scored queries {part[0]}..{part[-1]}", flush=True)
 
     def cluster_pt(c):
         return np.concatenate([o.encode_cluster(layout.chunk_rows(lay, lay.first[c] + j, emb, offs))
@@ -231,10 +233,14 @@ def test_large_copack_sampled_parity():
         _check_layout(ctx, lay, p, 13)
         real, counts, chosen = _hot_cold_multi(w, lay)
         chosen.append(next(int(c) for c in np.argsort(-counts) if lay.base[int(c)] > 0 and int(c) not in chosen))
-        picks = {int(np.nonzero(real == c)[0][0]) for c in chosen}
-        batch = sorted(set(range(8192)) | picks)
-        checked = _sampled_parity(ctx, p, w, emb, lay, batch, picks, PATH_BATCHED, pool=256)
-        assert checked >= 6
+        # the whole 1,008,108-query batch (two calls of half the batch, about a
+        # minute and a quarter each); samples from its end (the
+        # last real query of each chosen cluster and the last fake); the ~1.6 TB
+        # of responses share a ring of response slots
+        picks = {int(np.nonzero(real == c)[0][-1]) for c in chosen} | {len(w.targets) - 1}
+        checked = _sampled_parity(ctx, p, w, emb, lay, range(len(w.targets)), picks, PATH_BATCHED, ring=16384,
+                                  pool=256, calls=2)
+        assert checked >= 7
     finally:
         ctx.close()
 
