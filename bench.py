@@ -732,6 +732,14 @@ def main():
             roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                         "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
                         "bytes_per_item": inner_bytes(n, L)}
+        elif len(per_item_units(dom, n, L, info.g, info.h)) > 1:  # mixed units: VALU lane-instructions
+            ins = per_item_instr(dom, n, L, info.g, info.h)
+            achieved = ins * items_per_launch / (avg_ms * 1e-3)
+            roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e9, "peak": PEAK_VALU_LANE_OPS / 1e9,
+                        "unit": "G VALU lane-instructions/s", "frac": achieved / PEAK_VALU_LANE_OPS, "traffic": None,
+                        "work_per_item": per_item_units(dom, n, L, info.g, info.h),
+                        "peak_derivation": "256 CU x 64 lanes x 2.4 GHz; work at the compiled instruction cost of "
+                                           "each unit"}
         else:
             achieved = work[dom] * items_per_launch / (avg_ms * 1e-3)
             roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e9, "peak": peak / 1e9,
@@ -820,7 +828,7 @@ def main():
             f"inverse {measured['inverse']:.4g}/s")
         if roofline is not None:
             roofline["isolated"] = isolated
-            if roofline["bound"] == "alu":
+            if roofline["bound"] == "alu" and roofline["unit"] == "Gbutterfly/s":
                 roofline["peak_measured"] = measured["forward"] / 1e9
                 roofline["frac_of_measured_peak"] = roofline["achieved"] * 1e9 / measured["forward"]
             roofline["bfly_rate_measured"] = measured
