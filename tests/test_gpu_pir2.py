@@ -142,3 +142,55 @@ def test_pir2_rejects_bad_input():
             ctx.pir_answer2(np.zeros(1, dtype=PIR_QUERY2_DTYPE))
     finally:
         ctx.close()
+
+
+def test_keyword_pir_both_dimensions():
+    """Keyword PIR (paper §4.2) with one answer ciphertext per table: 700
+    entries of 256 bytes in split cuckoo tables over plaintext buckets; for
+    each keyword the client sends one two-index query per table (row and
+    column of its bucket) and decrypts the single answer.  Present keywords
+    come back from exactly one table, an absent one from neither."""
+    from paper_2406_06761_amd import keyword as kw
+    from paper_2406_06761_amd.wally import PIR_QUERY2_DTYPE, Context, to_device, to_host
+
+    p = preset("tiny")
+    o = Oracle(p)
+    rng = np.random.default_rng(18)
+    eb = 256
+    items = {b"doc-%d" % i: rng.integers(0, 256, rng.integers(1, eb - kw.TAG_BYTES + 1), dtype=np.uint8).tobytes()
+             for i in range(700)}
+    t = kw.build(items, p.n, eb, seed=9)
+    d1, d2 = kw.shape(t.size)
+    c_lv = pir.levels2(d1, d2)
+    lookups = [b"doc-0", b"doc-351", b"doc-699", b"nowhere"]
+    found = {k: [] for k in lookups}
+    ctx = Context.preset("tiny")
+    try:
+        for side in (0, 1):
+            ctx.pir_encode(kw.pack(t, side, p.n))
+            levels, a0, gals, _ = ctx.pir_info2()
+            assert levels == c_lv
+            packets = []
+            for key in lookups:
+                r, col = kw.locate(key, t.size, t.seed)[side]
+                s = o.secret_key(rng)
+                packets.append((to_device(pir.query2(o, s, r, col, d1, c_lv, rng)),
+                                to_device(pir.make_keys(o, s, c_lv, rng, a0)), to_device(o.relin_key(s, rng)), s))
+            outs = torch.zeros((len(lookups), 2, p.L, p.n), dtype=torch.int64, device="cuda")
+            q = np.zeros(len(lookups), dtype=PIR_QUERY2_DTYPE)
+            q["ct"] = [pk[0].data_ptr() for pk in packets]
+            q["keys"] = [pk[1].data_ptr() for pk in packets]
+            q["relin_key"] = [pk[2].data_ptr() for pk in packets]
+            q["out"] = [outs[i].data_ptr() for i in range(len(lookups))]
+            ctx.pir_answer2(q)
+            torch.cuda.synchronize()
+            got = to_host(outs)
+            for i, key in enumerate(lookups):
+                v = kw.extract(pir.decrypt_poly(o, packets[i][3], got[i]), key, eb)
+                if v is not None:
+                    found[key].append(v)
+    finally:
+        ctx.close()
+    assert found[b"nowhere"] == []
+    for key in lookups[:3]:
+        assert len(found[key]) == 1 and found[key][0][: len(items[key])] == items[key], key
