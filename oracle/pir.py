@@ -26,6 +26,23 @@ slot plaintexts of the scoring path) and held in NTT form.
 Subs(x, g) is the automorphism X -> X^g followed by key switching, i.e. the
 oracle's rotate() with Galois element g.
 
+Linearised last level (paper §4.2, "Linearizing parts of query expansion":
+some substitutions of the expansion become linear operations on x and its
+automorphic image).  Key switching is linear, so the key switch of the last
+level can move past the first dimension's plaintext products and sums: at
+level c-1 a pair whose outputs are both row entries (or unused) is expanded
+with z = x(X^g) (the automorphism alone, a ciphertext under s(X^g)) into
+three-part ciphertexts (u0, u1, u2) that decrypt as u0 + u1 s + u2 s(X^g):
+    (x0 + z0, x1, z1)                                   at b,
+    ((x0 - z0) X^(-2^a), x1 X^(-2^a), -z1 X^(-2^a))     at b + 2^a.
+The other pairs (those with a column entry of a two-index query) are
+expanded as before, with a zero third part.  Each first-dimension column is
+then a three-part sum (U0, U1, U2), and one key switch per column with the
+query's key of g_(c-1) (the identity automorphism on (U0, U2), then + U1)
+makes it an ordinary ciphertext.  That replaces the key switches of the
+linearised pairs, 2^(c-1) of them for a one-index query, by d2.  This
+reading is ours: the paper describes the optimisation in one sentence.
+
 Both dimensions (paper §4.2, "Overview of MulPIR"; §7.1, "Reducing the
 computation of BFV operations"):
 
@@ -129,13 +146,14 @@ def _add(oracle, a, b):
     return (a + b) % q
 
 
-def expand(oracle, ct, keys, c: int, a0=None):
-    """The 2^c expanded ciphertexts [2^c][2][L][n] of one query."""
+def expand(oracle, ct, keys, c: int, a0=None, upto=None):
+    """The 2^c expanded ciphertexts [2^c][2][L][n] of one query (with upto:
+    only the levels a < upto of the c-level expansion, 2^upto ciphertexts)."""
     n = oracle.n
     a0 = first_key_level(n, c) if a0 is None else a0
     assert a0 <= first_key_level(n, c)
     cts = [np.asarray(ct, dtype=np.uint64)]
-    for a in range(c):
+    for a in range(c if upto is None else upto):
         ka = max(a, a0)
         key, g = keys[ka - a0], galois(n, ka)
         reps = 2 ** (ka - a)
@@ -151,20 +169,94 @@ def expand(oracle, ct, keys, c: int, a0=None):
     return np.stack(cts)
 
 
+def _pt_times(oracle, pt, ct):
+    """pt * ct part by part, for two- and three-part ciphertexts."""
+    if len(ct) == 2:
+        return oracle.ptct_mul(pt, ct)
+    return np.concatenate([oracle.ptct_mul(pt, ct[:2]), oracle.ptct_mul(pt, np.stack([ct[2], ct[2]]))[:1]])
+
+
 def first_dimension(oracle, expanded, pts, d1: int):
-    """Columns [d2][2][L][n]: column k = sum_{r < d1} expanded[r] * pts[k][r]."""
+    """Columns [d2][parts][L][n]: column k = sum_{r < d1} expanded[r] * pts[k][r]."""
     out = []
     for col in pts:
         acc = np.zeros_like(expanded[0])
         for r in range(d1):
-            acc = _add(oracle, acc, oracle.ptct_mul(col[r], expanded[r]))
+            acc = _add(oracle, acc, _pt_times(oracle, col[r], expanded[r]))
         out.append(acc)
     return np.stack(out)
 
 
-def answer(oracle, ct, keys, pts, d1: int, a0=None):
-    """Server side of one query: expansion, then the first dimension."""
-    return first_dimension(oracle, expand(oracle, ct, keys, levels(d1), a0), pts, d1)
+def answer(oracle, ct, keys, pts, d1: int, a0=None, linear=False):
+    """Server side of one query: expansion, then the first dimension (with
+    linear=True: the linearised last level and one key switch per column)."""
+    c = levels(d1)
+    if linear:
+        e3 = expand_linear(oracle, ct, keys, c, d1, 0, a0)
+        return finish_columns(oracle, first_dimension(oracle, e3, pts, d1), keys[-1])
+    return first_dimension(oracle, expand(oracle, ct, keys, c, a0), pts, d1)
+
+
+# ---------------------------------------------------------------------------
+# linearised last level
+
+def substitute(oracle, x, g: int):
+    """x(X^g) for an NTT-form polynomial array [..., L, n]: each row through
+    its coefficients (no key switching)."""
+    x = np.asarray(x, dtype=np.uint64)
+    out = np.empty_like(x)
+    for idx in np.ndindex(x.shape[:-2]):
+        for l in range(oracle.L):
+            coef = oracle.intt(x[idx + (l,)], l)
+            out[idx + (l,)] = oracle.ntt(oracle.automorphism(coef, g, l), l)
+    return out
+
+
+def linear_pairs(c: int, d1: int, d2: int):
+    """Last-level pairs b < 2^(c-1) that are linearised: those whose outputs b
+    and b + 2^(c-1) are both outside the column entries d1 .. d1+d2-1 (d2 = 0
+    for a one-index query, where every pair is)."""
+    half = 1 << (c - 1)
+    col = range(d1, d1 + d2)
+    return [b for b in range(half) if b not in col and b + half not in col]
+
+
+def expand_linear(oracle, ct, keys, c: int, d1: int, d2: int = 0, a0=None):
+    """The 2^c expanded entries [2^c][3][L][n] with the linearised last level:
+    entry r decrypts, as u0 + u1 s + u2 s(X^g), g = g_(c-1), to [r == i] (and
+    to the column indicator at d1 + k for a two-index query).  Levels below
+    c - 1 are those of expand(); pairs of the last level that touch a column
+    entry are substituted as there, with u2 = 0."""
+    n = oracle.n
+    a0 = first_key_level(n, c) if a0 is None else a0
+    lower = expand(oracle, ct, keys, c, a0, upto=c - 1)
+    a = c - 1
+    key, g = keys[a - a0], galois(n, a)
+    w = monomial_inverse(oracle, 2**a)
+    half = len(lower)
+    lin = set(linear_pairs(c, d1, d2))
+    out = np.zeros((2 * half, 3, oracle.L, oracle.n), dtype=np.uint64)
+    for b, x in enumerate(lower):
+        if b in lin:
+            z = substitute(oracle, x, g)
+            out[b, 0] = _add(oracle, x[0][None], z[0][None])[0]
+            out[b, 1] = x[1]
+            out[b, 2] = z[1]
+            d = _sub(oracle, x[0][None], z[0][None])[0]
+            neg = _sub(oracle, np.zeros_like(z[1])[None], z[1][None])[0]
+            out[b + half] = _pt_times(oracle, w, np.stack([d, x[1], neg]))
+        else:
+            y = oracle.rotate(x, key, g)
+            out[b, :2] = _add(oracle, x, y)
+            out[b + half, :2] = oracle.ptct_mul(w, _sub(oracle, x, y))
+    return out
+
+
+def finish_columns(oracle, cols3, key):
+    """Three-part columns [d2][3][L][n] -> ciphertexts [d2][2][L][n]: each
+    (U0, U1, U2) becomes (U0, U1) + KeySwitch_{s(X^g) -> s}(U2) with the
+    Galois key of g (the identity automorphism on (U0, U2), then + U1)."""
+    return np.stack([relinearize(oracle, col, key) for col in cols3])
 
 
 # ---------------------------------------------------------------------------
@@ -262,11 +354,12 @@ def relinearize(oracle, ct3, rk):
     return out
 
 
-def decrypt3_poly(oracle, s, ct3):
+def decrypt3_poly(oracle, s, ct3, s2=None):
     """Coefficients of the decryption of a three-part ciphertext:
-    round(t [c0 + c1 s + c2 s^2]_Q / Q) mod t."""
+    round(t [c0 + c1 s + c2 s2]_Q / Q) mod t, s2 = s^2 unless given."""
     Q, t = oracle.p.Q, oracle.p.t
-    s2 = oracle.negacyclic_square(s)
+    if s2 is None:
+        s2 = oracle.negacyclic_square(s)
     zero = np.zeros_like(ct3[0])
     x = oracle._crt_lift(oracle.phase(s, np.stack([ct3[0], ct3[1]])))
     x2 = oracle._crt_lift(oracle.phase(s2, np.stack([zero, ct3[2]])))
@@ -278,10 +371,16 @@ def second_dimension(oracle, cols, e2, rk):
     return relinearize(oracle, tensor_scale(oracle, list(zip(cols, e2))), rk)
 
 
-def answer2(oracle, ct, keys, rk, pts, d1: int, d2: int, a0=None):
+def answer2(oracle, ct, keys, rk, pts, d1: int, d2: int, a0=None, linear=False):
     """Server side of one two-dimensional query: expansion to 2^c entries
     (c = levels2(d1, d2)), the first dimension on entries r < d1, the second on
-    entries d1 .. d1 + d2 - 1."""
-    e = expand(oracle, ct, keys, levels2(d1, d2), a0)
+    entries d1 .. d1 + d2 - 1 (with linear=True: the linearised last level,
+    and the columns key-switched before their products)."""
+    c = levels2(d1, d2)
+    if linear:
+        e3 = expand_linear(oracle, ct, keys, c, d1, d2, a0)
+        cols = finish_columns(oracle, first_dimension(oracle, e3[:d1], pts, d1), keys[-1])
+        return second_dimension(oracle, cols, e3[d1 : d1 + d2, :2], rk)
+    e = expand(oracle, ct, keys, c, a0)
     cols = first_dimension(oracle, e[:d1], pts, d1)
     return second_dimension(oracle, cols, e[d1 : d1 + d2], rk)
