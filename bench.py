@@ -455,8 +455,10 @@ def pir_legs(nq, steps):
         cts = synth.uniform_residues(gen, (pool, 2), qs, n, device="cuda")
         outs = torch.empty((nq, d2 * 2 * L * n), dtype=torch.int64, device="cuda")
         legs = {}
-        for name, a0 in (("paper_key_reduction", 0xFFFFFFFF), ("key_per_level", 0)):
+        for name, a0, lin in (("paper_key_reduction", 0xFFFFFFFF, False), ("paper_key_reduction_linear", 0xFFFFFFFF, True),
+                              ("key_per_level", 0, False), ("key_per_level_linear", 0, True)):
             ctx.pir_encode(db, a0)
+            ctx.pir_set_linear(lin)
             c, a0_, gals = ctx.pir_info()
             keys = synth.uniform_residues(gen, (pool, len(gals) * L, 2), qs + [info.P], n, device="cuda")
             pidx = np.arange(nq) % pool
@@ -472,16 +474,21 @@ def pir_legs(nq, steps):
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / steps
             subs = sum((1 << a) * (1 << (max(a, a0_) - a)) for a in range(c))
+            # the linearised last level: its 2^(c-1) substitutions become one key switch per column
+            ks = subs - (1 << (c - 1)) + d2 if lin else subs
             legs[name] = {"first_key_level": a0_, "keys_per_query": len(gals), "substitutions_per_query": subs,
+                          "linear_last_level": lin, "key_switches_per_query": ks,
                           "ms_per_batch": dt * 1e3, "queries_per_s": nq / dt,
                           "pt_ct_products_per_s": nq * d1 * d2 / dt}
-            log(f"pir {name}: a0={a0_}, {len(gals)} keys, {subs} substitutions per query, {dt * 1e3:.1f} ms for "
+            log(f"pir {name}: a0={a0_}, {len(gals)} keys, {ks} key switches per query, {dt * 1e3:.1f} ms for "
                 f"{nq} queries, {nq / dt:.0f} queries/s")
             del keys
-        # both dimensions (one answer ciphertext per query), the paper's key reduction
+        # both dimensions (one answer ciphertext per query), the paper's key
+        # reduction, without and with the linearised last level
         from paper_2406_06761_amd.wally import PIR_QUERY2_DTYPE
 
         ctx.pir_encode(db, 0xFFFFFFFF)
+        ctx.pir_set_linear(False)
         c2, a02, gals2, n_aux = ctx.pir_info2()
         keys = synth.uniform_residues(gen, (pool, len(gals2) * L, 2), qs + [info.P], n, device="cuda")
         rks = synth.uniform_residues(gen, (pool, L, 2), qs + [info.P], n, device="cuda")
@@ -492,20 +499,25 @@ def pir_legs(nq, steps):
         q2["keys"] = keys.data_ptr() + pidx * keys[0].numel() * 8
         q2["relin_key"] = rks.data_ptr() + pidx * rks[0].numel() * 8
         q2["out"] = outs2.data_ptr() + np.arange(nq) * outs2[0].numel() * 8
-        ctx.pir_answer2(q2)  # warm-up (workspace)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            ctx.pir_answer2(q2)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
         subs = sum((1 << a) * (1 << (max(a, a02) - a)) for a in range(c2))
-        legs["two_dimensions"] = {"first_key_level": a02, "keys_per_query": len(gals2) + 1,
-                                  "substitutions_per_query": subs, "ciphertext_products_per_query": d2,
-                                  "auxiliary_primes": n_aux, "ms_per_batch": dt * 1e3, "queries_per_s": nq / dt,
-                                  "answer_bytes_per_query": 2 * L * n * 8}
-        log(f"pir two dimensions: a0={a02}, {len(gals2)} Galois keys + relinearization key, {subs} substitutions "
-            f"and {d2} products per query, {dt * 1e3:.1f} ms for {nq} queries, {nq / dt:.0f} queries/s")
+        half = 1 << (c2 - 1)
+        n_lin = sum(1 for b in range(half) if not (d1 <= b < d1 + d2) and not (d1 <= b + half < d1 + d2))
+        for name, lin in (("two_dimensions", False), ("two_dimensions_linear", True)):
+            ctx.pir_set_linear(lin)
+            ctx.pir_answer2(q2)  # warm-up (workspace)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ctx.pir_answer2(q2)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            ks = subs - n_lin + d2 if lin else subs
+            legs[name] = {"first_key_level": a02, "keys_per_query": len(gals2) + 1,
+                          "substitutions_per_query": subs, "linear_last_level": lin, "key_switches_per_query": ks,
+                          "ciphertext_products_per_query": d2, "auxiliary_primes": n_aux, "ms_per_batch": dt * 1e3,
+                          "queries_per_s": nq / dt, "answer_bytes_per_query": 2 * L * n * 8}
+            log(f"pir {name}: a0={a02}, {len(gals2)} Galois keys + relinearization key, {ks} key switches "
+                f"and {d2} products per query, {dt * 1e3:.1f} ms for {nq} queries, {nq / dt:.0f} queries/s")
         del keys, rks, outs2
     finally:
         ctx.close()

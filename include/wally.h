@@ -290,6 +290,24 @@ int wally_pir_info2(const wally_ctx* ctx, uint32_t* levels, uint32_t* first_key_
  * pointers, d1 + d2 > 2048), ESTATE. */
 int wally_pir_answer2(wally_ctx* ctx, const wally_pir_query2* q, uint64_t nq, void* hip_stream);
 
+/* Linearised last expansion level (paper §4.2, "Linearizing parts of query
+ * expansion") for the answers of both kinds enqueued after this call; off
+ * (0) by default.  Key switching is linear, so the key switches of the last
+ * level move past the first dimension's sums: at level c - 1 each pair whose
+ * two outputs are row entries (or unused) takes the automorphism
+ * z = x(X^g), g = g_(c-1), without key switching and gives the three-part
+ * ciphertexts (x0 + z0, x1, z1) at b and ((x0 - z0) X^(-2^a), x1 X^(-2^a),
+ * -z1 X^(-2^a)) at b + 2^a, which decrypt as u0 + u1 s + u2 s(X^g); pairs
+ * that give a column entry of a two-index query are substituted as before.
+ * Every first-dimension column (U0, U1, U2) then becomes (U0, U1) +
+ * KeySwitch_{s(X^g) -> s}(U2) with the query's Galois key of g_(c-1): one key
+ * switch per column instead of one per linearised pair (2^(c-1) of them for
+ * a one-index query).  Queries, keys and the client's decryption are
+ * unchanged; the answer words differ from those of the plain expansion (the
+ * key-switch rounding happens at another point) and decrypt to the same
+ * entries.  EINVAL for a null or destroyed ctx. */
+int wally_pir_set_linear(wally_ctx* ctx, int on);
+
 /* Answer nq PIR queries (device pointers) on hip_stream: expansion and first
  * dimension, up to 64 queries at a time (fewer for deep expansions, so that a
  * wave's expansion buffers stay within 8 GiB).  Returns once enqueued; caller buffers must

@@ -239,6 +239,8 @@ struct wally_ctx {
   hipEvent_t pir_done = nullptr;  // after the last answer's work; the next call (any stream) and frees wait for it
   uint64_t pir_work_S = 0;        // expansion size the workspace was made for
   bool pir_work_two = false;      // ... and whether it has the second dimension's buffers
+  bool pir_work_lin = false;      // ... and the linearised level's buffers
+  bool pir_linear = false;        // linearised last expansion level (wally_pir_set_linear)
   // second dimension: depth and first key level of two-index queries (0
   // levels: not available), the auxiliary primes, constants of the extended
   // basis (device) and the auxiliary transform tables; buffers of one wave
@@ -246,6 +248,7 @@ struct wally_ctx {
   Pir2Consts* pir2_K = nullptr;
   ulonglong2* pir2_tables = nullptr;
   uint64_t *pir2_col = nullptr, *pir2_cf = nullptr, *pir2_ext = nullptr, *pir2_x3 = nullptr, *pir2_c3 = nullptr;
+  uint64_t *pir_e3 = nullptr, *pir_cols3 = nullptr;  // third parts of the last level; three-part columns
   // response compression constants
   CompressArgs comp{};
   // wally_score_batch_static: the device's static scratch, pinned host
@@ -1469,10 +1472,11 @@ struct PirQ {
   uint64_t* out;
 };
 
-// Expansion depth, first key level and whether the second dimension runs.
+// Expansion depth, first key level, whether the second dimension runs and
+// whether the last level is linearised.
 struct PirMode {
   uint32_t c, a0;
-  bool two;
+  bool two, lin;
 };
 
 void pir_free_work(wally_ctx* c) {
@@ -1484,7 +1488,7 @@ void pir_free_work(wally_ctx* c) {
     c->pir_lev[k] = c->pir_y[k] = nullptr;
   }
   for (uint64_t** p : {&c->pir_X, &c->pir_U, &c->pir_Y, &c->pir_D, &c->pir2_col, &c->pir2_cf, &c->pir2_ext,
-                       &c->pir2_x3, &c->pir2_c3}) {
+                       &c->pir2_x3, &c->pir2_c3, &c->pir_e3, &c->pir_cols3}) {
     dfree(c, *p);
     *p = nullptr;
   }
@@ -1502,25 +1506,32 @@ void pir_free_work(wally_ctx* c) {
   c->pir_out_host = nullptr;
   c->pir_work_S = 0;
   c->pir_work_two = false;
+  c->pir_work_lin = false;
 }
 
 // Device bytes per query of a wave: the two expansion lists and the two
-// substitution buffers (3 S ciphertexts), and for the second dimension the
+// substitution buffers (3 S ciphertexts), for the second dimension the
 // columns, one pass's coefficient and auxiliary rows, the tensor sums and the
-// scaled product.
-uint64_t pir_query_bytes(const wally_ctx* c, uint64_t S, bool two, uint32_t kc) {
+// scaled product, and for a linearised last level the third parts (S rows of
+// L n) and the three-part columns (4 L n words each).
+uint64_t pir_query_bytes(const wally_ctx* c, uint64_t S, bool two, bool lin, uint32_t kc) {
   const uint64_t ctw = c->ctw(), n = c->n, L = c->L, Lb = c->pir_Lb;
   uint64_t w = 3 * S * ctw;
   if (two) w += (uint64_t)c->pir_d2 * ctw + kc * 2 * ctw + kc * 4 * Lb * n + 3 * (L + Lb) * n + 4 * L * n;
+  if (lin) w += S * L * n + (uint64_t)c->pir_d2 * 4 * L * n;
   return 8 * w;
 }
 
-int pir_alloc_work(wally_ctx* c, uint64_t S, bool two) {
+int pir_alloc_work(wally_ctx* c, uint64_t S, bool two, bool lin) {
   const size_t w8 = 8, ctw = c->ctw(), n = c->n, L = c->L, Lb = c->pir_Lb;
   const uint32_t kc = two ? std::min(c->pir_d2, kPir2Cols) : 0;
-  c->pir_wq = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kPirWaveMax, kPirWaveBytes / pir_query_bytes(c, S, two, kc)));
+  c->pir_wq = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>(kPirWaveMax, kPirWaveBytes / pir_query_bytes(c, S, two, lin, kc)));
   const size_t W = c->pir_wq;
-  const size_t items = W * S;  // substitutions (S - 1 per query) and one relinearization
+  // per query: substitutions (S - 1), one relinearization, and with a
+  // linearised last level one key switch per column and up to S / 2
+  // automorphism items
+  const size_t items = W * (S + (lin ? S / 2 + c->pir_d2 : 0));
   int rc;
   for (int k = 0; k < 2; ++k) {
     if ((rc = dalloc(c, W * S * ctw * w8, (void**)&c->pir_lev[k]))) return rc;
@@ -1538,6 +1549,10 @@ int pir_alloc_work(wally_ctx* c, uint64_t S, bool two) {
     if ((rc = dalloc(c, W * 4 * L * n * w8, (void**)&c->pir2_c3))) return rc;
     c->pir2_kc = kc;
   }
+  if (lin) {
+    if ((rc = dalloc(c, W * S * L * n * w8, (void**)&c->pir_e3))) return rc;
+    if ((rc = dalloc(c, W * c->pir_d2 * 4 * L * n * w8, (void**)&c->pir_cols3))) return rc;
+  }
   if ((rc = dalloc(c, items * sizeof(KsItem), (void**)&c->pir_items_dev))) return rc;
   if ((rc = dalloc(c, W * sizeof(CopyItem), (void**)&c->pir_copy_dev))) return rc;
   if ((rc = dalloc(c, W * sizeof(uint64_t*), (void**)&c->pir_out_dev))) return rc;
@@ -1547,6 +1562,7 @@ int pir_alloc_work(wally_ctx* c, uint64_t S, bool two) {
   if (!c->pir_staged) HIP_OK(c, hipEventCreateWithFlags(&c->pir_staged, hipEventDisableTiming));
   c->pir_work_S = S;
   c->pir_work_two = two;
+  c->pir_work_lin = lin;
   return WALLY_OK;
 }
 
@@ -1555,29 +1571,44 @@ int pir_alloc_work(wally_ctx* c, uint64_t S, bool two) {
 // the answers in flight), and a failed allocation frees what was taken.
 int pir_ensure_work(wally_ctx* c, const PirMode& md) {
   const uint64_t S = 1ull << md.c;
-  if (c->pir_lev[0] && c->pir_work_S == S && (c->pir_work_two || !md.two)) return WALLY_OK;
+  if (c->pir_lev[0] && c->pir_work_S == S && (c->pir_work_two || !md.two) && (c->pir_work_lin || !md.lin))
+    return WALLY_OK;
   pir_free_work(c);
-  const int rc = pir_alloc_work(c, S, md.two);
+  const int rc = pir_alloc_work(c, S, md.two, md.lin);
   if (rc) pir_free_work(c);
   return rc;
 }
 
+// Whether pair b of the last level of a linearised expansion is linearised:
+// neither of its outputs b, b + S/2 is a column entry of a two-index query.
+bool pir_pair_linear(const wally_ctx* c, const PirMode& md, uint64_t b) {
+  if (!md.two) return true;
+  const uint64_t half = 1ull << (md.c - 1), lo = c->pir_d1, hi = (uint64_t)c->pir_d1 + c->pir_d2;
+  return !((b >= lo && b < hi) || (b + half >= lo && b + half < hi));
+}
+
 // Expansion of up to pir_wq queries on stream st, then the first dimension
 // (into the callers' outputs, or the column buffer for two-index queries),
-// then, for two-index queries, the second dimension into the outputs.
+// then, for two-index queries, the second dimension into the outputs.  With
+// a linearised last level the pairs it covers take the automorphism alone
+// (k_pir_lin_split), the first dimension sums three parts, and one key switch per
+// column (identity automorphism, the key of the last level) finishes them.
 int pir_wave(wally_ctx* c, const PirMode& md, const PirQ* q, uint32_t w, hipStream_t st) {
   const uint64_t ctw = c->ctw(), S = 1ull << md.c, keyw = c->keyw();
   HIP_OK(c, hipEventSynchronize(c->pir_staged));  // host descriptors of the last wave were copied
-  // descriptors: copies, substitution items of every level, relinearization items, outputs
+  // descriptors: copies, substitution items of every level, relinearization
+  // items, column items, automorphism items, outputs
   size_t base = 0;
-  std::vector<size_t> lev_base(md.c);
+  std::vector<size_t> lev_base(md.c), lev_count(md.c);
   for (uint32_t a = 0; a < md.c; ++a) {
     lev_base[a] = base;
     const uint64_t half = 1ull << a;
     const uint32_t ka = std::max(a, md.a0);
+    const bool last_lin = md.lin && a + 1 == md.c;
     uint64_t* cur = c->pir_lev[a & 1];
     for (uint32_t i = 0; i < w; ++i)
       for (uint64_t b = 0; b < half; ++b) {
+        if (last_lin && pir_pair_linear(c, md, b)) continue;
         KsItem it{};
         it.key = q[i].keys + (uint64_t)(ka - md.a0) * keyw;
         it.buf0 = cur + (i * S + b) * ctw;
@@ -1585,22 +1616,53 @@ int pir_wave(wally_ctx* c, const PirMode& md, const PirQ* q, uint32_t w, hipStre
         it.fin = c->pir_y[1] + (i * (S / 2) + b) * ctw;
         c->pir_items_host[base++] = it;
       }
+    lev_count[a] = base - lev_base[a];
   }
   const size_t relin_base = base;
-  const uint64_t c3w = 4ull * c->L * c->n;  // words of one scaled product (c0, c2, 0, c1)
+  const uint64_t p3w = 4ull * c->L * c->n;  // words of one scaled product (c0, c2, 0, c1)
   if (md.two)
     for (uint32_t i = 0; i < w; ++i) {
       // key switch of (c0, c2) with the identity automorphism, + (0, c1): (c0, c1) + KS(c2)
       KsItem it{};
       it.key = q[i].rk;
-      it.buf0 = c->pir2_c3 + i * c3w;
-      it.acc = c->pir2_c3 + i * c3w + c3w / 2;
+      it.buf0 = c->pir2_c3 + i * p3w;
+      it.acc = c->pir2_c3 + i * p3w + p3w / 2;
       it.fin = q[i].out;
       c->pir_items_host[base++] = it;
     }
+  // linearised last level: the column key switches, then the automorphism items
+  const uint64_t c3w = 4ull * c->L * c->n;  // words of one three-part column [U0][U2][0][U1]
+  const size_t col_base = base;
+  if (md.lin)
+    for (uint32_t i = 0; i < w; ++i)
+      for (uint32_t k = 0; k < c->pir_d2; ++k) {
+        KsItem it{};
+        it.key = q[i].keys + (uint64_t)(md.c - 1 - md.a0) * keyw;
+        it.buf0 = c->pir_cols3 + ((uint64_t)i * c->pir_d2 + k) * c3w;
+        it.acc = it.buf0 + c3w / 2;
+        it.fin = (md.two ? c->pir2_col + (uint64_t)i * c->pir_d2 * ctw : q[i].out) + (uint64_t)k * ctw;
+        c->pir_items_host[base++] = it;
+      }
+  const size_t sig_base = base;
+  if (md.lin) {
+    uint64_t* cur = c->pir_lev[(md.c - 1) & 1];
+    uint64_t* nxt = c->pir_lev[md.c & 1];
+    const uint64_t half = S / 2;
+    for (uint32_t i = 0; i < w; ++i)
+      for (uint64_t b = 0; b < half; ++b)
+        if (pir_pair_linear(c, md, b)) {
+          KsItem it{};
+          it.buf0 = cur + (i * S + b) * ctw;
+          it.buf1 = nxt + (i * S + b) * ctw;
+          it.fin = c->pir_e3 + (i * S + b) * c->L * c->n;
+          c->pir_items_host[base++] = it;
+        }
+  }
   for (uint32_t i = 0; i < w; ++i) {
     c->pir_copy_host[i] = CopyItem{q[i].ct, c->pir_lev[0] + i * S * ctw};
-    c->pir_out_host[i] = md.two ? c->pir2_col + (uint64_t)i * c->pir_d2 * ctw : q[i].out;
+    c->pir_out_host[i] = md.lin   ? c->pir_cols3 + (uint64_t)i * c->pir_d2 * c3w
+                         : md.two ? c->pir2_col + (uint64_t)i * c->pir_d2 * ctw
+                                  : q[i].out;
   }
   HIP_OK(c, hipMemcpyAsync(c->pir_items_dev, c->pir_items_host, base * sizeof(KsItem), hipMemcpyHostToDevice, st));
   HIP_OK(c, hipMemcpyAsync(c->pir_copy_dev, c->pir_copy_host, w * sizeof(CopyItem), hipMemcpyHostToDevice, st));
@@ -1628,12 +1690,14 @@ int pir_wave(wally_ctx* c, const PirMode& md, const PirQ* q, uint32_t w, hipStre
     const uint32_t ka = std::max(a, md.a0);
     const uint32_t reps = 1u << (ka - a);  // Subs(., g_ka) applied 2^(ka - a) times is Subs(., g_a)
     const int n_items = (int)(w * half);
+    const int n_ks = (int)lev_count[a];
+    const bool last_lin = md.lin && a + 1 == md.c;  // then ka = a and reps = 1 (a0 <= c - 1)
     int last_out = 1;
     for (uint32_t r = 0; r < reps; ++r) {
       // x, then alternately y0, y1
       const KsArgs ka_args = ks_args(c->n / (1u << ka) + 1, r == 0 ? 0 : (r % 2 == 1 ? 1 : 2), r % 2 == 0 ? 1 : 2);
-      for (int i0 = 0; i0 < n_items; i0 += kPirKsItems)
-        HIP_OK(c, keyswitch(c, c->pir_items_dev + lev_base[a] + i0, std::min(kPirKsItems, n_items - i0), ka_args, st));
+      for (int i0 = 0; i0 < n_ks; i0 += kPirKsItems)
+        HIP_OK(c, keyswitch(c, c->pir_items_dev + lev_base[a] + i0, std::min(kPirKsItems, n_ks - i0), ka_args, st));
       last_out = ka_args.out_sel;
     }
     PirSplitArgs sa{};
@@ -1646,7 +1710,14 @@ int pir_wave(wally_ctx* c, const PirMode& md, const PirQ* q, uint32_t w, hipStre
     sa.half = (uint32_t)half;
     sa.log_n = c->log_n;
     sa.L = c->L;
-    HIP_OK(c, launch_pir_split(sa, n_items, c->M, st));
+    if (last_lin) {
+      sa.e3 = c->pir_e3;
+      sa.col_lo = md.two ? c->pir_d1 : 0;
+      sa.col_hi = md.two ? c->pir_d1 + c->pir_d2 : 0;
+      HIP_OK(c, launch_pir_lin_split(c->pir_items_dev + sig_base, (int)(base - sig_base), sa, c->n / (1u << a) + 1,
+                                     c->M, st));
+    }
+    if (!last_lin || n_ks > 0) HIP_OK(c, launch_pir_split(sa, n_items, c->M, st));
   }
   const uint64_t* E = c->pir_lev[md.c & 1];
   PirDotArgs da{};
@@ -1659,7 +1730,15 @@ int pir_wave(wally_ctx* c, const PirMode& md, const PirQ* q, uint32_t w, hipStre
   da.nq = w;
   da.log_n = c->log_n;
   da.L = c->L;
+  da.E3 = md.lin ? c->pir_e3 : nullptr;
   HIP_OK(c, timed(c, st, WALLY_KERNEL_MAC, w, [&] { return launch_pir_dot(da, c->M, st); }));
+  if (md.lin) {  // (U0, U1) + KeySwitch(U2): identity automorphism on (U0, U2), + (0, U1)
+    KsArgs fa = ks_args(1, 0, 2);
+    fa.giant = 0;
+    const int n_cols = (int)(sig_base - col_base);
+    for (int i0 = 0; i0 < n_cols; i0 += kPirKsItems)
+      HIP_OK(c, keyswitch(c, c->pir_items_dev + col_base + i0, std::min(kPirKsItems, n_cols - i0), fa, st));
+  }
   if (!md.two) return WALLY_OK;
   // second dimension, columns in passes of pir2_kc
   Pir2Args pa{};
@@ -1965,7 +2044,7 @@ int wally_pir_answer(wally_ctx* c, const wally_pir_query* q, uint64_t nq, void* 
     qs[i] = PirQ{q[i].ct, q[i].keys, nullptr, q[i].out};
   }
   if (nq == 0) return WALLY_OK;
-  return pir_answer_any(c, PirMode{c->pir_c, c->pir_a0, false}, qs, (hipStream_t)hip_stream);
+  return pir_answer_any(c, PirMode{c->pir_c, c->pir_a0, false, c->pir_linear}, qs, (hipStream_t)hip_stream);
 }
 
 int wally_pir_answer2(wally_ctx* c, const wally_pir_query2* q, uint64_t nq, void* hip_stream) {
@@ -1986,7 +2065,15 @@ int wally_pir_answer2(wally_ctx* c, const wally_pir_query2* q, uint64_t nq, void
     qs[i] = PirQ{q[i].ct, q[i].keys, q[i].relin_key, q[i].out};
   }
   if (nq == 0) return WALLY_OK;
-  return pir_answer_any(c, PirMode{c->pir_c2, c->pir_a02, true}, qs, (hipStream_t)hip_stream);
+  return pir_answer_any(c, PirMode{c->pir_c2, c->pir_a02, true, c->pir_linear}, qs, (hipStream_t)hip_stream);
+}
+
+int wally_pir_set_linear(wally_ctx* c, int on) {
+  int rc = check_live(c);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->pir_linear = on != 0;
+  return WALLY_OK;
 }
 
 }  // extern "C"

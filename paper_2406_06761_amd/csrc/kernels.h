@@ -94,14 +94,27 @@ struct PirSplitArgs {
   uint32_t ystride; // ciphertexts per query in ybuf (2^(c-1))
   uint32_t half;    // 2^a
   int log_n, L;
+  // Linearised last level (paper §4.2, "Linearizing parts of query
+  // expansion"): when e3 is set, the pairs b whose outputs b and b + half both
+  // lie outside [col_lo, col_hi) are k_pir_lin_split's (no key switch; their
+  // outputs get a third part u2, decrypted against s(X^g), in e3
+  // [queries][stride][L][n]); the split kernel skips them and gives the
+  // other pairs u2 = 0.
+  uint64_t* e3;
+  uint32_t col_lo, col_hi;
 };
 // First dimension: out[q][k] = sum_{r < d1} E[q][r] * PT[k][r], k < d2.
+// With E3 (the third parts of a linearised expansion) the sums have three
+// parts, written per column as [U0][U2][0][U1] (4 L n words): (U0, U2) is
+// the input of the key switch that finishes the column and (0, U1) what it
+// adds.
 struct PirDotArgs {
   const uint64_t* E;     // expanded ciphertexts [queries][stride][2][L][n]
   const uint64_t* pt;    // plaintexts [d2][d1][L][n]
-  uint64_t* const* out;  // per query: [d2][2][L][n]
+  uint64_t* const* out;  // per query: [d2][2][L][n], or [d2][4][L][n] with E3
   uint32_t stride, d1, d2, nq;
   int log_n, L;
+  const uint64_t* E3;    // null, or [queries][stride][L][n]
 };
 // Index PIR, second dimension (paper §4.2 "Overview of MulPIR", step 3; the
 // products computed in a larger basis and scaled once, §7.1 "Reducing the
@@ -168,6 +181,9 @@ hipError_t launch_rows_ntt(uint64_t* data, int rows, int log_n, const Pir2Consts
 hipError_t launch_pir_encode(const uint32_t* coeffs, uint64_t* out, int n_pt, int log_n, int L, const DevModuli& M,
                              hipStream_t st);
 hipError_t launch_pir_split(const PirSplitArgs& a, int items, const DevModuli& M, hipStream_t st);
+// the linearised pairs of a last expansion level: items[b] = {buf0: x, buf1: output b, fin: its third part}
+hipError_t launch_pir_lin_split(const KsItem* items, int n_items, const PirSplitArgs& a, uint32_t gal,
+                                const DevModuli& M, hipStream_t st);
 hipError_t launch_pir_dot(const PirDotArgs& a, const DevModuli& M, hipStream_t st);
 
 hipError_t launch_ks_digits(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);

@@ -482,6 +482,14 @@ __global__ __launch_bounds__(256) void k_pir_split(PirSplitArgs a, DevModuli M) 
   const uint64_t off = (uint64_t)tl * n + x;
   const uint64_t q = M.q[l];
   const uint64_t base = (uint64_t)qi * a.stride + b;
+  if (a.e3 != nullptr) {  // linearised last level: its linearised pairs are k_pir_lin_split's
+    if (!((b >= a.col_lo && b < a.col_hi) || (b + a.half >= a.col_lo && b + a.half < a.col_hi))) return;
+    if (tl >= a.L) {  // the other pairs get no third part
+      WALLY_GLOBAL uint64_t* e3 = gmem(a.e3) + (base * a.L + l) * n + x;
+      e3[0] = 0;
+      e3[(uint64_t)a.half * a.L * n] = 0;
+    }
+  }
   const uint64_t xv = gmem(a.cur)[base * ctw + off];
   const uint64_t yv = gmem(a.ybuf)[((uint64_t)qi * a.ystride + b) * ctw + off];
   const u64x2 w = *((WALLY_GLOBAL const u64x2*)a.w + (uint64_t)l * n + x);  // (value, Shoup factor)
@@ -489,11 +497,57 @@ __global__ __launch_bounds__(256) void k_pir_split(PirSplitArgs a, DevModuli M) 
   gmem(a.next)[(base + a.half) * ctw + off] = csub(shoup(xv + q - yv, w.x, w.y, q), q);
 }
 
+// The linearised pairs of the last expansion level (PirSplitArgs): the
+// automorphism z = x(X^g) without key switching, which in NTT form permutes
+// the entries of every row the same way, and the pair's outputs
+//   b: (x0 + z0, x1 | z1),  b + half: ((x0 - z0) w, x1 w | -z1 w).
+// A row of x is read with coalesced loads into LDS; z's words come from
+// their source entries there.  Item fields: buf0 = x, buf1 = output b in
+// the next list, fin = its third part (output b + half is half ciphertexts,
+// half third parts further on).  grid (2 L, items); block 256
+template <int LOGN>
+__global__ __launch_bounds__(256) void k_pir_lin_split(const KsItem* __restrict__ items, PirSplitArgs a, uint32_t gal,
+                                                       DevModuli M) {
+  constexpr int N = 1 << LOGN;
+  __shared__ uint64_t lds[N];
+  const int tl = blockIdx.x, l = tl % a.L;
+  const uint64_t q = M.q[l];
+  const KsItem it = items[blockIdx.y];
+  WALLY_GLOBAL const uint64_t* src = gmem(it.buf0) + (uint64_t)tl * N;
+  for (int k = threadIdx.x; k < N; k += 256) lds[k] = src[k];
+  __syncthreads();
+  const uint64_t ctw = 2ull * a.L * N;
+  WALLY_GLOBAL uint64_t* nb = gmem(it.buf1) + (uint64_t)tl * N;
+  WALLY_GLOBAL uint64_t* nh = nb + (uint64_t)a.half * ctw;
+  WALLY_GLOBAL const u64x2* w = (WALLY_GLOBAL const u64x2*)a.w + (uint64_t)l * N;  // (value, Shoup factor)
+  if (tl < a.L) {
+    for (int k = threadIdx.x; k < N; k += 256) {
+      const uint64_t xv = lds[k], zv = lds[galois_src<LOGN>((uint32_t)k, gal)];
+      const u64x2 wk = w[k];
+      nb[k] = addmod(xv, zv, q);
+      nh[k] = csub(shoup(xv + q - zv, wk.x, wk.y, q), q);
+    }
+  } else {
+    WALLY_GLOBAL uint64_t* eb = gmem(it.fin) + (uint64_t)l * N;
+    WALLY_GLOBAL uint64_t* eh = eb + (uint64_t)a.half * a.L * N;
+    for (int k = threadIdx.x; k < N; k += 256) {
+      const uint64_t xv = lds[k], zv = lds[galois_src<LOGN>((uint32_t)k, gal)];
+      const u64x2 wk = w[k];
+      nb[k] = xv;
+      eb[k] = zv;
+      nh[k] = csub(shoup(xv, wk.x, wk.y, q), q);
+      eh[k] = csub(shoup(q - zv, wk.x, wk.y, q), q);
+    }
+  }
+}
+
 // first dimension: grid (n / 512, L, column pairs x query pairs); block 256.
 // A thread takes two adjacent coefficients (16-byte loads) of two columns and
-// two queries, both ciphertext parts: per row r it loads 2 plaintext pairs and
-// 4 ciphertext pairs and does 16 products into 128-bit lazy sums (d1 <= 2048
-// products of words below 2^54 stay below 2^119), reduced once at the end.
+// two queries, all TP ciphertext parts: per row r it loads 2 plaintext pairs
+// and 2 TP ciphertext pairs and does 8 TP products into 128-bit lazy sums
+// (d1 <= 2048 products of words below 2^54 stay below 2^119), reduced once at
+// the end.  TP = 3 for a linearised expansion (the third parts from E3).
+template <int TP>
 __global__ __launch_bounds__(256) void k_pir_dot(PirDotArgs a, DevModuli M) {
   const uint64_t n = 1ull << a.log_n;
   const uint64_t x = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 2;
@@ -507,37 +561,51 @@ __global__ __launch_bounds__(256) void k_pir_dot(PirDotArgs a, DevModuli M) {
   WALLY_GLOBAL const uint64_t* pt1 = pt0 + (k1v ? (uint64_t)a.d1 * ptw : 0);
   WALLY_GLOBAL const uint64_t* e0 = gmem(a.E) + (uint64_t)q0 * a.stride * ctw + (uint64_t)l * n + x;
   WALLY_GLOBAL const uint64_t* e1 = e0 + (q1v ? (uint64_t)a.stride * ctw : 0);
-  u128w acc[2][2][2][2] = {};  // [column][query][part][coefficient]
+  WALLY_GLOBAL const uint64_t* f0 = nullptr;
+  WALLY_GLOBAL const uint64_t* f1 = nullptr;
+  if constexpr (TP == 3) {
+    f0 = gmem(a.E3) + (uint64_t)q0 * a.stride * ptw + (uint64_t)l * n + x;
+    f1 = f0 + (q1v ? (uint64_t)a.stride * ptw : 0);
+  }
+  u128w acc[2][2][TP][2] = {};  // [column][query][part][coefficient]
   for (uint32_t r = 0; r < a.d1; ++r) {
     const u64x2 w[2] = {*(WALLY_GLOBAL const u64x2*)(pt0 + (uint64_t)r * ptw),
                         *(WALLY_GLOBAL const u64x2*)(pt1 + (uint64_t)r * ptw)};
-    u64x2 v[2][2];
+    u64x2 v[2][TP];
 #pragma unroll
     for (int tp = 0; tp < 2; ++tp) {
       v[0][tp] = *(WALLY_GLOBAL const u64x2*)(e0 + (uint64_t)r * ctw + (uint64_t)tp * ptw);
       v[1][tp] = *(WALLY_GLOBAL const u64x2*)(e1 + (uint64_t)r * ctw + (uint64_t)tp * ptw);
+    }
+    if constexpr (TP == 3) {
+      v[0][2] = *(WALLY_GLOBAL const u64x2*)(f0 + (uint64_t)r * ptw);
+      v[1][2] = *(WALLY_GLOBAL const u64x2*)(f1 + (uint64_t)r * ptw);
     }
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
       for (int qq = 0; qq < 2; ++qq)
 #pragma unroll
-        for (int tp = 0; tp < 2; ++tp) {
+        for (int tp = 0; tp < TP; ++tp) {
           mac128(acc[kk][qq][tp][0], w[kk].x, v[qq][tp].x);
           mac128(acc[kk][qq][tp][1], w[kk].y, v[qq][tp].y);
         }
   }
+  // column layout: [U0][U1] (TP = 2), [U0][U2][0][U1] (TP = 3)
+  constexpr int kSlot[3] = {0, TP == 3 ? 3 : 1, 1};
+  const uint64_t colw = TP == 3 ? 4 * ptw : ctw;
 #pragma unroll
   for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
     for (int qq = 0; qq < 2; ++qq) {
       if ((kk && !k1v) || (qq && !q1v)) continue;
-      WALLY_GLOBAL uint64_t* o = gmem(a.out[q0 + qq]) + (uint64_t)(k0 + kk) * ctw + (uint64_t)l * n + x;
+      WALLY_GLOBAL uint64_t* o = gmem(a.out[q0 + qq]) + (uint64_t)(k0 + kk) * colw + (uint64_t)l * n + x;
 #pragma unroll
-      for (int tp = 0; tp < 2; ++tp)
-        *(WALLY_GLOBAL u64x2*)(o + (uint64_t)tp * ptw) =
+      for (int tp = 0; tp < TP; ++tp)
+        *(WALLY_GLOBAL u64x2*)(o + (uint64_t)kSlot[tp] * ptw) =
             u64x2{reduce128(acc[kk][qq][tp][0], mc.q, mc.r64, mc.r64p, mc.onep),
                   reduce128(acc[kk][qq][tp][1], mc.q, mc.r64, mc.r64p, mc.onep)};
+      if constexpr (TP == 3) *(WALLY_GLOBAL u64x2*)(o + 2 * ptw) = u64x2{0, 0};
     }
 }
 
@@ -1084,7 +1152,20 @@ hipError_t launch_pir_split(const PirSplitArgs& a, int items, const DevModuli& M
 hipError_t launch_pir_dot(const PirDotArgs& a, const DevModuli& M, hipStream_t st) {
   if (a.nq == 0 || a.d2 == 0) return hipSuccess;
   const uint32_t pairs = ((a.d2 + 1) / 2) * ((a.nq + 1) / 2);
-  hipLaunchKernelGGL(k_pir_dot, dim3((1u << a.log_n) / 512, a.L, pairs), dim3(256), 0, st, a, M);
+  const dim3 grid((1u << a.log_n) / 512, a.L, pairs);
+  if (a.E3) hipLaunchKernelGGL(k_pir_dot<3>, grid, dim3(256), 0, st, a, M);
+  else hipLaunchKernelGGL(k_pir_dot<2>, grid, dim3(256), 0, st, a, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_pir_lin_split(const KsItem* items, int n_items, const PirSplitArgs& a, uint32_t gal,
+                                const DevModuli& M, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  switch (a.log_n) {
+    case 12: hipLaunchKernelGGL(k_pir_lin_split<12>, dim3(2 * a.L, n_items), dim3(256), 0, st, items, a, gal, M); break;
+    case 13: hipLaunchKernelGGL(k_pir_lin_split<13>, dim3(2 * a.L, n_items), dim3(256), 0, st, items, a, gal, M); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

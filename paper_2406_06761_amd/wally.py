@@ -67,6 +67,7 @@ SYMBOLS = [
     "wally_score_batch", "wally_score_batch_static",
     "wally_tune", "wally_compress_responses", "wally_encode_clusters_i16",
     "wally_pir_encode", "wally_pir_info", "wally_pir_answer", "wally_pir_info2", "wally_pir_answer2",
+    "wally_pir_set_linear",
     "wally_serve_start", "wally_serve_submit", "wally_serve_poll", "wally_serve_stop", "wally_strerror",
     "wally_last_error", "wally_destroy", "wally_diag_ntt", "wally_diag_rotate", "wally_diag_kernel_timing",
     "wally_diag_kernel_stats", "wally_diag_bfly_rate",
@@ -115,6 +116,7 @@ def load():
         "wally_pir_info2": ([vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u32)],
                             i32),
         "wally_pir_answer2": ([vp, vp, u64, vp], i32),
+        "wally_pir_set_linear": ([vp, ctypes.c_int], i32),
         "wally_compress_responses": ([vp, vp, u64, vp, vp], i32),
         "wally_tune": ([vp, vp, u64, vp, vp, vp, vp, ctypes.POINTER(TuneEntry), u32, ctypes.POINTER(u32)], i32),
         "wally_serve_start": ([vp, vp], i32),
@@ -252,6 +254,10 @@ class Context:
         queries = np.ascontiguousarray(queries, dtype=PIR_QUERY2_DTYPE)
         self._check(self.lib.wally_pir_answer2(self.h, queries.ctypes.data, len(queries), _stream_handle(stream)),
                     "wally_pir_answer2")
+
+    def pir_set_linear(self, on: bool):
+        """Linearised last expansion level for later answers (wally_pir_set_linear)."""
+        self._check(self.lib.wally_pir_set_linear(self.h, 1 if on else 0), "wally_pir_set_linear")
 
     def compress_responses(self, responses, out, stream=None):
         """responses: device tensor of [chunks][2][L][n] words; out: device

@@ -9,7 +9,9 @@ products summed and scaled once, relinearization; §7.1) against the oracle
   the second dimension (16);
 * both ring sizes; every answer equals the oracle's words and decrypts to the
   queried entry's plaintext;
-* bad inputs refused before anything is enqueued.
+* bad inputs refused before anything is enqueued;
+* the linearised last level (paper §4.2, "Linearizing parts of query
+  expansion"): the same cases against the oracle's linearised answer.
 """
 from concurrent.futures import ThreadPoolExecutor
 
@@ -24,7 +26,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _run(name, d1, d2, nq, a0=None, seed=0, check_dec=3):
+def _run(name, d1, d2, nq, a0=None, seed=0, check_dec=3, linear=False):
     from paper_2406_06761_amd.wally import PIR_PAPER_KEYS, PIR_QUERY2_DTYPE, Context, to_device, to_host
 
     p = preset(name)
@@ -35,8 +37,9 @@ def _run(name, d1, d2, nq, a0=None, seed=0, check_dec=3):
     c_lv = pir.levels2(d1, d2)
     ctx = Context.preset(name)
     try:
-        print(f"pir2 {name} d1={d1} d2={d2} nq={nq} a0={a0}", flush=True)
+        print(f"pir2 {name} d1={d1} d2={d2} nq={nq} a0={a0} linear={linear}", flush=True)
         ctx.pir_encode(db, PIR_PAPER_KEYS if a0 is None else a0)
+        ctx.pir_set_linear(linear)
         levels, a0_got, gals, n_aux = ctx.pir_info2()
         a0_want = pir.first_key_level(p.n, c_lv) if a0 is None else a0
         assert (levels, a0_got) == (c_lv, a0_want)
@@ -51,7 +54,7 @@ def _run(name, d1, d2, nq, a0=None, seed=0, check_dec=3):
                             pir.make_keys(o, s, c_lv, rng, a0_want), o.relin_key(s, rng), s))
         pts = np.stack([np.stack([pir.plaintext(o, db[k][r]) for r in range(d1)]) for k in range(d2)])
         with ThreadPoolExecutor(8) as ex:
-            ref = list(ex.map(lambda pk: pir.answer2(o, pk[0], pk[1], pk[2], pts, d1, d2, a0_want), packets))
+            ref = list(ex.map(lambda pk: pir.answer2(o, pk[0], pk[1], pk[2], pts, d1, d2, a0_want, linear), packets))
         cts = [to_device(pk[0]) for pk in packets]
         keys = [to_device(pk[1]) for pk in packets]
         rks = [to_device(pk[2]) for pk in packets]
@@ -83,6 +86,16 @@ def test_pir2_small_ring(d1, d2, nq, a0):
 
 def test_pir2_paper_parameters():
     _run("paper", 5, 3, 2, None, seed=11).close()
+
+
+@pytest.mark.parametrize("d1,d2,nq,a0", [(5, 3, 3, None), (6, 3, 70, None), (3, 2, 2, 0), (1, 2, 2, None),
+                                         (4, 20, 2, None), (11, 2, 2, 0)])
+def test_pir2_linear_small_ring(d1, d2, nq, a0):
+    _run("tiny", d1, d2, nq, a0, seed=d1 * 100 + d2 + 7, linear=True).close()
+
+
+def test_pir2_linear_paper_parameters():
+    _run("paper", 5, 3, 2, None, seed=12, linear=True).close()
 
 
 def test_pir2_then_one_dimension_on_the_same_database():
