@@ -128,15 +128,15 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_digits(const K
                                                                          DevModuli M) {
   using S = NttShape<LOGN, LOGE>;
   using FM = FirstMap<LOGN, LOGE>;
-  __shared__ uint64_t lds[S::LDS_WORDS];
+  __shared__ uint64_t lds[(S::LDS_WORDS + 1) / 2];  // 32-bit exchanges
   const int tid = threadIdx.x;
   const int b = blockIdx.x, i = blockIdx.y;
   const auto c1 = sel_in(items + b, a.in_sel, a.in_off) + ((uint64_t)a.L + i) * S::N;
   const uint64_t q = M.q[i];
   uint64_t x[S::E];
-  gather_galois<LOGN, LOGE, LastMap<LOGN, LOGE>>(x, c1, lds, a.gal, tid);  // sigma(c1)_i, INTT input order
+  gather_galois_split<LOGN, LOGE, LastMap<LOGN, LOGE>>(x, c1, lds, a.gal, tid);  // sigma(c1)_i, INTT input order
   store_last<LOGN, LOGE, true>(a.D + (((uint64_t)b * (a.L + 1) + i) * a.L + i) * S::N, x, tid);  // D[i][i]
-  ntt_inv<LOGN, LOGE>(x, lds, M.inv[i], q, tid);
+  ntt_inv<LOGN, LOGE, true>(x, lds, M.inv[i], q, tid);
   uint64_t* X = a.X + ((uint64_t)b * a.L + i) * S::N;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) X[FM::idx(tid, e)] = csub(shoup(x[e], M.ninv[i], M.ninvp[i], q), q);
@@ -152,7 +152,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const K
                                                                          int n_items, DevModuli M) {
   using S = NttShape<LOGN, LOGE>;
   using FM = FirstMap<LOGN, LOGE>;
-  __shared__ uint64_t lds[S::LDS_WORDS];
+  __shared__ uint64_t lds[(S::LDS_WORDS + 1) / 2];  // 32-bit exchanges
   const int tid = threadIdx.x;
   const int L = a.L;
   const GroupSlot gs = xcd_group(blockIdx.x, L);
@@ -165,7 +165,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const K
   const uint64_t* X = a.X + ((uint64_t)b * L + i) * S::N;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) d[e] = X[FM::idx(tid, e)];  // < q_i < 2 q_m: a valid lazy input
-  ntt_fwd<LOGN, LOGE>(d, lds, M.fwd[m], q, tid);  // out < 54 q, LastMap order
+  ntt_fwd<LOGN, LOGE, true>(d, lds, M.fwd[m], q, tid);  // out < 54 q, LastMap order
   // stored unreduced: the inner product's 128-bit sums take words below 54 q
   // (up to eight products of them with key words stay below 2^117) and
   // reduce once
@@ -218,7 +218,7 @@ template <int LOGN, int LOGE>
 __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_pinv(KsArgs a, DevModuli M) {
   using S = NttShape<LOGN, LOGE>;
   using FM = FirstMap<LOGN, LOGE>;
-  __shared__ uint64_t lds[S::LDS_WORDS];
+  __shared__ uint64_t lds[(S::LDS_WORDS + 1) / 2];  // 32-bit exchanges
   const int tid = threadIdx.x;
   const int b = blockIdx.x, t = blockIdx.y;
   const int L = a.L, MM = a.L + 1;
@@ -226,7 +226,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_pinv(KsArgs a,
   const uint64_t* U = a.U + (((uint64_t)b * 2 + t) * MM + L) * S::N;
   uint64_t y[S::E];
   load_last<LOGN, LOGE, true>(y, U, tid);
-  ntt_inv<LOGN, LOGE>(y, lds, M.inv[L], P, tid);  // out FirstMap order
+  ntt_inv<LOGN, LOGE, true>(y, lds, M.inv[L], P, tid);  // out FirstMap order
   uint64_t* Y = a.Y + ((uint64_t)b * 2 + t) * S::N;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) Y[FM::idx(tid, e)] = csub(shoup(y[e], M.ninv[L], M.ninvp[L], P), P);
@@ -239,11 +239,11 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_pinv(KsArgs a,
 // 1-D grid of xcd_blocks(items * 2, L): group (b, t) reads Y_t of item b, its L
 // members are the target limbs j; block T
 template <int LOGN, int LOGE>
-__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_waves_per_eu(4))) void k_ks_moddown(
+__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_waves_per_eu(6))) void k_ks_moddown(
     const KsItem* __restrict__ items, KsArgs a, int n_items, DevModuli M) {
   using S = NttShape<LOGN, LOGE>;
   using FM = FirstMap<LOGN, LOGE>;
-  __shared__ uint64_t lds[S::LDS_WORDS];
+  __shared__ uint64_t lds[(S::LDS_WORDS + 1) / 2];  // 32-bit exchanges
   const int tid = threadIdx.x;
   const int L = a.L, MM = a.L + 1;
   const GroupSlot gs = xcd_group(blockIdx.x, L);
@@ -259,7 +259,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_wa
     const uint64_t y = Y[FM::idx(tid, e)];
     z[e] = y > halfP ? y + (q - P) : y;  // centred lift, then mod q_j (P < q_j)
   }
-  ntt_fwd<LOGN, LOGE>(z, lds, M.fwd[j], q, tid);  // LastMap order from here on, z < (2 + 4 LOGN) q
+  ntt_fwd<LOGN, LOGE, true>(z, lds, M.fwd[j], q, tid);  // LastMap order from here on, z < (2 + 4 LOGN) q
   using LM = LastMap<LOGN, LOGE>;
   // u - z is taken as u + zb - z with zb the transform's output bound: below
   // 2^60, which the Shoup product by P^-1 accepts unreduced
@@ -271,7 +271,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_wa
     z[2 * c] = csub(shoup(u.x + zb - z[2 * c], M.pinv[j], M.pinvp[j], q), q);
     z[2 * c + 1] = csub(shoup(u.y + zb - z[2 * c + 1], M.pinv[j], M.pinvp[j], q), q);
   }
-  if (t == 0) add_galois<LOGN, LOGE, LM>(z, sel_in(items + b, a.in_sel, a.in_off) + (uint64_t)j * S::N, lds, a.gal, q, tid);
+  if (t == 0) add_galois_split<LOGN, LOGE, LM>(z, sel_in(items + b, a.in_sel, a.in_off) + (uint64_t)j * S::N, lds, a.gal, q, tid);
   const uint64_t toff = ((uint64_t)t * L + j) * S::N;
   if (a.add_in) {  // fold step: + the input itself, unpermuted (R + Rot(R))
     WALLY_GLOBAL const uint64_t* r = sel_in(items + b, a.in_sel, a.in_off) + toff;

@@ -175,42 +175,74 @@ __device__ __forceinline__ void exchange(uint64_t (&x)[1 << LOGE], uint64_t* lds
   __syncthreads();
 }
 
-template <int LOGN, int LOGE, int P>
+// The same move through half the LDS: the low 32-bit halves of the words
+// first, then the high halves (N + N/32 32-bit words; four barriers).
+template <int LOGN, int LOGE, int SA, int SB>
+__device__ __forceinline__ void exchange_split(uint64_t (&x)[1 << LOGE], uint64_t* lds, int tid) {
+  using S = NttShape<LOGN, LOGE>;
+  using MA = PassMap<LOGN, LOGE, SA>;
+  using MB = PassMap<LOGN, LOGE, SB>;
+  static_assert(lds_split_holds<LOGN, LOGE, MA>() && lds_split_holds<LOGN, LOGE, MB>(), "padded offsets split");
+  uint32_t* l32 = (uint32_t*)lds;
+  uint32_t* wa = l32 + lds_base<LOGN, LOGE, MA>(tid);
+  const uint32_t* rb = l32 + lds_base<LOGN, LOGE, MB>(tid);
+  uint32_t lo[S::E];
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, MA>(e)] = (uint32_t)x[e];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) lo[e] = rb[lds_off<LOGN, LOGE, MB>(e)];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, MA>(e)] = (uint32_t)(x[e] >> 32);
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) x[e] = ((uint64_t)rb[lds_off<LOGN, LOGE, MB>(e)] << 32) | lo[e];
+  __syncthreads();
+}
+
+template <int LOGN, int LOGE, int P, bool SPLIT = false>
 __device__ __forceinline__ void fwd_passes(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* tw, uint64_t q,
                                            uint64_t q4, int tid) {
   constexpr int S0 = LOGE * P;
   if constexpr (S0 < LOGN) {
-    if constexpr (P > 0) exchange<LOGN, LOGE, LOGE * (P - 1), S0>(x, lds, tid);
+    if constexpr (P > 0) {
+      if constexpr (SPLIT) exchange_split<LOGN, LOGE, LOGE * (P - 1), S0>(x, lds, tid);
+      else exchange<LOGN, LOGE, LOGE * (P - 1), S0>(x, lds, tid);
+    }
     ct_pass<LOGN, LOGE, S0>(x, tw, q, q4, tid);
-    fwd_passes<LOGN, LOGE, P + 1>(x, lds, tw, q, q4, tid);
+    fwd_passes<LOGN, LOGE, P + 1, SPLIT>(x, lds, tw, q, q4, tid);
   }
 }
 
-template <int LOGN, int LOGE, int P>
+template <int LOGN, int LOGE, int P, bool SPLIT = false>
 __device__ __forceinline__ void inv_passes(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* itw, uint64_t q,
                                            uint64_t q4, int tid) {
   if constexpr (P >= 0) {
     constexpr int S0 = LOGE * P;
-    if constexpr (P < NttShape<LOGN, LOGE>::NPASS - 1) exchange<LOGN, LOGE, LOGE * (P + 1), S0>(x, lds, tid);
+    if constexpr (P < NttShape<LOGN, LOGE>::NPASS - 1) {
+      if constexpr (SPLIT) exchange_split<LOGN, LOGE, LOGE * (P + 1), S0>(x, lds, tid);
+      else exchange<LOGN, LOGE, LOGE * (P + 1), S0>(x, lds, tid);
+    }
     gs_pass<LOGN, LOGE, S0>(x, itw, q, q4, tid);
-    inv_passes<LOGN, LOGE, P - 1>(x, lds, itw, q, q4, tid);
+    inv_passes<LOGN, LOGE, P - 1, SPLIT>(x, lds, itw, q, q4, tid);
   }
 }
 
 // Forward transform.  In: FirstMap order, values < 2q.  Out: LastMap order,
 // values below (2 + 4 LOGN) q (reduce with reduce_lazy).
-template <int LOGN, int LOGE>
+template <int LOGN, int LOGE, bool SPLIT = false>
 __device__ __forceinline__ void ntt_fwd(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* tw, uint64_t q,
                                         int tid) {
-  fwd_passes<LOGN, LOGE, 0>(x, lds, tw, q, 4 * q, tid);
+  fwd_passes<LOGN, LOGE, 0, SPLIT>(x, lds, tw, q, 4 * q, tid);
 }
 
 // Inverse transform without the n^-1 factor.  In: LastMap order, values < 4q.
 // Out: FirstMap order, [0, 4q).
-template <int LOGN, int LOGE>
+template <int LOGN, int LOGE, bool SPLIT = false>
 __device__ __forceinline__ void ntt_inv(uint64_t (&x)[1 << LOGE], uint64_t* lds, const ulonglong2* itw, uint64_t q,
                                         int tid) {
-  inv_passes<LOGN, LOGE, NttShape<LOGN, LOGE>::NPASS - 1>(x, lds, itw, q, 4 * q, tid);
+  inv_passes<LOGN, LOGE, NttShape<LOGN, LOGE>::NPASS - 1, SPLIT>(x, lds, itw, q, 4 * q, tid);
 }
 
 // Forward transform with natural-order I/O: in and out in FirstMap order
@@ -259,6 +291,32 @@ __device__ __forceinline__ void gather_galois(uint64_t (&x)[1 << LOGE], SRC src,
   __syncthreads();
 }
 
+// gather_galois through half the LDS: the low 32-bit halves of the row, then
+// the high halves (N + N/32 32-bit words).
+template <int LOGN, int LOGE, class MAP, class SRC>
+__device__ __forceinline__ void gather_galois_split(uint64_t (&x)[1 << LOGE], SRC src, uint64_t* lds, uint32_t gal,
+                                                    int tid) {
+  using S = NttShape<LOGN, LOGE>;
+  using FM = FirstMap<LOGN, LOGE>;
+  uint32_t* l32 = (uint32_t*)lds;
+  uint32_t* wa = l32 + lds_base<LOGN, LOGE, FM>(tid);
+  uint64_t v[S::E];
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) v[e] = __builtin_nontemporal_load(&src[FM::idx(tid, e)]);
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = (uint32_t)v[e];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) x[e] = l32[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = (uint32_t)(v[e] >> 32);
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) x[e] |= (uint64_t)l32[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))] << 32;
+  __syncthreads();
+}
+
 // x <- x + sigma_gal(src) (mod q) in the register mapping MAP, with the same
 // coalesced LDS staging as gather_galois; the permuted word is added as it is
 // read, so no second register row is live.
@@ -273,6 +331,33 @@ __device__ __forceinline__ void add_galois(uint64_t (&x)[1 << LOGE], SRC src, ui
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < S::E; ++e) x[e] = addmod(x[e], lds[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))], q);
+  __syncthreads();
+}
+
+// add_galois through half the LDS (as gather_galois_split).
+template <int LOGN, int LOGE, class MAP, class SRC>
+__device__ __forceinline__ void add_galois_split(uint64_t (&x)[1 << LOGE], SRC src, uint64_t* lds, uint32_t gal,
+                                                 uint64_t q, int tid) {
+  using S = NttShape<LOGN, LOGE>;
+  using FM = FirstMap<LOGN, LOGE>;
+  uint32_t* l32 = (uint32_t*)lds;
+  uint32_t* wa = l32 + lds_base<LOGN, LOGE, FM>(tid);
+  uint64_t v[S::E];
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) v[e] = __builtin_nontemporal_load(&src[FM::idx(tid, e)]);
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = (uint32_t)v[e];
+  __syncthreads();
+  uint32_t lo[S::E];
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) lo[e] = l32[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = (uint32_t)(v[e] >> 32);
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < S::E; ++e)
+    x[e] = addmod(x[e], ((uint64_t)l32[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))] << 32) | lo[e], q);
   __syncthreads();
 }
 
