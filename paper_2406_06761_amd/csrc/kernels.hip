@@ -103,6 +103,27 @@ __device__ __forceinline__ void store_last(PTR dst, const uint64_t (&x)[1 << LOG
   }
 }
 
+// x <- sigma_gal(src) in LastMap order, read straight from global memory.
+// Entry i of an NTT row holds a(psi^(2 brv(i) + 1)); under X -> X^gal (gal
+// odd) the top bits of the source index depend only on the top bits of i,
+// so an aligned pair (i, i + 1) comes from an aligned pair (possibly
+// swapped), and the 128 consecutive entries a wave holds for one register
+// pair come from 8 whole 128-byte lines: the loads use every byte they fetch,
+// as a coalesced read does, and need no LDS staging.
+template <int LOGN, int LOGE, class PTR>
+__device__ __forceinline__ void load_galois_last(uint64_t (&x)[1 << LOGE], PTR src, uint32_t gal, int tid) {
+  using LM = LastMap<LOGN, LOGE>;
+  static_assert(LM::LOWB == 0 && LM::RW >= 1, "pairs of the last pass are adjacent words");
+#pragma unroll
+  for (int c = 0; c < (1 << LOGE) / 2; ++c) {
+    const uint32_t sidx = galois_src<LOGN>(LM::idx(tid, 2 * c), gal);
+    const u64x2 v = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(src + (sidx & ~1u)));
+    const bool odd = sidx & 1u;
+    x[2 * c] = odd ? v.y : v.x;
+    x[2 * c + 1] = odd ? v.x : v.y;
+  }
+}
+
 // XCD-aware placement. The work-groups of a launch go to the eight XCDs round
 // robin (block id mod 8) and each XCD has its own L2. Where a launch has groups
 // of `per` blocks that read the same input row, a group's members get ids that
@@ -134,7 +155,7 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_digits(const K
   const auto c1 = sel_in(items + b, a.in_sel, a.in_off) + ((uint64_t)a.L + i) * S::N;
   const uint64_t q = M.q[i];
   uint64_t x[S::E];
-  gather_galois_split<LOGN, LOGE, LastMap<LOGN, LOGE>>(x, c1, lds, a.gal, tid);  // sigma(c1)_i, INTT input order
+  load_galois_last<LOGN, LOGE>(x, c1, a.gal, tid);  // sigma(c1)_i, INTT input order
   store_last<LOGN, LOGE, true>(a.D + (((uint64_t)b * (a.L + 1) + i) * a.L + i) * S::N, x, tid);  // D[i][i]
   ntt_inv<LOGN, LOGE, true>(x, lds, M.inv[i], q, tid);
   uint64_t* X = a.X + ((uint64_t)b * a.L + i) * S::N;
@@ -271,7 +292,12 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_wa
     z[2 * c] = csub(shoup(u.x + zb - z[2 * c], M.pinv[j], M.pinvp[j], q), q);
     z[2 * c + 1] = csub(shoup(u.y + zb - z[2 * c + 1], M.pinv[j], M.pinvp[j], q), q);
   }
-  if (t == 0) add_galois_split<LOGN, LOGE, LM>(z, sel_in(items + b, a.in_sel, a.in_off) + (uint64_t)j * S::N, lds, a.gal, q, tid);
+  if (t == 0) {  // + sigma(c0)_j
+    uint64_t v[S::E];
+    load_galois_last<LOGN, LOGE>(v, sel_in(items + b, a.in_sel, a.in_off) + (uint64_t)j * S::N, a.gal, tid);
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) z[e] = addmod(z[e], v[e], q);
+  }
   const uint64_t toff = ((uint64_t)t * L + j) * S::N;
   if (a.add_in) {  // fold step: + the input itself, unpermuted (R + Rot(R))
     WALLY_GLOBAL const uint64_t* r = sel_in(items + b, a.in_sel, a.in_off) + toff;

@@ -273,92 +273,4 @@ __device__ __forceinline__ uint32_t galois_src(uint32_t i, uint32_t gal) {
   return __brev((f - 1u) >> 1) >> (32 - LOGN);
 }
 
-// x <- sigma_gal(src) in the register mapping MAP: the row is read with
-// coalesced loads into LDS and permuted there (a direct gather from global
-// memory would touch a different cache line in every lane).  The source row is
-// read once, so the loads are non-temporal.
-template <int LOGN, int LOGE, class MAP, class SRC>
-__device__ __forceinline__ void gather_galois(uint64_t (&x)[1 << LOGE], SRC src, uint64_t* lds, uint32_t gal,
-                                              int tid) {
-  using S = NttShape<LOGN, LOGE>;
-  using FM = FirstMap<LOGN, LOGE>;
-  uint64_t* wa = lds + lds_base<LOGN, LOGE, FM>(tid);
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = __builtin_nontemporal_load(&src[FM::idx(tid, e)]);
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) x[e] = lds[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))];
-  __syncthreads();
-}
-
-// gather_galois through half the LDS: the low 32-bit halves of the row, then
-// the high halves (N + N/32 32-bit words).
-template <int LOGN, int LOGE, class MAP, class SRC>
-__device__ __forceinline__ void gather_galois_split(uint64_t (&x)[1 << LOGE], SRC src, uint64_t* lds, uint32_t gal,
-                                                    int tid) {
-  using S = NttShape<LOGN, LOGE>;
-  using FM = FirstMap<LOGN, LOGE>;
-  uint32_t* l32 = (uint32_t*)lds;
-  uint32_t* wa = l32 + lds_base<LOGN, LOGE, FM>(tid);
-  uint64_t v[S::E];
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) v[e] = __builtin_nontemporal_load(&src[FM::idx(tid, e)]);
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = (uint32_t)v[e];
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) x[e] = l32[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))];
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = (uint32_t)(v[e] >> 32);
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) x[e] |= (uint64_t)l32[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))] << 32;
-  __syncthreads();
-}
-
-// x <- x + sigma_gal(src) (mod q) in the register mapping MAP, with the same
-// coalesced LDS staging as gather_galois; the permuted word is added as it is
-// read, so no second register row is live.
-template <int LOGN, int LOGE, class MAP, class SRC>
-__device__ __forceinline__ void add_galois(uint64_t (&x)[1 << LOGE], SRC src, uint64_t* lds, uint32_t gal,
-                                           uint64_t q, int tid) {
-  using S = NttShape<LOGN, LOGE>;
-  using FM = FirstMap<LOGN, LOGE>;
-  uint64_t* wa = lds + lds_base<LOGN, LOGE, FM>(tid);
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = __builtin_nontemporal_load(&src[FM::idx(tid, e)]);
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) x[e] = addmod(x[e], lds[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))], q);
-  __syncthreads();
-}
-
-// add_galois through half the LDS (as gather_galois_split).
-template <int LOGN, int LOGE, class MAP, class SRC>
-__device__ __forceinline__ void add_galois_split(uint64_t (&x)[1 << LOGE], SRC src, uint64_t* lds, uint32_t gal,
-                                                 uint64_t q, int tid) {
-  using S = NttShape<LOGN, LOGE>;
-  using FM = FirstMap<LOGN, LOGE>;
-  uint32_t* l32 = (uint32_t*)lds;
-  uint32_t* wa = l32 + lds_base<LOGN, LOGE, FM>(tid);
-  uint64_t v[S::E];
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) v[e] = __builtin_nontemporal_load(&src[FM::idx(tid, e)]);
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = (uint32_t)v[e];
-  __syncthreads();
-  uint32_t lo[S::E];
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) lo[e] = l32[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))];
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) wa[lds_off<LOGN, LOGE, FM>(e)] = (uint32_t)(v[e] >> 32);
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < S::E; ++e)
-    x[e] = addmod(x[e], ((uint64_t)l32[S::lds(galois_src<LOGN>(MAP::idx(tid, e), gal))] << 32) | lo[e], q);
-  __syncthreads();
-}
-
 }  // namespace wally
