@@ -7,9 +7,9 @@
 //
 // Key switching for CtRotate (paper §2.1) follows the hybrid RNS method of
 // paper §7.1 with one digit per ciphertext limb and one special prime P:
-//   ks_digits : x_i = INTT_{q_i}(sigma(c1)_i), D[i][i] = sigma(c1)_i  (L per item)
+//   ks_digits : x_i = INTT_{q_i}(sigma(c1)_i)                         (L per item)
 //   ks_extend : D[m][i] = NTT_m(x_i mod m), m in {q_0..q_{L-1}, P} \ {q_i}   (L^2 per item)
-//   ks_inner  : u_t[m] = sum_i D[m][i] * key[i][t][m]               (elementwise)
+//   ks_inner  : u_t[m] = sum_i D[m][i] * key[i][t][m], D[i][i] = sigma(c1)_i (elementwise)
 //   ks_pinv   : y_t = INTT_P(u_t[P])                                (2 per item)
 //   ks_moddown: out_t[j] = (u_t[j] - NTT_j([y_t]_centred mod q_j)) * P^-1
 //               (+ sigma(c0)_j for t = 0) (+ acc_i)                (2L per item)
@@ -140,12 +140,12 @@ __device__ __forceinline__ GroupSlot xcd_group(uint32_t id, uint32_t per) {
 inline uint32_t xcd_blocks(uint32_t groups, uint32_t per) { return (groups + kXcds - 1) / kXcds * kXcds * per; }
 
 // ---------------------------------------------------------------------------
-// key switching, step 1: digits.  The gathered sigma(c1)_i is also the
-// extended digit D[i][i] (its own modulus needs no transform) and is stored
-// as such here, so the extension kernel only transforms.
+// key switching, step 1: digits.  The extended digit D[i][i] (digit i in its
+// own modulus) is sigma(c1)_i itself: it is not stored, the inner product
+// reads it from the input row.
 // grid (items, L); block T
 template <int LOGN, int LOGE>
-__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_digits(const KsItem* __restrict__ items, KsArgs a,
+__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_waves_per_eu(8))) void k_ks_digits(const KsItem* __restrict__ items, KsArgs a,
                                                                          DevModuli M) {
   using S = NttShape<LOGN, LOGE>;
   using FM = FirstMap<LOGN, LOGE>;
@@ -156,7 +156,6 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_digits(const K
   const uint64_t q = M.q[i];
   uint64_t x[S::E];
   load_galois_last<LOGN, LOGE>(x, c1, a.gal, tid);  // sigma(c1)_i, INTT input order
-  store_last<LOGN, LOGE, true>(a.D + (((uint64_t)b * (a.L + 1) + i) * a.L + i) * S::N, x, tid);  // D[i][i]
   ntt_inv<LOGN, LOGE, true>(x, lds, M.inv[i], q, tid);
   uint64_t* X = a.X + ((uint64_t)b * a.L + i) * S::N;
 #pragma unroll
@@ -165,7 +164,8 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_digits(const K
 
 // ---------------------------------------------------------------------------
 // key switching, step 2: extended digits D[m][i] = NTT_m(x_i mod m) for the
-// L moduli m != i of Q P (D[i][i] is written by the digit kernel).
+// L moduli m != i of Q P (D[i][i] = sigma(c1)_i is read by the inner product
+// from the input row).
 // 1-D grid of xcd_blocks(items * L, L): group (b, i) reads digit x_i of item
 // b, its L members are the target moduli m; block T
 template <int LOGN, int LOGE>
@@ -197,7 +197,9 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const K
 // key switching, step 3: key inner product u_t[m] = sum_i D[m][i] * key[i][t][m]
 // with one 128-bit lazy sum per output word (elementwise, memory bound; two
 // words per thread through 16-byte loads).  D words are below 54 q (the
-// forward transform's lazy bound), key words below q.
+// forward transform's lazy bound), key words below q.  D[m][m] (m < L) is
+// sigma(c1)_m, read from the input row as load_galois_last does: the aligned
+// pair of words a thread takes comes from an aligned pair there.
 // grid (n / 512, L+1, items); block 256
 template <int L>
 __global__ __launch_bounds__(256) void k_ks_inner(const KsItem* __restrict__ items, KsArgs a, DevModuli M) {
@@ -208,12 +210,22 @@ __global__ __launch_bounds__(256) void k_ks_inner(const KsItem* __restrict__ ite
   WALLY_GLOBAL const uint64_t* key = a.key_fold ? gmem(items[b].key_fold) + a.key_off : gmem(items[b].key);
   const uint64_t* D = a.D + ((uint64_t)b * MM + m) * L * n + p;
   const ModConst mc = M.mc[m];
+  // source of sigma(c1)_m at p (and p + 1): entry p holds a(psi^(2 brv(p) + 1))
+  const uint32_t mask2n = (2u << a.log_n) - 1;
+  const uint32_t ep = 2u * (__brev((uint32_t)p) >> (32 - a.log_n)) + 1u;
+  const uint32_t sidx = __brev((((ep * a.gal) & mask2n) - 1u) >> 1) >> (32 - a.log_n);
   // all 3L loads of a thread are issued before the first product (L is a
   // compile-time constant), so each thread keeps 48 L bytes in flight
   u64x2 d[L], k0[L], k1[L];
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    d[i] = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(D + (uint64_t)i * n));
+    if (i == m) {
+      const u64x2 v = __builtin_nontemporal_load(
+          (WALLY_GLOBAL const u64x2*)(sel_in(items + b, a.in_sel, a.in_off) + ((uint64_t)L + m) * n + (sidx & ~1u)));
+      d[i] = (sidx & 1u) ? u64x2{v.y, v.x} : v;
+    } else {
+      d[i] = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(D + (uint64_t)i * n));
+    }
     k0[i] = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + 0) * MM + m) * n + p));
     k1[i] = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + 1) * MM + m) * n + p));
   }
