@@ -87,6 +87,7 @@ def test_error_strings_and_null_handling():
     assert lib.wally_params_init(None, None) == wally.EINVAL
     lib.wally_destroy(None)  # no-op
     assert lib.wally_last_error(None) == b"null context"
+    assert lib.wally_pir_set_linear(None, 1) == wally.EINVAL
     # unsupported sizes are rejected before any device call
     d = wally.ParamsDesc(11, 3, 36, 20, 64, 0, 0, 0, 0, 0, 0)
     h = ctypes.c_void_p()
