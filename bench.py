@@ -686,7 +686,7 @@ def main():
     if not args.no_tune and args.workload != "tiny":
         t0 = time.perf_counter()
         sub = q[: min(8192, nq)]
-        res = ctx.tune(sub, batches=(512, 1024), sets=(2, 3), tiles=(8, 16), radices=(8, 16))
+        res = ctx.tune(sub, batches=(128, 256, 512), sets=(3, 6), tiles=(8, 16), radices=(8, 16))
         best = min(res, key=lambda r: r[4])
         tuned = {"sample_queries": len(sub), "candidates": [list(r) for r in res],
                  "candidate_fields": ["max_batch", "wave_sets", "tile_items", "ntt_radix", "ms"],
@@ -801,16 +801,23 @@ def main():
     # share the GPU.
     isolated = None
     if timing:
+        # launches of 512 items whatever the scoring schedule: a context of
+        # its own (no index) with waves of 512
+        from paper_2406_06761_amd.wally import Context as _Ctx
+
+        ictx = _Ctx.preset(preset_name, max_batch=512)
         cnt = min(1024, pool)
         out_i = torch.empty_like(cts[:cnt])
-        ctx.diag_rotate(cts[:cnt], kbs[:cnt], out_i, 0)
+        ictx.diag_rotate(cts[:cnt], kbs[:cnt], out_i, 0)
         torch.cuda.synchronize()
-        ctx.kernel_timing(True)
-        ctx.kernel_stats()
+        ictx.kernel_timing(True)
+        ictx.kernel_stats()
         for r in range(5):
-            ctx.diag_rotate(cts[:cnt], kbs[:cnt], out_i, r & 1)
-        ist = ctx.kernel_stats()
-        ctx.kernel_timing(False)
+            ictx.diag_rotate(cts[:cnt], kbs[:cnt], out_i, r & 1)
+        ist = ictx.kernel_stats()
+        ictx.kernel_timing(False)
+        ictx.close()
+        del out_i
         isolated = {}
         for k, (nl, it, ms) in ist.items():
             if not nl:
@@ -889,9 +896,25 @@ def main():
         log(f"plain per-cluster path: {pdt / args.plain_steps * 1e3:.1f} ms/step, {plain:.4g} scores/s")
 
     serving = None
+    serving_schedule = None
     if args.serve_rates:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
+        # serving runs on the library's default schedule (waves of 512, two in
+        # flight, or the --max-batch/--wave-sets given): many waves in flight
+        # lower the throughput a batch needs but raise the latency of a lightly
+        # loaded server.  wally_tune with one candidate sets it, and the tuned
+        # schedule is restored after.
+        sb, ss = args.max_batch or 512, args.wave_sets or 2
+        st_tile = tuned["chosen"]["tile_items"] if tuned else 8
+        st_radix = tuned["chosen"]["ntt_radix"] if tuned else 16
+        if tuned and (tuned["chosen"]["max_batch"], tuned["chosen"]["wave_sets"]) != (sb, ss):
+            ctx.tune(q[: min(2048, nq)], batches=(sb,), sets=(ss,), tiles=(st_tile,), radices=(st_radix,))
+        serving_schedule = {"max_batch": sb, "wave_sets": ss, "tile_items": st_tile, "ntt_radix": st_radix}
         serving = serve_rates(ctx, w, chunks, cts, kbs, kgs, pool, rates, args.serve_seconds)
+        if tuned and (tuned["chosen"]["max_batch"], tuned["chosen"]["wave_sets"]) != (sb, ss):
+            ch = tuned["chosen"]
+            ctx.tune(q[: min(2048, nq)], batches=(ch["max_batch"],), sets=(ch["wave_sets"],),
+                     tiles=(ch["tile_items"],), radices=(ch["ntt_radix"],))
 
     # The 500k-query batch (503,710 with the fakes) on the same resident index:
     # one warm-up and the timed steps on the batched path.  Its responses
@@ -1040,6 +1063,7 @@ def main():
         "tuned": tuned,
         "response_compression": compress,
         "serving": serving,
+        "serving_schedule": serving_schedule,
         "serving_capacity_qps": max((r["sustained_qps"] for r in serving), default=None) if serving else None,
         "epoch_s": EPOCH_S,
         "batch500k": batch500k,

@@ -88,7 +88,8 @@ typedef struct {
   uint32_t max_batch;  /* queries resident per wave (0 = 512, at most 32768;
                           max_batch x chunks of the largest cluster at most
                           32768, else scoring returns WALLY_EINVAL)          */
-  uint32_t wave_sets;  /* waves in flight on separate streams (0 = 2)       */
+  uint32_t wave_sets;  /* waves in flight on separate streams (0 = 2, at
+                          most 8)                                          */
   uint32_t fold_max;   /* WALLY_LAYOUT_FOLDED: largest fold factor, a power
                           of two (0 = 16); must be 0 for the other layouts  */
   uint64_t hbm_budget; /* bytes the context may allocate (0 = 90% of free)  */

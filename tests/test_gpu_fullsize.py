@@ -163,13 +163,17 @@ def _check_layout(ctx, lay, p, k_step=1):
         assert (chunks, base, (ptr - chunk0) // ptw_bytes) == (lay.chunks[k], lay.base[k], lay.first[k]), k
 
 
-def test_paper_scale_sampled_parity():
+@pytest.mark.parametrize("max_batch,wave_sets", [(0, 0), (128, 6)])
+def test_paper_scale_sampled_parity(max_batch, wave_sets):
+    """The paper-scale batch at the default schedule (waves of 512, two
+    streams) and at the one the benchmark's tuner has chosen on these boxes
+    (waves of 128, six streams)."""
     from paper_2406_06761_amd.wally import PATH_BATCHED, Context
 
     p, emb = _paper_index()
     w = synth.paper_workload()
     lay = layout.per_cluster(w.sizes, p.n)
-    ctx = Context.preset("paper")  # default wave size and streams, as in the benchmark
+    ctx = Context.preset("paper", max_batch=max_batch, wave_sets=wave_sets)
     try:
         ctx.encode_clusters(emb, synth.offsets(w.sizes))
         _check_layout(ctx, lay, p, 7)
