@@ -712,10 +712,9 @@ int wally_params_init(const wally_params_desc* desc, wally_ctx** out) {
     return WALLY_EDEVICE;
   }
   c->budget = desc->hbm_budget ? desc->hbm_budget : (uint64_t)(free_b * 0.9);
-  // default schedule: waves of 512 queries, two in flight.  For whole
-  // batches wally_tune often finds waves of 128 on six streams 1-2% faster,
-  // but in serving at low rates six waves in flight slow each other down
-  // (p50 twice that of two), so the default keeps two.
+  // default schedule: waves of 512 queries, two in flight.  Waves of 128 on
+  // six streams can be 1-2% faster for whole batches, but in serving at low
+  // rates six waves in flight slow each other down (p50 twice that of two).
   c->B = desc->max_batch ? (int)desc->max_batch : 512;
   c->n_sets = desc->wave_sets ? (int)desc->wave_sets : 2;
   if (c->n_sets > 8) c->n_sets = 8;
