@@ -69,6 +69,16 @@ def per_item_work(kernel, n, L, g, h):
     return sum(per_item_units(kernel, n, L, g, h).values())
 
 
+def roofline_kind(kernel, n, L, g, h):
+    """How a kernel's rate is priced: "hbm" (the key inner product streams its
+    key), "bfly" (forward butterflies only: butterflies/s against 39.3e12 / 17)
+    or "instr" (anything else, mixed units or multiply-accumulates: VALU
+    lane-instructions at each unit's compiled cost against 39.3e12)."""
+    if kernel == "ks_inner":
+        return "hbm"
+    return "bfly" if set(per_item_units(kernel, n, L, g, h)) == {"bfly_fwd"} else "instr"
+
+
 def per_item_instr(kernel, n, L, g, h):
     """VALU lane-instructions per work item at the compiled cost of each unit."""
     return sum(v * INSTR[k] for k, v in per_item_units(kernel, n, L, g, h).items())
@@ -743,12 +753,13 @@ def main():
         items_per_launch = items / max(launches, 1)
         peak = PEAK_VALU_LANE_OPS / INSTR_PER_MODMUL
         step_instr = sum(kstats[k][1] * per_item_instr(k, n, L, info.g, info.h) for k in kstats) / args.steps
-        if dom == "ks_inner":  # streams the key: HBM bound
+        kind = roofline_kind(dom, n, L, info.g, info.h)
+        if kind == "hbm":  # streams the key: HBM bound
             achieved = inner_bytes(n, L) * items_per_launch / (avg_ms * 1e-3)
             roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                         "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
                         "bytes_per_item": inner_bytes(n, L)}
-        elif len(per_item_units(dom, n, L, info.g, info.h)) > 1:  # mixed units: VALU lane-instructions
+        elif kind == "instr":
             ins = per_item_instr(dom, n, L, info.g, info.h)
             achieved = ins * items_per_launch / (avg_ms * 1e-3)
             roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e9, "peak": PEAK_VALU_LANE_OPS / 1e9,

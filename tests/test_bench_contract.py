@@ -50,3 +50,18 @@ def test_instruction_weighted_work():
     assert bench.per_item_instr("ks_inner", n, L, g, h) == 31 * 2 * L * (L + 1) * n
     assert bench.per_item_instr("mac", n, L, g, h) == 9.25 * 2 * g * L * n * h
     assert bench.per_item_instr("copy_ct", n, L, g, h) == 0
+
+
+def test_roofline_pricing_of_each_kernel():
+    """Only a kernel of forward butterflies alone is priced in butterflies; the
+    giant-step sums (multiply-accumulates) and the mixed kernels in VALU
+    lane-instructions; the key inner product against HBM."""
+    sys.path.insert(0, str(ROOT))
+    import bench
+
+    n, L, g, h = 8192, 4, 16, 16
+    assert bench.roofline_kind("ks_extend", n, L, g, h) == "bfly"
+    assert bench.roofline_kind("ks_inner", n, L, g, h) == "hbm"
+    for k in ("ks_digits", "ks_pinv", "ks_moddown", "mac"):
+        assert bench.roofline_kind(k, n, L, g, h) == "instr", k
+
