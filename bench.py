@@ -112,8 +112,9 @@ KERNEL_SOURCES = ["kernels.hip", "ntt.h", "arith.h", "kernels.h", "items.h"]
 
 
 def kernel_source_hash():
-    """Hash of the kernel sources with comments and blank lines removed, so
-    that an edit of a comment does not invalidate the stored counters."""
+    """Hash of the kernel sources with comments and all whitespace removed, so
+    that an edit of a comment or of the layout does not invalidate the stored
+    counters."""
     import hashlib
     import re
 
@@ -121,8 +122,8 @@ def kernel_source_hash():
     for f in KERNEL_SOURCES:
         text = (Path(__file__).resolve().parent / "paper_2406_06761_amd" / "csrc" / f).read_text()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
-        h.update("\n".join(ln for ln in lines if ln.strip()).encode())
+        lines = [re.sub(r"//.*$", "", ln) for ln in text.splitlines()]
+        h.update(re.sub(r"\s+", "", "".join(lines)).encode())
     return h.hexdigest()
 
 

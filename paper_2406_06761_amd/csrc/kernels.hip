@@ -143,10 +143,12 @@ inline uint32_t xcd_blocks(uint32_t groups, uint32_t per) { return (groups + kXc
 // key switching, step 1: digits.  The extended digit D[i][i] (digit i in its
 // own modulus) is sigma(c1)_i itself: it is not stored, the inner product
 // reads it from the input row.
+// Held at eight waves per SIMD (64 VGPRs, four workgroups per CU; it spills
+// two registers).
 // grid (items, L); block T
 template <int LOGN, int LOGE>
-__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_waves_per_eu(8))) void k_ks_digits(const KsItem* __restrict__ items, KsArgs a,
-                                                                         DevModuli M) {
+__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_waves_per_eu(8))) void k_ks_digits(
+    const KsItem* __restrict__ items, KsArgs a, DevModuli M) {
   using S = NttShape<LOGN, LOGE>;
   using FM = FirstMap<LOGN, LOGE>;
   __shared__ uint64_t lds[(S::LDS_WORDS + 1) / 2];  // 32-bit exchanges
