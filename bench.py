@@ -39,8 +39,11 @@ PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 39.3e
 # a giant-step multiply-accumulate with 27-bit split operands 9.25 (296 per 32
 # products, the per-output fold included), a key inner-product step with a
 # 128-bit sum 31 (the straight-line kernel body: 497 per 16 products,
-# reductions and addressing included).
-INSTR = {"bfly_fwd": 17.0, "bfly_inv": 21.0, "scale": 13.0, "mac27": 9.25, "mac128": 31.0}
+# reductions and addressing included), and 22.5 in the loop that forms the
+# inner products of the q_j rows inside the division by P (43 and 47 VALU
+# instructions per two products in its two loop bodies).
+INSTR = {"bfly_fwd": 17.0, "bfly_inv": 21.0, "scale": 13.0, "mac27": 9.25, "mac128": 31.0,
+         "mac128_loop": 22.5}
 INSTR_PER_MODMUL = INSTR["bfly_fwd"]        # the dominant kernel's unit: a forward butterfly
 HBM_PEAK = 8.0e12
 EPOCH_S = 10.0  # shortest epoch of the paper's serving table: every query must finish within it
@@ -57,9 +60,9 @@ def per_item_units(kernel, n, L, g, h):
     return {
         "ks_digits": {"bfly_inv": L * bf, "scale": L * n},
         "ks_extend": {"bfly_fwd": L * L * bf},
-        "ks_inner": {"mac128": 2 * L * (L + 1) * n},
+        "ks_inner": {"mac128": 2 * L * n},  # the P rows only
         "ks_pinv": {"bfly_inv": 2 * bf, "scale": 2 * n},
-        "ks_moddown": {"bfly_fwd": 2 * L * bf, "scale": 2 * L * n},
+        "ks_moddown": {"bfly_fwd": 2 * L * bf, "scale": 2 * L * n, "mac128_loop": 2 * L * L * n},
         "mac": {"mac27": 2 * g * L * n * h},
     }.get(kernel, {})
 
@@ -102,9 +105,9 @@ def host_cpu():
 
 
 def inner_bytes(n, L):
-    """Compulsory HBM bytes per item of the key inner product: the key
-    L x 2 x (L+1) x n, the extended digits (L+1) x L x n, the output 2 x (L+1) x n."""
-    return 8 * n * (2 * L * (L + 1) + (L + 1) * L + 2 * (L + 1))
+    """Compulsory HBM bytes per item of the key inner product of the P rows:
+    their key L x 2 x n, their extended digits L x n, the output 2 x n."""
+    return 8 * n * (2 * L + L + 2)
 
 
 TRAFFIC_FILE = Path(__file__).resolve().parent / "profiles" / "hbm_traffic_paper.json"
@@ -847,9 +850,12 @@ def main():
                 ins = per_item_instr(k, n, L, info.g, info.h)
                 e.update(bound="alu", achieved_gunits=w_ * it / (ms * 1e-3) / 1e9,
                          frac=ins * it / (ms * 1e-3) / PEAK_VALU_LANE_OPS)
+            tb = stored_traffic(k, preset_name)
+            if tb is not None:  # the same launches against HBM, at the counter-calibrated bytes
+                e["hbm_frac"] = tb * it / (ms * 1e-3) / HBM_PEAK
             isolated[k] = e
             log(f"  isolated {k:11s} {e['ms_per_launch']:.3f} ms per launch of {e['items_per_launch']:.0f} items, "
-                f"frac {e['frac']:.3f}")
+                f"frac {e['frac']:.3f}" + (f", HBM {e['hbm_frac']:.3f}" if "hbm_frac" in e else ""))
         # the measured peak of the transforms' arithmetic: the register-resident
         # butterfly loop (wally_diag_bfly_rate) forward and inverse
         bout = torch.empty(4096 * 256 * 16, dtype=torch.int64, device="cuda")
@@ -870,6 +876,7 @@ def main():
             traffic = stored_traffic(roofline["kernel"], preset_name)
             if traffic is not None:
                 roofline["traffic"] = traffic * roofline["items_per_launch"]
+                roofline["traffic_frac"] = roofline["traffic"] / (roofline["avg_launch_ms"] * 1e-3) / HBM_PEAK
             # the whole key switch against HBM: counter-calibrated bytes per
             # item of each of its kernels times the items of one step
             ks = [k for k in kstats if k.startswith("ks_") and kstats[k][1]]

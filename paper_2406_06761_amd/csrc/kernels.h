@@ -40,7 +40,7 @@ struct KsArgs {
   uint64_t key_off;
   int g;
   uint64_t* X;  // scratch [items][L][n]
-  uint64_t* U;  // scratch [items][2][L+1][n]: key inner products (m = L: the P part)
+  uint64_t* U;  // scratch [items][2][L+1][n]: key inner products; only m = L (the P part) is written
   uint64_t* Y;  // scratch [items][2][n]
   uint64_t* D;  // scratch [items][L+1][L][n]: extended digits
 };

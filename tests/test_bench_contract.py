@@ -23,21 +23,23 @@ def test_work_per_item_and_inner_bytes():
     bf = n // 2 * 13  # butterflies of one 8192-point transform
     assert bench.per_item_work("ks_extend", n, L, 16, 16) == L * L * bf
     assert bench.per_item_work("ks_digits", n, L, 16, 16) == L * (bf + n)
-    assert bench.per_item_work("ks_inner", n, L, 16, 16) == 2 * L * (L + 1) * n
-    assert bench.per_item_work("ks_moddown", n, L, 16, 16) == 2 * L * bf + 2 * L * n
+    # the P rows' inner products apart; those of the q_j rows inside moddown
+    assert bench.per_item_work("ks_inner", n, L, 16, 16) == 2 * L * n
+    assert bench.per_item_work("ks_moddown", n, L, 16, 16) == 2 * L * bf + 2 * L * n + 2 * L * L * n
     # one key switch: 30 transforms, the n^-1 scalings of its L + 2 inverse
     # transforms, the inner products and the P^-1 products
     ks = sum(bench.per_item_work(k, n, L, 16, 16) for k in ("ks_digits", "ks_extend", "ks_inner", "ks_pinv",
                                                               "ks_moddown"))
     assert ks == 30 * bf + (L + 2) * n + 2 * L * (L + 1) * n + 2 * L * n == 2_039_808
-    # key 2.5 MiB + extended digits 1.25 MiB in, inner products 640 KiB out
-    assert bench.inner_bytes(n, L) == 4.375 * 2**20
+    # the P rows: key 512 KiB + extended digits 256 KiB in, 128 KiB out
+    assert bench.inner_bytes(n, L) == 0.875 * 2**20
 
 
 def test_instruction_weighted_work():
     """The path fraction counts each unit at its compiled VALU instruction
     cost: a forward butterfly 17, an inverse one 21, a scaling 13, a
-    27-bit-split product 9.25, a 128-bit-sum product 31."""
+    27-bit-split product 9.25, a 128-bit-sum product 31 (22.5 in moddown's
+    loop)."""
     sys.path.insert(0, str(ROOT))
     import bench
 
@@ -46,8 +48,8 @@ def test_instruction_weighted_work():
     assert bench.per_item_instr("ks_extend", n, L, g, h) == 17 * L * L * bf
     assert bench.per_item_instr("ks_digits", n, L, g, h) == 21 * L * bf + 13 * L * n
     assert bench.per_item_instr("ks_pinv", n, L, g, h) == 21 * 2 * bf + 13 * 2 * n
-    assert bench.per_item_instr("ks_moddown", n, L, g, h) == 17 * 2 * L * bf + 13 * 2 * L * n
-    assert bench.per_item_instr("ks_inner", n, L, g, h) == 31 * 2 * L * (L + 1) * n
+    assert bench.per_item_instr("ks_moddown", n, L, g, h) == 17 * 2 * L * bf + 13 * 2 * L * n + 22.5 * 2 * L * L * n
+    assert bench.per_item_instr("ks_inner", n, L, g, h) == 31 * 2 * L * n
     assert bench.per_item_instr("mac", n, L, g, h) == 9.25 * 2 * g * L * n * h
     assert bench.per_item_instr("copy_ct", n, L, g, h) == 0
 
