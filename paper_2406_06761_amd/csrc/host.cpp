@@ -1312,7 +1312,7 @@ extern "C" {
 // waves and launches the next ones.
 
 namespace {
-int serve_pump(wally_ctx* c) {
+static int serve_pump(wally_ctx* c) {
   int rc;
   for (auto& s : c->sets) {
     if (s.busy) {
@@ -1452,6 +1452,8 @@ void wally_destroy(wally_ctx* c) {
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
+
+}  // extern "C"
 
 // ---------------------------------------------------------------------------
 // Index PIR for metadata fetch (paper §4.2, MulPIR): oblivious expansion of
@@ -2083,6 +2085,8 @@ int wally_pir_set_linear(wally_ctx* c, int on) {
 
 // ---------------------------------------------------------------------------
 // diagnostics
+
+extern "C" {
 
 int wally_diag_ntt(wally_ctx* c, uint32_t mi, uint64_t* data, uint64_t rows, int inverse, void* hip_stream) {
   int rc = check_live(c);
