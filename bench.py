@@ -61,8 +61,10 @@ def per_item_units(kernel, n, L, g, h):
         "ks_digits": {"bfly_inv": L * bf, "scale": L * n},
         "ks_extend": {"bfly_fwd": L * L * bf},
         "ks_inner": {"mac128": 2 * L * n},  # the P rows only
+        "ks_inner_all": {"mac128": 2 * L * (L + 1) * n},  # every row (launches of few items)
         "ks_pinv": {"bfly_inv": 2 * bf, "scale": 2 * n},
         "ks_moddown": {"bfly_fwd": 2 * L * bf, "scale": 2 * L * n, "mac128_loop": 2 * L * L * n},
+        "ks_moddown_u": {"bfly_fwd": 2 * L * bf, "scale": 2 * L * n},  # reads the stored inner products
         "mac": {"mac27": 2 * g * L * n * h},
     }.get(kernel, {})
 
@@ -77,7 +79,7 @@ def roofline_kind(kernel, n, L, g, h):
     key), "bfly" (forward butterflies only: butterflies/s against 39.3e12 / 17)
     or "instr" (anything else, mixed units or multiply-accumulates: VALU
     lane-instructions at each unit's compiled cost against 39.3e12)."""
-    if kernel == "ks_inner":
+    if kernel in ("ks_inner", "ks_inner_all"):
         return "hbm"
     return "bfly" if set(per_item_units(kernel, n, L, g, h)) == {"bfly_fwd"} else "instr"
 
@@ -104,10 +106,12 @@ def host_cpu():
     return model, visible
 
 
-def inner_bytes(n, L):
-    """Compulsory HBM bytes per item of the key inner product of the P rows:
-    their key L x 2 x n, their extended digits L x n, the output 2 x n."""
-    return 8 * n * (2 * L + L + 2)
+def inner_bytes(n, L, kernel="ks_inner"):
+    """Compulsory HBM bytes per item of the key inner product: of the P rows
+    (ks_inner: their key L x 2 x n, their extended digits L x n, the output
+    2 x n) or of all L + 1 rows (ks_inner_all)."""
+    rows = L + 1 if kernel == "ks_inner_all" else 1
+    return 8 * n * rows * (2 * L + L + 2)
 
 
 TRAFFIC_FILE = Path(__file__).resolve().parent / "profiles" / "hbm_traffic_paper.json"
@@ -759,10 +763,10 @@ def main():
         step_instr = sum(kstats[k][1] * per_item_instr(k, n, L, info.g, info.h) for k in kstats) / args.steps
         kind = roofline_kind(dom, n, L, info.g, info.h)
         if kind == "hbm":  # streams the key: HBM bound
-            achieved = inner_bytes(n, L) * items_per_launch / (avg_ms * 1e-3)
+            achieved = inner_bytes(n, L, dom) * items_per_launch / (avg_ms * 1e-3)
             roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                         "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
-                        "bytes_per_item": inner_bytes(n, L)}
+                        "bytes_per_item": inner_bytes(n, L, dom)}
         elif kind == "instr":
             ins = per_item_instr(dom, n, L, info.g, info.h)
             achieved = ins * items_per_launch / (avg_ms * 1e-3)
@@ -842,9 +846,9 @@ def main():
             if not nl:
                 continue
             e = {"ms_per_launch": ms / nl, "items_per_launch": it / nl}
-            if k == "ks_inner":  # streams the key: HBM bound
-                e.update(bound="hbm", achieved_gbs=inner_bytes(n, L) * it / (ms * 1e-3) / 1e9,
-                         frac=inner_bytes(n, L) * it / (ms * 1e-3) / HBM_PEAK)
+            if k in ("ks_inner", "ks_inner_all"):  # streams the key: HBM bound
+                e.update(bound="hbm", achieved_gbs=inner_bytes(n, L, k) * it / (ms * 1e-3) / 1e9,
+                         frac=inner_bytes(n, L, k) * it / (ms * 1e-3) / HBM_PEAK)
             else:
                 w_ = per_item_work(k, n, L, info.g, info.h)
                 ins = per_item_instr(k, n, L, info.g, info.h)
@@ -881,13 +885,16 @@ def main():
             # item of each of its kernels times the items of one step
             ks = [k for k in kstats if k.startswith("ks_") and kstats[k][1]]
             bpi = {k: stored_traffic(k, preset_name) for k in ks}
-            if ks and all(v is not None for v in bpi.values()):
-                ks_bytes = sum(bpi[k] * kstats[k][1] for k in ks) / args.steps
+            known = [k for k in ks if bpi[k] is not None]
+            if known:
+                ks_bytes = sum(bpi[k] * kstats[k][1] for k in known) / args.steps
                 roofline["path_hbm"] = {
                     "scope": "key-switch kernels (calibrated bytes per item x items per step); the giant-step sums "
                              "and copies add a few percent more",
                     "bytes_per_step": ks_bytes, "achieved_tbs": ks_bytes / (ms_per_step * 1e-3) / 1e12,
-                    "frac": ks_bytes / (ms_per_step * 1e-3) / HBM_PEAK}
+                    "frac": ks_bytes / (ms_per_step * 1e-3) / HBM_PEAK,
+                    # items per step of kernels the counter profile does not cover (not in the sum)
+                    "uncounted_items": {k: kstats[k][1] / args.steps for k in ks if bpi[k] is None}}
 
     graph = None
     graph_b = tuned["chosen"]["max_batch"] if tuned else (args.max_batch or 512)

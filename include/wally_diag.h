@@ -36,12 +36,17 @@ int wally_diag_rotate(wally_ctx* ctx, const uint64_t* in, const uint64_t* keys, 
  * records. */
 #define WALLY_KERNEL_DIGITS 0   /* key switch: INTT of the digits            */
 #define WALLY_KERNEL_EXTEND 1   /* key switch: NTT of the extended digits    */
-#define WALLY_KERNEL_INNER 2    /* key switch: key inner product             */
+#define WALLY_KERNEL_INNER 2    /* key switch: key inner product, P rows     */
 #define WALLY_KERNEL_PINV 3     /* key switch: INTT of the P part            */
-#define WALLY_KERNEL_MODDOWN 4  /* key switch: division by P (+ acc_i)       */
+#define WALLY_KERNEL_MODDOWN 4  /* key switch: division by P (+ acc_i), with
+                                   the inner products of the q_j rows       */
 #define WALLY_KERNEL_MAC 5      /* giant-step sums (plaintext products)      */
 #define WALLY_KERNEL_COPY 6     /* query copy into the baby-step buffer      */
-#define WALLY_KERNEL_COUNT 7
+/* launches of fewer than 256 items: the inner products of every row in one
+ * kernel, and the division by P reading them */
+#define WALLY_KERNEL_INNER_ALL 7   /* key switch: key inner product, all rows */
+#define WALLY_KERNEL_MODDOWN_U 8   /* key switch: division by P, stored u     */
+#define WALLY_KERNEL_COUNT 9
 
 /* Register-resident butterfly rate: the peak of the transforms' arithmetic.
  * One launch of `blocks` workgroups of 256 threads; each thread keeps 16

@@ -370,13 +370,23 @@ hipError_t timed(wally_ctx* c, hipStream_t st, int kernel, uint64_t items, F fn)
   return e;
 }
 
+// Launches of at least this many items form the inner products of the q_j
+// rows inside the division by P (less HBM traffic; each workgroup then does
+// more work, at two workgroups per CU); smaller launches keep them in the
+// inner-product kernel, whose many small workgroups fill the chip sooner.
+constexpr int kKsFuseItems = 256;
+
 hipError_t keyswitch(wally_ctx* c, const KsItem* items, int n, const KsArgs& a, hipStream_t st) {
+  const bool fused = n >= kKsFuseItems;
   hipError_t e = timed(c, st, WALLY_KERNEL_DIGITS, n, [&] { return launch_ks_digits(items, n, a, c->M, st); });
   if (e == hipSuccess) e = timed(c, st, WALLY_KERNEL_EXTEND, n, [&] { return launch_ks_extend(items, n, a, c->M, st); });
-  if (e == hipSuccess) e = timed(c, st, WALLY_KERNEL_INNER, n, [&] { return launch_ks_inner(items, n, a, c->M, st); });
+  if (e == hipSuccess)
+    e = timed(c, st, fused ? WALLY_KERNEL_INNER : WALLY_KERNEL_INNER_ALL, n,
+              [&] { return launch_ks_inner(items, n, a, c->M, !fused, st); });
   if (e == hipSuccess) e = timed(c, st, WALLY_KERNEL_PINV, n, [&] { return launch_ks_pinv(n, a, c->M, st); });
   if (e == hipSuccess)
-    e = timed(c, st, WALLY_KERNEL_MODDOWN, n, [&] { return launch_ks_moddown(items, n, a, c->M, st); });
+    e = timed(c, st, fused ? WALLY_KERNEL_MODDOWN : WALLY_KERNEL_MODDOWN_U, n,
+              [&] { return launch_ks_moddown(items, n, a, c->M, fused, st); });
   return e;
 }
 

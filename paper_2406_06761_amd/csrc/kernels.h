@@ -40,7 +40,8 @@ struct KsArgs {
   uint64_t key_off;
   int g;
   uint64_t* X;  // scratch [items][L][n]
-  uint64_t* U;  // scratch [items][2][L+1][n]: key inner products; only m = L (the P part) is written
+  uint64_t* U;  // scratch [items][2][L+1][n]: key inner products (m = L: the P part; the others only
+                // when moddown reads them)
   uint64_t* Y;  // scratch [items][2][n]
   uint64_t* D;  // scratch [items][L+1][L][n]: extended digits
 };
@@ -188,9 +189,13 @@ hipError_t launch_pir_dot(const PirDotArgs& a, const DevModuli& M, hipStream_t s
 
 hipError_t launch_ks_digits(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
 hipError_t launch_ks_extend(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
-hipError_t launch_ks_inner(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
+// the inner products of every row (all_rows, for k_ks_moddown_u) or of the P rows
+hipError_t launch_ks_inner(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, bool all_rows,
+                           hipStream_t st);
 hipError_t launch_ks_pinv(int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
-hipError_t launch_ks_moddown(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st);
+// fused: forms the inner products of the q_j rows itself; else reads them from U
+hipError_t launch_ks_moddown(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, bool fused,
+                             hipStream_t st);
 // acc_i = sum_{j<g} PT[g i + j] * ct'_j for every giant index i of every item
 hipError_t launch_mac_tiles(const KsItem* items, const MacTile* tiles, int n_tiles, const KsArgs& a, int h,
                             const DevModuli& M, hipStream_t st);

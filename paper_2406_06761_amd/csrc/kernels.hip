@@ -198,19 +198,19 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_extend(const K
 }
 
 // ---------------------------------------------------------------------------
-// key switching, step 3: key inner product of the P rows,
-// u_t[P] = sum_i D[P][i] * key[i][t][P], with one 128-bit lazy sum per output
-// word (elementwise, memory bound; two words per thread through 16-byte
-// loads).  D words are below 54 q (the forward transform's lazy bound), key
-// words below q.  The inner products of the other moduli are formed in
-// moddown, which consumes them, so they never go through memory.
-// (For m < L, D[m][m] would be sigma(c1)_m, read from the input row as
-// load_galois_last does.)
-// grid (n / 512, 1, items); block 256
+// key switching, step 3: key inner product u_t[m] = sum_i D[m][i] * key[i][t][m]
+// for the rows m = m0 .. L, with one 128-bit lazy sum per output word
+// (elementwise, memory bound; two words per thread through 16-byte loads).
+// D words are below 54 q (the forward transform's lazy bound), key words
+// below q.  D[m][m] (m < L) is sigma(c1)_m, read from the input row as
+// load_galois_last does: the aligned pair of words a thread takes comes from
+// an aligned pair there.  m0 = L (the P rows alone) when k_ks_moddown forms
+// the others, m0 = 0 when k_ks_moddown_u reads them.
+// grid (n / 512, L + 1 - m0, items); block 256
 template <int L>
-__global__ __launch_bounds__(256) void k_ks_inner(const KsItem* __restrict__ items, KsArgs a, DevModuli M) {
+__global__ __launch_bounds__(256) void k_ks_inner(const KsItem* __restrict__ items, KsArgs a, int m0, DevModuli M) {
   constexpr int MM = L + 1;
-  const int m = L + blockIdx.y, b = blockIdx.z;  // the P rows only: moddown forms the others
+  const int m = m0 + blockIdx.y, b = blockIdx.z;
   const uint64_t n = 1ull << a.log_n;
   const uint64_t p = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 2;
   WALLY_GLOBAL const uint64_t* key = a.key_fold ? gmem(items[b].key_fold) + a.key_off : gmem(items[b].key);
@@ -275,67 +275,48 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_pinv(KsArgs a,
 // key switching, step 5: division by P and the rest of CtRotate:
 //   out_t[j] = (u_t[j] - NTT_j([y_t]_centred mod q_j)) * P^-1
 //              (+ sigma(c0)_j for t = 0) (+ acc_i in a Horner step)
-// with the key inner product u_t[j] = sum_i D[j][i] * key[i][t][j] formed
-// here, one pair of words at a time with 128-bit lazy sums (D[j][j] =
-// sigma(c1)_j straight from the input row), so that it is neither stored nor
-// read back.  Uncapped, the kernel takes 128 VGPRs (two workgroups per CU);
-// held lower it spills.
-// 1-D grid of xcd_blocks(items, 2 L): group b is item b; its 2 L members
-// (j, t) are consecutive on one XCD, so the two parts of limb j read D[j][*]
-// and the members of part t read Y_t from that XCD's L2; block T
+// Two kernels share the transform and the additions: k_ks_moddown forms the
+// key inner products u_t[j] itself, k_ks_moddown_u reads them from U (where
+// the inner-product kernel wrote every row); the host picks by launch size.
+
+// z = NTT_j([Y_t]_centred mod q_j), LastMap order, below (2 + 4 LOGN) q_j
 template <int LOGN, int LOGE>
-__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_moddown(
-    const KsItem* __restrict__ items, KsArgs a, int n_items, DevModuli M) {
+__device__ __forceinline__ void moddown_transform(uint64_t (&z)[1 << LOGE], uint64_t* lds, const KsArgs& a, const DevModuli& M,
+                                                  int b, int t, int j, int tid) {
   using S = NttShape<LOGN, LOGE>;
   using FM = FirstMap<LOGN, LOGE>;
-  __shared__ uint64_t lds[(S::LDS_WORDS + 1) / 2];  // 32-bit exchanges
-  const int tid = threadIdx.x;
-  const int L = a.L, MM = a.L + 1;
-  const GroupSlot gs = xcd_group(blockIdx.x, 2 * L);
-  if (gs.group >= (uint32_t)n_items) return;  // padding block (whole block, before any barrier)
-  const int b = gs.group, t = gs.member & 1, j = gs.member >> 1;
   const uint64_t q = M.q[j];
-  const uint64_t P = M.q[L];
+  const uint64_t P = M.q[a.L];
   const uint64_t halfP = (P - 1) / 2;
   const uint64_t* Y = a.Y + ((uint64_t)b * 2 + t) * S::N;
-  uint64_t z[S::E];
 #pragma unroll
   for (int e = 0; e < S::E; ++e) {
     const uint64_t y = Y[FM::idx(tid, e)];
     z[e] = y > halfP ? y + (q - P) : y;  // centred lift, then mod q_j (P < q_j)
   }
-  ntt_fwd<LOGN, LOGE, true>(z, lds, M.fwd[j], q, tid);  // LastMap order from here on, z < (2 + 4 LOGN) q
-  using LM = LastMap<LOGN, LOGE>;
-  // u - z is taken as u + zb - z with zb the transform's output bound: below
-  // 2^60, which the Shoup product by P^-1 accepts unreduced
+  ntt_fwd<LOGN, LOGE, true>(z, lds, M.fwd[j], q, tid);
+}
+
+// z = (u + zb - z) P^-1 mod q_j for one pair of words: u - z taken as
+// u + zb - z with zb the transform's output bound (below 2^60, which the
+// Shoup product by P^-1 accepts unreduced)
+template <int LOGN>
+__device__ __forceinline__ void moddown_div(uint64_t& z0, uint64_t& z1, uint64_t u0, uint64_t u1, const DevModuli& M,
+                                            int j) {
+  const uint64_t q = M.q[j];
   const uint64_t zb = (2 + 4 * LOGN) * q;
-  // u_t[j] = sum_i D[j][i] key[i][t][j], D[j][j] = sigma(c1)_j from the input row
-  WALLY_GLOBAL const uint64_t* key = a.key_fold ? gmem(items[b].key_fold) + a.key_off : gmem(items[b].key);
-  const uint64_t* Dj = a.D + ((uint64_t)b * MM + j) * L * S::N;
-  WALLY_GLOBAL const uint64_t* c1j = sel_in(items + b, a.in_sel, a.in_off) + ((uint64_t)L + j) * S::N;
-  const ModConst mc = M.mc[j];
-#pragma unroll
-  for (int c = 0; c < S::E / 2; ++c) {
-    const uint32_t p = LM::idx(tid, 2 * c);
-    u128w s0{0, 0}, s1{0, 0};
-#pragma unroll 1
-    for (int i = 0; i < L; ++i) {
-      u64x2 d;
-      if (i == j) {
-        const uint32_t sidx = galois_src<LOGN>(p, a.gal);
-        const u64x2 v = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(c1j + (sidx & ~1u)));
-        d = (sidx & 1u) ? u64x2{v.y, v.x} : v;
-      } else {
-        d = *(WALLY_GLOBAL const u64x2*)(Dj + (uint64_t)i * S::N + p);
-      }
-      const u64x2 k = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + t) * MM + j) * S::N + p));
-      mac128(s0, d.x, k.x);
-      mac128(s1, d.y, k.y);
-    }
-    const uint64_t u0 = reduce128(s0, mc.q, mc.r64, mc.r64p, mc.onep), u1 = reduce128(s1, mc.q, mc.r64, mc.r64p, mc.onep);
-    z[2 * c] = csub(shoup(u0 + zb - z[2 * c], M.pinv[j], M.pinvp[j], q), q);
-    z[2 * c + 1] = csub(shoup(u1 + zb - z[2 * c + 1], M.pinv[j], M.pinvp[j], q), q);
-  }
+  z0 = csub(shoup(u0 + zb - z0, M.pinv[j], M.pinvp[j], q), q);
+  z1 = csub(shoup(u1 + zb - z1, M.pinv[j], M.pinvp[j], q), q);
+}
+
+// + sigma(c0)_j (t = 0), + the input itself (fold step), + acc_i (Horner
+// step), then the store of out_t[j]
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void moddown_finish(uint64_t (&z)[1 << LOGE], const KsItem* __restrict__ items, const KsArgs& a,
+                                               int b, int t, int j, uint64_t q, int tid) {
+  using S = NttShape<LOGN, LOGE>;
+  using LM = LastMap<LOGN, LOGE>;
+  const int L = a.L;
   if (t == 0) {  // + sigma(c0)_j
     uint64_t v[S::E];
     load_galois_last<LOGN, LOGE>(v, sel_in(items + b, a.in_sel, a.in_off) + (uint64_t)j * S::N, a.gal, tid);
@@ -362,6 +343,84 @@ __global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_moddown(
     }
   }
   store_last<LOGN, LOGE>(sel_out(items + b, a.out_sel, a.out_off) + toff, z, tid);
+}
+
+// The key inner product u_t[j] = sum_i D[j][i] * key[i][t][j] is formed here,
+// one pair of words at a time with 128-bit lazy sums (D[j][j] = sigma(c1)_j
+// straight from the input row), so that it is neither stored nor read back.
+// Uncapped, the kernel takes 128 VGPRs (two workgroups per CU); held lower it
+// spills.
+// 1-D grid of xcd_blocks(items, 2 L): group b is item b; its 2 L members
+// (j, t) are consecutive on one XCD, so the two parts of limb j read D[j][*]
+// and the members of part t read Y_t from that XCD's L2; block T
+template <int LOGN, int LOGE>
+__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) void k_ks_moddown(
+    const KsItem* __restrict__ items, KsArgs a, int n_items, DevModuli M) {
+  using S = NttShape<LOGN, LOGE>;
+  using LM = LastMap<LOGN, LOGE>;
+  __shared__ uint64_t lds[(S::LDS_WORDS + 1) / 2];  // 32-bit exchanges
+  const int tid = threadIdx.x;
+  const int L = a.L, MM = a.L + 1;
+  const GroupSlot gs = xcd_group(blockIdx.x, 2 * L);
+  if (gs.group >= (uint32_t)n_items) return;  // padding block (whole block, before any barrier)
+  const int b = gs.group, t = gs.member & 1, j = gs.member >> 1;
+  uint64_t z[S::E];
+  moddown_transform<LOGN, LOGE>(z, lds, a, M, b, t, j, tid);
+  // u_t[j] = sum_i D[j][i] key[i][t][j], D[j][j] = sigma(c1)_j from the input row
+  WALLY_GLOBAL const uint64_t* key = a.key_fold ? gmem(items[b].key_fold) + a.key_off : gmem(items[b].key);
+  const uint64_t* Dj = a.D + ((uint64_t)b * MM + j) * L * S::N;
+  WALLY_GLOBAL const uint64_t* c1j = sel_in(items + b, a.in_sel, a.in_off) + ((uint64_t)L + j) * S::N;
+  const ModConst mc = M.mc[j];
+#pragma unroll
+  for (int c = 0; c < S::E / 2; ++c) {
+    const uint32_t p = LM::idx(tid, 2 * c);
+    u128w s0{0, 0}, s1{0, 0};
+#pragma unroll 1
+    for (int i = 0; i < L; ++i) {
+      u64x2 d;
+      if (i == j) {
+        const uint32_t sidx = galois_src<LOGN>(p, a.gal);
+        const u64x2 v = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(c1j + (sidx & ~1u)));
+        d = (sidx & 1u) ? u64x2{v.y, v.x} : v;
+      } else {
+        d = *(WALLY_GLOBAL const u64x2*)(Dj + (uint64_t)i * S::N + p);
+      }
+      const u64x2 k = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(key + (((uint64_t)i * 2 + t) * MM + j) * S::N + p));
+      mac128(s0, d.x, k.x);
+      mac128(s1, d.y, k.y);
+    }
+    moddown_div<LOGN>(z[2 * c], z[2 * c + 1], reduce128(s0, mc.q, mc.r64, mc.r64p, mc.onep),
+                      reduce128(s1, mc.q, mc.r64, mc.r64p, mc.onep), M, j);
+  }
+  moddown_finish<LOGN, LOGE>(z, items, a, b, t, j, M.q[j], tid);
+}
+
+// The same with u_t[j] read from U (the inner-product kernel wrote every
+// row): for launches of few items, where the inner products spread over many
+// small workgroups and this kernel, at 68 VGPRs, holds three workgroups per
+// CU.
+// 1-D grid of xcd_blocks(items * 2, L): group (b, t) reads Y_t of item b, its
+// L members are the target limbs j; block T
+template <int LOGN, int LOGE>
+__global__ __launch_bounds__((NttShape<LOGN, LOGE>::T)) __attribute__((amdgpu_waves_per_eu(6))) void k_ks_moddown_u(
+    const KsItem* __restrict__ items, KsArgs a, int n_items, DevModuli M) {
+  using S = NttShape<LOGN, LOGE>;
+  using LM = LastMap<LOGN, LOGE>;
+  __shared__ uint64_t lds[(S::LDS_WORDS + 1) / 2];  // 32-bit exchanges
+  const int tid = threadIdx.x;
+  const int L = a.L, MM = a.L + 1;
+  const GroupSlot gs = xcd_group(blockIdx.x, L);
+  if (gs.group >= (uint32_t)(n_items * 2)) return;  // padding block (whole block, before any barrier)
+  const int b = gs.group >> 1, t = gs.group & 1, j = gs.member;
+  uint64_t z[S::E];
+  moddown_transform<LOGN, LOGE>(z, lds, a, M, b, t, j, tid);
+  const uint64_t* U = a.U + (((uint64_t)b * 2 + t) * MM + j) * S::N;
+#pragma unroll
+  for (int c = 0; c < S::E / 2; ++c) {
+    const u64x2 u = __builtin_nontemporal_load((WALLY_GLOBAL const u64x2*)(U + LM::idx(tid, 2 * c)));
+    moddown_div<LOGN>(z[2 * c], z[2 * c + 1], u.x, u.y, M, j);
+  }
+  moddown_finish<LOGN, LOGE>(z, items, a, b, t, j, M.q[j], tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -1158,18 +1217,20 @@ hipError_t launch_ks_extend(const KsItem* items, int n_items, const KsArgs& a, c
   return hipGetLastError();
 }
 
-hipError_t launch_ks_inner(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
+hipError_t launch_ks_inner(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, bool all_rows,
+                           hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  const dim3 grid((1u << a.log_n) / 512, 1, n_items);
+  const int m0 = all_rows ? 0 : a.L;
+  const dim3 grid((1u << a.log_n) / 512, a.L + 1 - m0, n_items);
   switch (a.L) {
-    case 1: hipLaunchKernelGGL(k_ks_inner<1>, grid, dim3(256), 0, st, items, a, M); break;
-    case 2: hipLaunchKernelGGL(k_ks_inner<2>, grid, dim3(256), 0, st, items, a, M); break;
-    case 3: hipLaunchKernelGGL(k_ks_inner<3>, grid, dim3(256), 0, st, items, a, M); break;
-    case 4: hipLaunchKernelGGL(k_ks_inner<4>, grid, dim3(256), 0, st, items, a, M); break;
-    case 5: hipLaunchKernelGGL(k_ks_inner<5>, grid, dim3(256), 0, st, items, a, M); break;
-    case 6: hipLaunchKernelGGL(k_ks_inner<6>, grid, dim3(256), 0, st, items, a, M); break;
-    case 7: hipLaunchKernelGGL(k_ks_inner<7>, grid, dim3(256), 0, st, items, a, M); break;
-    case 8: hipLaunchKernelGGL(k_ks_inner<8>, grid, dim3(256), 0, st, items, a, M); break;
+    case 1: hipLaunchKernelGGL(k_ks_inner<1>, grid, dim3(256), 0, st, items, a, m0, M); break;
+    case 2: hipLaunchKernelGGL(k_ks_inner<2>, grid, dim3(256), 0, st, items, a, m0, M); break;
+    case 3: hipLaunchKernelGGL(k_ks_inner<3>, grid, dim3(256), 0, st, items, a, m0, M); break;
+    case 4: hipLaunchKernelGGL(k_ks_inner<4>, grid, dim3(256), 0, st, items, a, m0, M); break;
+    case 5: hipLaunchKernelGGL(k_ks_inner<5>, grid, dim3(256), 0, st, items, a, m0, M); break;
+    case 6: hipLaunchKernelGGL(k_ks_inner<6>, grid, dim3(256), 0, st, items, a, m0, M); break;
+    case 7: hipLaunchKernelGGL(k_ks_inner<7>, grid, dim3(256), 0, st, items, a, m0, M); break;
+    case 8: hipLaunchKernelGGL(k_ks_inner<8>, grid, dim3(256), 0, st, items, a, m0, M); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1181,9 +1242,14 @@ hipError_t launch_ks_pinv(int n_items, const KsArgs& a, const DevModuli& M, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_ks_moddown(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, hipStream_t st) {
+hipError_t launch_ks_moddown(const KsItem* items, int n_items, const KsArgs& a, const DevModuli& M, bool fused,
+                             hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  WALLY_DISPATCH_KS(k_ks_moddown, dim3(xcd_blocks(n_items, 2 * a.L)), items, a, n_items, M);
+  if (fused) {
+    WALLY_DISPATCH_KS(k_ks_moddown, dim3(xcd_blocks(n_items, 2 * a.L)), items, a, n_items, M);
+  } else {
+    WALLY_DISPATCH_KS(k_ks_moddown_u, dim3(xcd_blocks(n_items * 2, a.L)), items, a, n_items, M);
+  }
   return hipGetLastError();
 }
 

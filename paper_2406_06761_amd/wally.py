@@ -73,7 +73,8 @@ SYMBOLS = [
     "wally_diag_kernel_stats", "wally_diag_bfly_rate",
 ]
 
-KERNELS = ["ks_digits", "ks_extend", "ks_inner", "ks_pinv", "ks_moddown", "mac", "copy_ct"]
+KERNELS = ["ks_digits", "ks_extend", "ks_inner", "ks_pinv", "ks_moddown", "mac", "copy_ct", "ks_inner_all",
+           "ks_moddown_u"]
 
 
 class TuneEntry(ctypes.Structure):

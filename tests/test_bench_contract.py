@@ -33,6 +33,14 @@ def test_work_per_item_and_inner_bytes():
     assert ks == 30 * bf + (L + 2) * n + 2 * L * (L + 1) * n + 2 * L * n == 2_039_808
     # the P rows: key 512 KiB + extended digits 256 KiB in, 128 KiB out
     assert bench.inner_bytes(n, L) == 0.875 * 2**20
+    # launches of few items: every row's inner products in one kernel (key
+    # 2.5 MiB + extended digits 1.25 MiB in, 640 KiB out), moddown reads them
+    assert bench.inner_bytes(n, L, "ks_inner_all") == 4.375 * 2**20
+    assert bench.per_item_work("ks_inner_all", n, L, 16, 16) == 2 * L * (L + 1) * n
+    assert bench.per_item_work("ks_moddown_u", n, L, 16, 16) == 2 * L * bf + 2 * L * n
+    ks_u = sum(bench.per_item_work(k, n, L, 16, 16) for k in ("ks_digits", "ks_extend", "ks_inner_all", "ks_pinv",
+                                                                "ks_moddown_u"))
+    assert ks_u == ks
 
 
 def test_instruction_weighted_work():
@@ -64,6 +72,8 @@ def test_roofline_pricing_of_each_kernel():
     n, L, g, h = 8192, 4, 16, 16
     assert bench.roofline_kind("ks_extend", n, L, g, h) == "bfly"
     assert bench.roofline_kind("ks_inner", n, L, g, h) == "hbm"
+    assert bench.roofline_kind("ks_inner_all", n, L, g, h) == "hbm"
+    assert bench.roofline_kind("ks_moddown_u", n, L, g, h) == "instr"
     for k in ("ks_digits", "ks_pinv", "ks_moddown", "mac"):
         assert bench.roofline_kind(k, n, L, g, h) == "instr", k
 

@@ -79,6 +79,44 @@ def test_rotate_parity(pair):
             assert (got[k] == o.rotate(ct[k], keys[k], gal)).all(), (which, k)
 
 
+@pytest.mark.parametrize("name", ["tiny", "paper"])
+def test_rotate_both_moddown_forms(name):
+    """Launches of at least 256 items form the inner products of the q_j rows
+    inside the division by P; smaller launches form every row's inner products
+    in the inner-product kernel and the division reads them back.  The same
+    items through both forms (300 items in one launch, then the first 255)
+    give the same words, and sampled items equal the oracle's rotation."""
+    from paper_2406_06761_amd.wally import to_host
+
+    c = _ctx(name, max_batch=512)
+    try:
+        o = Oracle(preset(name))
+        info = c.info
+        print(f"both moddown forms: {name}", flush=True)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(7)
+        qs = [info.q[j] for j in range(info.L)]
+        cnt, few = 300, 255
+        cts = synth.uniform_residues(gen, (cnt, 2), qs, info.n, device="cuda")
+        kbs = synth.uniform_residues(gen, (cnt, info.L, 2), qs + [info.P], info.n, device="cuda")
+        big = torch.empty_like(cts)
+        small = torch.empty_like(cts[:few])
+        c.kernel_timing(True)
+        c.kernel_stats()
+        c.diag_rotate(cts, kbs, big, 1)
+        c.diag_rotate(cts[:few], kbs[:few], small, 1)
+        st = c.kernel_stats()
+        c.kernel_timing(False)
+        assert st["ks_moddown"][:2] == (1, cnt) and st["ks_inner"][:2] == (1, cnt)
+        assert st["ks_moddown_u"][:2] == (1, few) and st["ks_inner_all"][:2] == (1, few)
+        got = to_host(big)
+        assert (got[:few] == to_host(small)).all()
+        for k in (0, few - 1, cnt - 1):
+            assert (got[k] == o.rotate(to_host(cts[k]), to_host(kbs[k]), o.p.gal_giant)).all(), k
+    finally:
+        c.close()
+
+
 def test_rotate_real_key_decrypts(pair):
     from paper_2406_06761_amd.wally import to_device, to_host
 
