@@ -74,12 +74,30 @@ def per_item_work(kernel, n, L, g, h):
     return sum(per_item_units(kernel, n, L, g, h).values())
 
 
+def kernel_bytes(kernel, n, L):
+    """Compulsory HBM bytes per item of a key-switch kernel (every row it needs
+    read once, every row it produces written once), or None."""
+    row = 8 * n
+    return {
+        "ks_digits": row * 2 * L,  # sigma(c1) in, the digits X out
+        "ks_extend": row * (L + L * L),  # X in, the extended digits out
+        "ks_inner": row * (3 * L + 2),  # the P rows: key 2L and extended digits L in, 2 out
+        "ks_inner_all": row * (L + 1) * (3 * L + 2),  # every row
+        "ks_pinv": row * 4,  # the P rows of U in, Y out
+        # key 2L^2, extended digits L^2 - L, sigma(c1) L, Y 2, sigma(c0) L in; 2L out
+        "ks_moddown": row * (3 * L * L + 3 * L + 2),
+        "ks_moddown_u": row * (5 * L + 2),  # U 2L, Y 2, sigma(c0) L in; 2L out
+    }.get(kernel)
+
+
 def roofline_kind(kernel, n, L, g, h):
-    """How a kernel's rate is priced: "hbm" (the key inner product streams its
-    key), "bfly" (forward butterflies only: butterflies/s against 39.3e12 / 17)
-    or "instr" (anything else, mixed units or multiply-accumulates: VALU
+    """The roof a kernel is priced against, by the roofline model: "hbm" when
+    its compulsory bytes take longer at 8 TB/s than its VALU instructions at
+    39.3e12/s, else "bfly" (forward butterflies only: butterflies/s against
+    39.3e12 / 17) or "instr" (mixed units or multiply-accumulates: VALU
     lane-instructions at each unit's compiled cost against 39.3e12)."""
-    if kernel in ("ks_inner", "ks_inner_all"):
+    b = kernel_bytes(kernel, n, L)
+    if b is not None and b / HBM_PEAK > per_item_instr(kernel, n, L, g, h) / PEAK_VALU_LANE_OPS:
         return "hbm"
     return "bfly" if set(per_item_units(kernel, n, L, g, h)) == {"bfly_fwd"} else "instr"
 
@@ -104,14 +122,6 @@ def host_cpu():
     except AttributeError:
         visible = os.cpu_count() or 1
     return model, visible
-
-
-def inner_bytes(n, L, kernel="ks_inner"):
-    """Compulsory HBM bytes per item of the key inner product: of the P rows
-    (ks_inner: their key L x 2 x n, their extended digits L x n, the output
-    2 x n) or of all L + 1 rows (ks_inner_all)."""
-    rows = L + 1 if kernel == "ks_inner_all" else 1
-    return 8 * n * rows * (2 * L + L + 2)
 
 
 TRAFFIC_FILE = Path(__file__).resolve().parent / "profiles" / "hbm_traffic_paper.json"
@@ -762,11 +772,14 @@ def main():
         peak = PEAK_VALU_LANE_OPS / INSTR_PER_MODMUL
         step_instr = sum(kstats[k][1] * per_item_instr(k, n, L, info.g, info.h) for k in kstats) / args.steps
         kind = roofline_kind(dom, n, L, info.g, info.h)
-        if kind == "hbm":  # streams the key: HBM bound
-            achieved = inner_bytes(n, L, dom) * items_per_launch / (avg_ms * 1e-3)
+        dom_bytes = kernel_bytes(dom, n, L)
+        dom_alu = per_item_instr(dom, n, L, info.g, info.h) * items_per_launch / (avg_ms * 1e-3) / PEAK_VALU_LANE_OPS
+        if kind == "hbm":  # its compulsory bytes outweigh its instructions
+            achieved = dom_bytes * items_per_launch / (avg_ms * 1e-3)
             roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                         "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
-                        "bytes_per_item": inner_bytes(n, L, dom)}
+                        "bytes_per_item": dom_bytes, "alu_frac": dom_alu,
+                        "work_per_item": per_item_units(dom, n, L, info.g, info.h)}
         elif kind == "instr":
             ins = per_item_instr(dom, n, L, info.g, info.h)
             achieved = ins * items_per_launch / (avg_ms * 1e-3)
@@ -781,6 +794,8 @@ def main():
                         "unit": "Gbutterfly/s", "frac": achieved / peak, "traffic": None, "work_per_item": work[dom],
                         "peak_derivation": "256 CU x 64 lanes x 2.4 GHz / 17 VALU instructions per compiled "
                                            "forward butterfly"}
+        if kind != "hbm" and dom_bytes is not None:  # the same launches against HBM
+            roofline["hbm_frac"] = dom_bytes * items_per_launch / (avg_ms * 1e-3) / HBM_PEAK
         roofline.update({"avg_launch_ms": avg_ms, "items_per_launch": items_per_launch,
                          "path_frac": step_instr / (ms_per_step * 1e-3) / PEAK_VALU_LANE_OPS,
                          "path_frac_method": "VALU lane-instructions of the path's algorithmic work (butterflies, "
@@ -846,20 +861,23 @@ def main():
             if not nl:
                 continue
             e = {"ms_per_launch": ms / nl, "items_per_launch": it / nl}
-            if k in ("ks_inner", "ks_inner_all"):  # streams the key: HBM bound
-                e.update(bound="hbm", achieved_gbs=inner_bytes(n, L, k) * it / (ms * 1e-3) / 1e9,
-                         frac=inner_bytes(n, L, k) * it / (ms * 1e-3) / HBM_PEAK)
+            kb = kernel_bytes(k, n, L)
+            alu = per_item_instr(k, n, L, info.g, info.h) * it / (ms * 1e-3) / PEAK_VALU_LANE_OPS
+            hbm = kb * it / (ms * 1e-3) / HBM_PEAK if kb is not None else None
+            if roofline_kind(k, n, L, info.g, info.h) == "hbm":
+                e.update(bound="hbm", achieved_gbs=kb * it / (ms * 1e-3) / 1e9, frac=hbm, alu_frac=alu)
             else:
                 w_ = per_item_work(k, n, L, info.g, info.h)
-                ins = per_item_instr(k, n, L, info.g, info.h)
-                e.update(bound="alu", achieved_gunits=w_ * it / (ms * 1e-3) / 1e9,
-                         frac=ins * it / (ms * 1e-3) / PEAK_VALU_LANE_OPS)
+                e.update(bound="alu", achieved_gunits=w_ * it / (ms * 1e-3) / 1e9, frac=alu)
+                if hbm is not None:
+                    e["hbm_frac"] = hbm
             tb = stored_traffic(k, preset_name)
-            if tb is not None:  # the same launches against HBM, at the counter-calibrated bytes
-                e["hbm_frac"] = tb * it / (ms * 1e-3) / HBM_PEAK
+            if tb is not None:  # the same launches at their counter-calibrated bytes
+                e["measured_hbm_frac"] = tb * it / (ms * 1e-3) / HBM_PEAK
             isolated[k] = e
             log(f"  isolated {k:11s} {e['ms_per_launch']:.3f} ms per launch of {e['items_per_launch']:.0f} items, "
-                f"frac {e['frac']:.3f}" + (f", HBM {e['hbm_frac']:.3f}" if "hbm_frac" in e else ""))
+                f"{e['bound']} frac {e['frac']:.3f}" + (f", alu {e['alu_frac']:.3f}" if "alu_frac" in e else "")
+                + (f", hbm {e['hbm_frac']:.3f}" if "hbm_frac" in e else ""))
         # the measured peak of the transforms' arithmetic: the register-resident
         # butterfly loop (wally_diag_bfly_rate) forward and inverse
         bout = torch.empty(4096 * 256 * 16, dtype=torch.int64, device="cuda")

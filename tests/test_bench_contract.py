@@ -15,7 +15,7 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_work_per_item_and_inner_bytes():
+def test_work_and_bytes_per_item():
     sys.path.insert(0, str(ROOT))
     import bench
 
@@ -31,11 +31,26 @@ def test_work_per_item_and_inner_bytes():
     ks = sum(bench.per_item_work(k, n, L, 16, 16) for k in ("ks_digits", "ks_extend", "ks_inner", "ks_pinv",
                                                               "ks_moddown"))
     assert ks == 30 * bf + (L + 2) * n + 2 * L * (L + 1) * n + 2 * L * n == 2_039_808
-    # the P rows: key 512 KiB + extended digits 256 KiB in, 128 KiB out
-    assert bench.inner_bytes(n, L) == 0.875 * 2**20
+    # compulsory bytes: the P rows' inner products (key 512 KiB + extended
+    # digits 256 KiB in, 128 KiB out); moddown with the q_j rows' inner
+    # products (key 2 MiB, extended digits 768 KiB, sigma(c1) 256 KiB, Y
+    # 128 KiB, sigma(c0) 256 KiB in, 512 KiB out)
+    mib = 2**20
+    assert bench.kernel_bytes("ks_inner", n, L) == 0.875 * mib
+    assert bench.kernel_bytes("ks_moddown", n, L) == 3.875 * mib
+    assert bench.kernel_bytes("ks_digits", n, L) == 0.5 * mib
+    assert bench.kernel_bytes("ks_extend", n, L) == 1.25 * mib
+    assert bench.kernel_bytes("ks_pinv", n, L) == 0.25 * mib
+    assert bench.kernel_bytes("mac", n, L) is None
     # launches of few items: every row's inner products in one kernel (key
     # 2.5 MiB + extended digits 1.25 MiB in, 640 KiB out), moddown reads them
-    assert bench.inner_bytes(n, L, "ks_inner_all") == 4.375 * 2**20
+    assert bench.kernel_bytes("ks_inner_all", n, L) == 4.375 * mib
+    assert bench.kernel_bytes("ks_moddown_u", n, L) == 1.375 * mib
+    # both forms move the same rows apart from the q_j rows' inner products,
+    # which the fused one neither writes nor reads back (2 x 2L rows)
+    fused = sum(bench.kernel_bytes(k, n, L) for k in ("ks_inner", "ks_moddown"))
+    split = sum(bench.kernel_bytes(k, n, L) for k in ("ks_inner_all", "ks_moddown_u"))
+    assert split - fused == 2 * 2 * L * n * 8
     assert bench.per_item_work("ks_inner_all", n, L, 16, 16) == 2 * L * (L + 1) * n
     assert bench.per_item_work("ks_moddown_u", n, L, 16, 16) == 2 * L * bf + 2 * L * n
     ks_u = sum(bench.per_item_work(k, n, L, 16, 16) for k in ("ks_digits", "ks_extend", "ks_inner_all", "ks_pinv",
@@ -63,17 +78,20 @@ def test_instruction_weighted_work():
 
 
 def test_roofline_pricing_of_each_kernel():
-    """Only a kernel of forward butterflies alone is priced in butterflies; the
-    giant-step sums (multiply-accumulates) and the mixed kernels in VALU
-    lane-instructions; the key inner product against HBM."""
+    """Each kernel is priced against the roof of the roofline model: HBM when
+    its compulsory bytes at 8 TB/s take longer than its VALU instructions at
+    39.3e12/s (the inner products; moddown once it forms the q_j rows'
+    inner products itself), else the VALU peak: in butterflies for a kernel of
+    forward butterflies alone, in lane-instructions for the others."""
     sys.path.insert(0, str(ROOT))
     import bench
 
     n, L, g, h = 8192, 4, 16, 16
     assert bench.roofline_kind("ks_extend", n, L, g, h) == "bfly"
-    assert bench.roofline_kind("ks_inner", n, L, g, h) == "hbm"
-    assert bench.roofline_kind("ks_inner_all", n, L, g, h) == "hbm"
-    assert bench.roofline_kind("ks_moddown_u", n, L, g, h) == "instr"
-    for k in ("ks_digits", "ks_pinv", "ks_moddown", "mac"):
+    for k in ("ks_inner", "ks_inner_all", "ks_moddown"):
+        assert bench.roofline_kind(k, n, L, g, h) == "hbm", k
+    for k in ("ks_digits", "ks_pinv", "ks_moddown_u", "mac"):
         assert bench.roofline_kind(k, n, L, g, h) == "instr", k
-
+    # moddown: 3.875 MiB at 8 TB/s (0.51 us) against 14.0 M lane-instructions at 39.3e12/s (0.36 us)
+    assert bench.kernel_bytes("ks_moddown", n, L) / bench.HBM_PEAK > 1.4 * (
+        bench.per_item_instr("ks_moddown", n, L, g, h) / bench.PEAK_VALU_LANE_OPS)
