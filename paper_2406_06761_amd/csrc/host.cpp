@@ -374,10 +374,15 @@ hipError_t timed(wally_ctx* c, hipStream_t st, int kernel, uint64_t items, F fn)
 // rows inside the division by P (less HBM traffic; each workgroup then does
 // more work, at two workgroups per CU); smaller launches keep them in the
 // inner-product kernel, whose many small workgroups fill the chip sooner.
+// The saving shows where another stream's kernels compete for HBM (the
+// scoring waves); alone on one stream the two forms take the same time for
+// 512 items and the stored form is faster for the PIR path's launches, so
+// callers there pass may_fuse = false.
 constexpr int kKsFuseItems = 256;
 
-hipError_t keyswitch(wally_ctx* c, const KsItem* items, int n, const KsArgs& a, hipStream_t st) {
-  const bool fused = n >= kKsFuseItems;
+hipError_t keyswitch(wally_ctx* c, const KsItem* items, int n, const KsArgs& a, hipStream_t st,
+                     bool may_fuse = true) {
+  const bool fused = may_fuse && n >= kKsFuseItems;
   hipError_t e = timed(c, st, WALLY_KERNEL_DIGITS, n, [&] { return launch_ks_digits(items, n, a, c->M, st); });
   if (e == hipSuccess) e = timed(c, st, WALLY_KERNEL_EXTEND, n, [&] { return launch_ks_extend(items, n, a, c->M, st); });
   if (e == hipSuccess)
@@ -1712,7 +1717,8 @@ int pir_wave(wally_ctx* c, const PirMode& md, const PirQ* q, uint32_t w, hipStre
       // x, then alternately y0, y1
       const KsArgs ka_args = ks_args(c->n / (1u << ka) + 1, r == 0 ? 0 : (r % 2 == 1 ? 1 : 2), r % 2 == 0 ? 1 : 2);
       for (int i0 = 0; i0 < n_ks; i0 += kPirKsItems)
-        HIP_OK(c, keyswitch(c, c->pir_items_dev + lev_base[a] + i0, std::min(kPirKsItems, n_ks - i0), ka_args, st));
+        HIP_OK(c, keyswitch(c, c->pir_items_dev + lev_base[a] + i0, std::min(kPirKsItems, n_ks - i0), ka_args, st,
+                            false));
       last_out = ka_args.out_sel;
     }
     PirSplitArgs sa{};
@@ -1752,7 +1758,7 @@ int pir_wave(wally_ctx* c, const PirMode& md, const PirQ* q, uint32_t w, hipStre
     fa.giant = 0;
     const int n_cols = (int)(sig_base - col_base);
     for (int i0 = 0; i0 < n_cols; i0 += kPirKsItems)
-      HIP_OK(c, keyswitch(c, c->pir_items_dev + col_base + i0, std::min(kPirKsItems, n_cols - i0), fa, st));
+      HIP_OK(c, keyswitch(c, c->pir_items_dev + col_base + i0, std::min(kPirKsItems, n_cols - i0), fa, st, false));
   }
   if (!md.two) return WALLY_OK;
   // second dimension, columns in passes of pir2_kc
@@ -1787,7 +1793,7 @@ int pir_wave(wally_ctx* c, const PirMode& md, const PirQ* q, uint32_t w, hipStre
   HIP_OK(c, launch_rows_ntt(c->pir2_c3, (int)(w * 4 * c->L), c->log_n, c->pir2_K, 0, c->L, 0, st));
   KsArgs rl = ks_args(1, 0, 2);
   rl.giant = 0;  // + acc = (0, c1)
-  HIP_OK(c, keyswitch(c, c->pir_items_dev + relin_base, (int)w, rl, st));
+  HIP_OK(c, keyswitch(c, c->pir_items_dev + relin_base, (int)w, rl, st, false));
   return WALLY_OK;
 }
 
