@@ -9,12 +9,14 @@
 // paper §7.1 with one digit per ciphertext limb and one special prime P:
 //   ks_digits : x_i = INTT_{q_i}(sigma(c1)_i)                         (L per item)
 //   ks_extend : D[m][i] = NTT_m(x_i mod m), m in {q_0..q_{L-1}, P} \ {q_i}   (L^2 per item)
-//   ks_inner  : u_t[P] = sum_i D[P][i] * key[i][t][P]               (elementwise)
+//   ks_inner  : u_t[m] = sum_i D[m][i] * key[i][t][m]               (elementwise)
+//               D[m][m] = sigma(c1)_m read from the input row
 //   ks_pinv   : y_t = INTT_P(u_t[P])                                (2 per item)
 //   ks_moddown: out_t[j] = (u_t[j] - NTT_j([y_t]_centred mod q_j)) * P^-1
 //               (+ sigma(c0)_j for t = 0) (+ acc_i)                (2L per item)
-//               with u_t[j] = sum_i D[j][i] * key[i][t][j] formed there,
-//               D[j][j] = sigma(c1)_j read from the input row
+// In the fused form ks_inner covers m = P alone and k_ks_moddown forms the
+// u_t[j] of the q_j rows itself; in the stored form ks_inner covers every m
+// and k_ks_moddown_u reads them (the host picks per launch).
 // Each transform kernel does one NTT per workgroup, with coalesced row I/O
 // (lane-consecutive words, or lane-consecutive word pairs where a row is in
 // the last pass's order), so the compute-bound transforms stay light on
