@@ -95,3 +95,27 @@ def test_roofline_pricing_of_each_kernel():
     # moddown: 3.875 MiB at 8 TB/s (0.51 us) against 14.0 M lane-instructions at 39.3e12/s (0.36 us)
     assert bench.kernel_bytes("ks_moddown", n, L) / bench.HBM_PEAK > 1.4 * (
         bench.per_item_instr("ks_moddown", n, L, g, h) / bench.PEAK_VALU_LANE_OPS)
+
+
+def test_committed_counters_cover_the_compulsory_bytes():
+    """The counter-calibrated HBM bytes per item committed for the key-switch
+    kernels of large launches are at least their compulsory bytes and at
+    most 1.2 times them (the digit kernel's small spill and moddown's second
+    reads of the extended digits included).  Skipped when the kernel sources
+    have changed since the counters were taken (the bench then reports no
+    traffic either)."""
+    import json
+
+    import pytest
+
+    sys.path.insert(0, str(ROOT))
+    import bench
+
+    rec = json.loads(bench.TRAFFIC_FILE.read_text())
+    assert rec["params"] == "paper"
+    if rec["kernel_sources_sha256"] != bench.kernel_source_hash():
+        pytest.skip("the stored counters belong to other kernel sources")
+    n, L = 8192, 4
+    for k in ("ks_digits", "ks_extend", "ks_inner", "ks_pinv", "ks_moddown"):
+        measured, compulsory = rec["bytes_per_item"][k], bench.kernel_bytes(k, n, L)
+        assert compulsory <= measured <= 1.2 * compulsory, (k, measured, compulsory)
