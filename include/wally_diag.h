@@ -42,7 +42,8 @@ int wally_diag_rotate(wally_ctx* ctx, const uint64_t* in, const uint64_t* keys, 
                                    the inner products of the q_j rows       */
 #define WALLY_KERNEL_MAC 5      /* giant-step sums (plaintext products)      */
 #define WALLY_KERNEL_COPY 6     /* query copy into the baby-step buffer      */
-/* launches of fewer than 256 items: the inner products of every row in one
+/* the stored form of the key switch (launches of fewer than 256 items, and
+ * every launch of the PIR path): the inner products of every row in one
  * kernel, and the division by P reading them */
 #define WALLY_KERNEL_INNER_ALL 7   /* key switch: key inner product, all rows */
 #define WALLY_KERNEL_MODDOWN_U 8   /* key switch: division by P, stored u     */
